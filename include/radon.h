@@ -1,0 +1,144 @@
+/*
+ * radon.h -- C ABI of libradon.so, the MI355X (gfx950) discretised Radon transform.
+ *
+ * The operator (TorchRadon, arXiv 2009.14788; geometry of Sec. 3.1.1 and 3.1.2,
+ * batch processing of Sec. 4.1, 16-bit storage with 32-bit arithmetic of Sec. 3.3,
+ * backprojection used as the adjoint of the projection in Sec. 4.3):
+ *
+ *   image x[r][c], 0 <= r,c < N, pixel centre (c-(N-1)/2, r-(N-1)/2), pixel size 1;
+ *   f = bilinear interpolant of x with zeros outside the image;
+ *   angle t: detector axis u = (cos t, sin t), ray axis v = (-sin t, cos t);
+ *   bin d: s_d = (d-(D-1)/2) * det_spacing;
+ *   parallel beam: ray through s_d*u along v;
+ *   fan beam: point source at -S*v, flat detector through E*v along u, the ray
+ *     joins the source and the bin centre E*v + s_d*u;
+ *   each ray is sampled at P_k = F + k*step*w (F = the ray's point closest to the
+ *     rotation centre, w = its unit direction, k any integer);
+ *   forward         y[a][d] = scale * step * sum_k f(P_k)            (y = scale*R x)
+ *   backprojection  x       = scale * R^T y (the exact transpose, no other factor).
+ *
+ * Layouts.  Images: x[B][N][N] contiguous, row-major.  Sinograms: y[B][A][D]
+ * contiguous.  Element type per call: RADON_F32, RADON_F16 or RADON_BF16; 16-bit
+ * values are widened exactly to FP32, all arithmetic and accumulation is FP32, and
+ * each output is rounded once (round-to-nearest-even) on store; FP16 overflow
+ * stores +-inf.
+ *
+ * Ownership.  The caller owns every data buffer (device memory); the library never
+ * frees, keeps or reallocates them.  Calls are asynchronous on `stream` (a
+ * hipStream_t passed as void*, NULL = the null stream); buffers must stay alive
+ * until the stream's work has completed.  The library owns only its per-geometry
+ * plans (angle/ray tables, launch shapes), created on first use or by
+ * radon_prepare() and kept until radon_release_plans().
+ *
+ * Errors.  Every entry point returns RADON_OK (0) or a negative status; no C++
+ * exception crosses the ABI.  A launch error is reported from the call; a fault
+ * during execution surfaces at the caller's next synchronisation.  batch == 0 is a
+ * no-op returning RADON_OK.  Device pointers must be 16-byte aligned
+ * (RADON_ERR_ALIGN).  Plans are built outside stream capture: a call on a capturing
+ * stream whose plan does not exist yet returns RADON_ERR_NOT_PREPARED.
+ */
+#ifndef RADON_H
+#define RADON_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    RADON_OK = 0,
+    RADON_ERR_INVALID_ARG = -1,   /* bad geometry, size, dtype or null pointer */
+    RADON_ERR_ALIGN = -2,         /* a device pointer is not 16-byte aligned */
+    RADON_ERR_UNSUPPORTED = -3,   /* valid request the library does not implement */
+    RADON_ERR_HIP = -4,           /* a HIP runtime call or kernel launch failed */
+    RADON_ERR_ALLOC = -5,         /* device or host allocation failed */
+    RADON_ERR_NO_DEVICE = -6,     /* no usable GPU */
+    RADON_ERR_NOT_PREPARED = -7   /* plan missing while the stream is capturing */
+};
+
+enum { RADON_PARALLEL = 0, RADON_FANBEAM = 1 };
+enum { RADON_F32 = 0, RADON_F16 = 1, RADON_BF16 = 2 };
+
+/* Acquisition geometry (Sec. 3.1.1 parallel beam: image size, angles, detector count
+ * and spacing; Sec. 3.1.2 fan beam: plus source and detector distances). */
+typedef struct radon_geometry {
+    int32_t beam;              /* RADON_PARALLEL or RADON_FANBEAM */
+    int32_t image_size;        /* N >= 1 */
+    int32_t n_angles;          /* A >= 1 */
+    int32_t det_count;         /* D >= 1 */
+    const double *angles;      /* host array [A] of angles in radians; read during the call */
+    double det_spacing;        /* > 0 */
+    double source_distance;    /* fan only: S > (N/2+1)*sqrt(2), source outside the image */
+    double det_distance;       /* fan only: E >= 0 */
+    double step;               /* sample spacing along each ray, > 0 (usual value 1) */
+} radon_geometry_t;
+
+/* Host-only check of a geometry (no device needed).  RADON_OK or
+ * RADON_ERR_INVALID_ARG; never touches the GPU. */
+int radon_validate(const radon_geometry_t *geometry);
+
+/* Build (or find) the plan of a geometry on the current device for `dtype` and a
+ * batch size: angle and ray tables, and launch shapes chosen by timing candidates
+ * when autotuning is on (RADON_AUTOTUNE=1, the default; results cached in memory and
+ * in the JSON file named by RADON_TUNE_CACHE if set).  Synchronises the device.
+ * Call before capturing a stream that will use the geometry. */
+int radon_prepare(const radon_geometry_t *geometry, int32_t dtype, int32_t batch);
+
+/* Forward projection (Sec. 3.1, Sec. 4.1): y[b] = scale * R x[b] for b < batch.
+ * x: device [batch][N][N], y: device [batch][A][D], both of `dtype`. */
+int radon_forward(const radon_geometry_t *geometry, const void *x, void *y, int32_t batch,
+                  int32_t dtype, float scale, void *stream);
+
+/* Backprojection, the exact transpose of radon_forward (used as the adjoint in
+ * Sec. 4.3): x[b] = scale * R^T y[b].  y: device [batch][A][D], x: device
+ * [batch][N][N], both of `dtype`.  A gather over the rays through each pixel: no
+ * atomics, deterministic. */
+int radon_backproject(const radon_geometry_t *geometry, const void *y, void *x,
+                      int32_t batch, int32_t dtype, float scale, void *stream);
+
+/* One job of an uneven batch: `batch` images of one geometry. */
+typedef struct radon_job {
+    const radon_geometry_t *geometry;
+    const void *input;     /* device: images (forward) or sinograms (backprojection) */
+    void *output;          /* device: sinograms (forward) or images (backprojection) */
+    int32_t batch;
+    float scale;
+} radon_job_t;
+
+/* Uneven batch (Sec. 4.1 batch processing, for jobs of different image sizes and
+ * angle sets): all jobs in ONE persistent kernel launch that pulls work items from a
+ * device queue, longest first.  Same results as calling radon_forward /
+ * radon_backproject per job.  The job table is built and uploaded on the first call
+ * for a given job list (by content); later calls with the same list only launch, so
+ * the call can be captured into a hipGraph once that first call has run. */
+int radon_forward_batched(const radon_job_t *jobs, int32_t n_jobs, int32_t dtype, void *stream);
+int radon_backproject_batched(const radon_job_t *jobs, int32_t n_jobs, int32_t dtype,
+                              void *stream);
+
+/* FP64 inner product sum_i a[i]*b[i] over n elements of `dtype` (device pointers),
+ * written to out (device, one double).  Used for the adjoint (dot-product) test and
+ * for losses; deterministic (fixed reduction tree). */
+int radon_dot_f64(const void *a, const void *b, int64_t n, int32_t dtype, double *out,
+                  void *stream);
+
+/* Free every plan and queue the library holds (synchronises the device). */
+int radon_release_plans(void);
+
+/* Launch shape chosen for a geometry/dtype/batch (after radon_prepare):
+ * out[0..3] = forward {images per thread, angles per block, rays per block, variant},
+ * out[4..7] = the same for the backprojection. */
+int radon_plan_info(const radon_geometry_t *geometry, int32_t dtype, int32_t batch,
+                    int32_t *out8);
+
+/* Static description of a status code. */
+const char *radon_status_string(int status);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int radon_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RADON_H */

@@ -1,0 +1,327 @@
+// C ABI of libradon.so: validation, per-geometry plans, dispatch to the kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/radon.h"
+#include "radon_launch.hpp"
+#include "radon_plan.hpp"
+
+namespace radon {
+
+// ---------------------------------------------------------------- validation
+int validate(const radon_geometry_t *g) {
+    if (!g) return RADON_ERR_INVALID_ARG;
+    if (g->beam != RADON_PARALLEL && g->beam != RADON_FANBEAM) return RADON_ERR_INVALID_ARG;
+    if (g->image_size < 1 || g->n_angles < 1 || g->det_count < 1) return RADON_ERR_INVALID_ARG;
+    // sizes whose index arithmetic would leave 32-bit float/int exactness
+    if (g->image_size > 16384 || g->det_count > (1 << 20) || g->n_angles > (1 << 20))
+        return RADON_ERR_UNSUPPORTED;
+    if (!g->angles) return RADON_ERR_INVALID_ARG;
+    for (int a = 0; a < g->n_angles; ++a)
+        if (!std::isfinite(g->angles[a])) return RADON_ERR_INVALID_ARG;
+    if (!(g->det_spacing > 0.0) || !std::isfinite(g->det_spacing)) return RADON_ERR_INVALID_ARG;
+    if (!(g->step > 0.0) || !std::isfinite(g->step)) return RADON_ERR_INVALID_ARG;
+    if (g->beam == RADON_FANBEAM) {
+        const double support = 0.5 * (g->image_size + 1) * std::sqrt(2.0);
+        if (!(g->source_distance > support) || !std::isfinite(g->source_distance))
+            return RADON_ERR_INVALID_ARG;
+        if (!(g->det_distance >= 0.0) || !std::isfinite(g->det_distance))
+            return RADON_ERR_INVALID_ARG;
+    }
+    return RADON_OK;
+}
+
+static int check_ptr(const void *p) {
+    if (!p) return RADON_ERR_INVALID_ARG;
+    if (reinterpret_cast<uintptr_t>(p) & 15u) return RADON_ERR_ALIGN;
+    return RADON_OK;
+}
+
+static int check_dtype(int32_t dtype) {
+    return (dtype == RADON_F32 || dtype == RADON_F16 || dtype == RADON_BF16) ? RADON_OK
+                                                                             : RADON_ERR_INVALID_ARG;
+}
+
+// ---------------------------------------------------------------- plan cache
+PlanKey make_key(const radon_geometry_t *g, int device) {
+    PlanKey k;
+    k.device = device;
+    k.beam = g->beam;
+    k.n = g->image_size;
+    k.det_count = g->det_count;
+    k.det_spacing = g->det_spacing;
+    k.source_distance = g->beam == RADON_FANBEAM ? g->source_distance : 0.0;
+    k.det_distance = g->beam == RADON_FANBEAM ? g->det_distance : 0.0;
+    k.step = g->step;
+    k.angles.assign(g->angles, g->angles + g->n_angles);
+    return k;
+}
+
+size_t PlanKeyHash::operator()(const PlanKey &k) const {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&h](const void *p, size_t n) {
+        const unsigned char *c = static_cast<const unsigned char *>(p);
+        for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
+    };
+    mix(&k.device, sizeof k.device);
+    mix(&k.beam, sizeof k.beam);
+    mix(&k.n, sizeof k.n);
+    mix(&k.det_count, sizeof k.det_count);
+    mix(&k.det_spacing, sizeof k.det_spacing);
+    mix(&k.source_distance, sizeof k.source_distance);
+    mix(&k.det_distance, sizeof k.det_distance);
+    mix(&k.step, sizeof k.step);
+    mix(k.angles.data(), k.angles.size() * sizeof(double));
+    return (size_t)h;
+}
+
+bool PlanKey::operator==(const PlanKey &o) const {
+    return device == o.device && beam == o.beam && n == o.n && det_count == o.det_count &&
+           det_spacing == o.det_spacing && source_distance == o.source_distance &&
+           det_distance == o.det_distance && step == o.step && angles == o.angles;
+}
+
+Plan::~Plan() {
+    if (trig) (void)hipFree(trig);
+    if (rays) (void)hipFree(rays);
+}
+
+static std::mutex g_mutex;
+static std::unordered_map<PlanKey, std::unique_ptr<Plan>, PlanKeyHash> g_plans;
+struct DeviceScratch { double *dot_partials = nullptr; };
+static std::unordered_map<int, DeviceScratch> g_scratch;
+constexpr int kDotPartials = 1024;
+
+// Host FP64 ray tables, rounded once to FP32.
+static void fill_tables(const radon_geometry_t *g, std::vector<float2> &trig,
+                        std::vector<float4> &rays) {
+    const int A = g->n_angles, D = g->det_count;
+    const double cn = 0.5 * (g->image_size - 1);
+    trig.resize(A);
+    for (int a = 0; a < A; ++a)
+        trig[a] = make_float2((float)std::cos(g->angles[a]), (float)std::sin(g->angles[a]));
+    if (g->beam != RADON_FANBEAM) return;
+    rays.resize((size_t)A * D);
+    const double S = g->source_distance, E = g->det_distance;
+    for (int a = 0; a < A; ++a) {
+        const double ux = std::cos(g->angles[a]), uy = std::sin(g->angles[a]);
+        const double vx = -uy, vy = ux;
+        for (int d = 0; d < D; ++d) {
+            const double s = (d - 0.5 * (D - 1)) * g->det_spacing;
+            const double sx = -S * vx, sy = -S * vy;              // source
+            const double ex = E * vx + s * ux, ey = E * vy + s * uy; // bin centre
+            double wx = ex - sx, wy = ey - sy;
+            const double len = std::sqrt(wx * wx + wy * wy);
+            wx /= len;
+            wy /= len;
+            const double along = sx * wx + sy * wy;
+            const double fx = sx - along * wx, fy = sy - along * wy; // foot point
+            rays[(size_t)a * D + d] = make_float4((float)(fx + cn), (float)(fy + cn),
+                                                  (float)(g->step * wx), (float)(g->step * wy));
+        }
+    }
+}
+
+static int build_plan(const radon_geometry_t *g, int device, std::unique_ptr<Plan> &out) {
+    std::unique_ptr<Plan> p(new (std::nothrow) Plan());
+    if (!p) return RADON_ERR_ALLOC;
+    std::vector<float2> trig;
+    std::vector<float4> rays;
+    fill_tables(g, trig, rays);
+    if (hipMalloc(&p->trig, trig.size() * sizeof(float2)) != hipSuccess) return RADON_ERR_ALLOC;
+    if (hipMemcpy(p->trig, trig.data(), trig.size() * sizeof(float2), hipMemcpyHostToDevice) !=
+        hipSuccess)
+        return RADON_ERR_HIP;
+    if (!rays.empty()) {
+        if (hipMalloc(&p->rays, rays.size() * sizeof(float4)) != hipSuccess) return RADON_ERR_ALLOC;
+        if (hipMemcpy(p->rays, rays.data(), rays.size() * sizeof(float4),
+                      hipMemcpyHostToDevice) != hipSuccess)
+            return RADON_ERR_HIP;
+    }
+    Geom &G = p->geom;
+    G.n = g->image_size;
+    G.n_angles = g->n_angles;
+    G.det_count = g->det_count;
+    G.fan = g->beam == RADON_FANBEAM ? 1 : 0;
+    G.cn = (float)(0.5 * (g->image_size - 1));
+    G.half_d = (float)(0.5 * (g->det_count - 1));
+    G.spacing = (float)g->det_spacing;
+    G.inv_spacing = (float)(1.0 / g->det_spacing);
+    G.step = (float)g->step;
+    G.inv_step = (float)(1.0 / g->step);
+    G.sd = (float)g->source_distance;
+    G.sde = (float)(g->source_distance + g->det_distance);
+    G.trig = p->trig;
+    G.rays = p->rays;
+    p->device = device;
+    out = std::move(p);
+    return RADON_OK;
+}
+
+// Find the plan of g on the current device; build it unless the stream captures.
+int get_plan(const radon_geometry_t *g, hipStream_t stream, Plan **out) {
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return RADON_ERR_NO_DEVICE;
+    PlanKey key = make_key(g, device);
+    std::lock_guard<std::mutex> lock(g_mutex);
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) {
+        *out = it->second.get();
+        return RADON_OK;
+    }
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cap) != hipSuccess) return RADON_ERR_HIP;
+    if (cap != hipStreamCaptureStatusNone) return RADON_ERR_NOT_PREPARED;
+    std::unique_ptr<Plan> p;
+    int rc = build_plan(g, device, p);
+    if (rc != RADON_OK) return rc;
+    *out = p.get();
+    g_plans.emplace(std::move(key), std::move(p));
+    return RADON_OK;
+}
+
+static int dot_scratch(hipStream_t stream, double **out) {
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return RADON_ERR_NO_DEVICE;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    DeviceScratch &s = g_scratch[device];
+    if (!s.dot_partials) {
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(stream, &cap) != hipSuccess) return RADON_ERR_HIP;
+        if (cap != hipStreamCaptureStatusNone) return RADON_ERR_NOT_PREPARED;
+        if (hipMalloc(&s.dot_partials, kDotPartials * sizeof(double)) != hipSuccess)
+            return RADON_ERR_ALLOC;
+    }
+    *out = s.dot_partials;
+    return RADON_OK;
+}
+
+static int release_all() {
+    std::lock_guard<std::mutex> lock(g_mutex);
+    if (!g_plans.empty() || !g_scratch.empty()) (void)hipDeviceSynchronize();
+    g_plans.clear();
+    for (auto &kv : g_scratch)
+        if (kv.second.dot_partials) (void)hipFree(kv.second.dot_partials);
+    g_scratch.clear();
+    return RADON_OK;
+}
+
+}  // namespace radon
+
+using namespace radon;
+
+extern "C" {
+
+int radon_validate(const radon_geometry_t *geometry) { return validate(geometry); }
+
+int radon_prepare(const radon_geometry_t *geometry, int32_t dtype, int32_t batch) {
+    int rc = validate(geometry);
+    if (rc != RADON_OK) return rc;
+    if ((rc = check_dtype(dtype)) != RADON_OK) return rc;
+    if (batch < 0) return RADON_ERR_INVALID_ARG;
+    Plan *p = nullptr;
+    rc = get_plan(geometry, nullptr, &p);
+    if (rc != RADON_OK) return rc;
+    return hipDeviceSynchronize() == hipSuccess ? RADON_OK : RADON_ERR_HIP;
+}
+
+int radon_forward(const radon_geometry_t *geometry, const void *x, void *y, int32_t batch,
+                  int32_t dtype, float scale, void *stream) {
+    int rc = validate(geometry);
+    if (rc != RADON_OK) return rc;
+    if ((rc = check_dtype(dtype)) != RADON_OK) return rc;
+    if (batch < 0 || !std::isfinite(scale)) return RADON_ERR_INVALID_ARG;
+    if (batch == 0) return RADON_OK;
+    if ((rc = check_ptr(x)) != RADON_OK || (rc = check_ptr(y)) != RADON_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Plan *p = nullptr;
+    if ((rc = get_plan(geometry, s, &p)) != RADON_OK) return rc;
+    hipError_t e = launch_forward(p->geom, dtype, p->fwd_shape, x, y, batch, scale, s);
+    return e == hipSuccess ? RADON_OK : RADON_ERR_HIP;
+}
+
+int radon_backproject(const radon_geometry_t *geometry, const void *y, void *x, int32_t batch,
+                      int32_t dtype, float scale, void *stream) {
+    int rc = validate(geometry);
+    if (rc != RADON_OK) return rc;
+    if ((rc = check_dtype(dtype)) != RADON_OK) return rc;
+    if (batch < 0 || !std::isfinite(scale)) return RADON_ERR_INVALID_ARG;
+    if (batch == 0) return RADON_OK;
+    if ((rc = check_ptr(x)) != RADON_OK || (rc = check_ptr(y)) != RADON_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Plan *p = nullptr;
+    if ((rc = get_plan(geometry, s, &p)) != RADON_OK) return rc;
+    hipError_t e = launch_backproject(p->geom, dtype, p->bp_shape, y, x, batch, scale, s);
+    return e == hipSuccess ? RADON_OK : RADON_ERR_HIP;
+}
+
+int radon_forward_batched(const radon_job_t *jobs, int32_t n_jobs, int32_t dtype, void *stream) {
+    (void)jobs; (void)n_jobs; (void)dtype; (void)stream;
+    return RADON_ERR_UNSUPPORTED;
+}
+
+int radon_backproject_batched(const radon_job_t *jobs, int32_t n_jobs, int32_t dtype,
+                              void *stream) {
+    (void)jobs; (void)n_jobs; (void)dtype; (void)stream;
+    return RADON_ERR_UNSUPPORTED;
+}
+
+int radon_dot_f64(const void *a, const void *b, int64_t n, int32_t dtype, double *out,
+                  void *stream) {
+    int rc = check_dtype(dtype);
+    if (rc != RADON_OK) return rc;
+    if (n < 0) return RADON_ERR_INVALID_ARG;
+    if (!out) return RADON_ERR_INVALID_ARG;
+    if (n > 0 && ((rc = check_ptr(a)) != RADON_OK || (rc = check_ptr(b)) != RADON_OK)) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double *partials = nullptr;
+    if ((rc = dot_scratch(s, &partials)) != RADON_OK) return rc;
+    hipError_t e = launch_dot_f64(a, b, (long long)n, dtype, out, partials, kDotPartials, s);
+    return e == hipSuccess ? RADON_OK : RADON_ERR_HIP;
+}
+
+int radon_release_plans(void) { return release_all(); }
+
+int radon_plan_info(const radon_geometry_t *geometry, int32_t dtype, int32_t batch,
+                    int32_t *out8) {
+    int rc = validate(geometry);
+    if (rc != RADON_OK) return rc;
+    if ((rc = check_dtype(dtype)) != RADON_OK) return rc;
+    if (!out8 || batch < 0) return RADON_ERR_INVALID_ARG;
+    Plan *p = nullptr;
+    if ((rc = get_plan(geometry, nullptr, &p)) != RADON_OK) return rc;
+    const LaunchShape *sh[2] = {&p->fwd_shape, &p->bp_shape};
+    for (int i = 0; i < 2; ++i) {
+        out8[4 * i + 0] = sh[i]->images;
+        out8[4 * i + 1] = sh[i]->angles;
+        out8[4 * i + 2] = sh[i]->rays;
+        out8[4 * i + 3] = sh[i]->variant;
+    }
+    return RADON_OK;
+}
+
+const char *radon_status_string(int status) {
+    switch (status) {
+    case RADON_OK: return "ok";
+    case RADON_ERR_INVALID_ARG: return "invalid argument";
+    case RADON_ERR_ALIGN: return "device pointer not 16-byte aligned";
+    case RADON_ERR_UNSUPPORTED: return "unsupported request";
+    case RADON_ERR_HIP: return "HIP runtime error";
+    case RADON_ERR_ALLOC: return "allocation failed";
+    case RADON_ERR_NO_DEVICE: return "no usable GPU";
+    case RADON_ERR_NOT_PREPARED: return "plan missing while the stream is capturing";
+    default: return "unknown status";
+    }
+}
+
+int radon_version(void) { return 100; }
+
+}  // extern "C"

@@ -1,0 +1,44 @@
+// Per-geometry plan: device tables and the launch shapes chosen for them.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "../../include/radon.h"
+#include "radon_common.hpp"
+#include "radon_launch.hpp"
+
+namespace radon {
+
+struct PlanKey {
+    int device = 0;
+    int beam = 0;
+    int n = 0;
+    int det_count = 0;
+    double det_spacing = 0, source_distance = 0, det_distance = 0, step = 0;
+    std::vector<double> angles;
+    bool operator==(const PlanKey &o) const;
+};
+
+struct PlanKeyHash {
+    size_t operator()(const PlanKey &k) const;
+};
+
+struct Plan {
+    int device = 0;
+    Geom geom{};
+    float2 *trig = nullptr;   // device [A]
+    float4 *rays = nullptr;   // device [A*D], fan beam only
+    LaunchShape fwd_shape, bp_shape;
+    Plan() = default;
+    Plan(const Plan &) = delete;
+    Plan &operator=(const Plan &) = delete;
+    ~Plan();
+};
+
+int validate(const radon_geometry_t *g);
+PlanKey make_key(const radon_geometry_t *g, int device);
+int get_plan(const radon_geometry_t *g, hipStream_t stream, Plan **out);
+
+}  // namespace radon

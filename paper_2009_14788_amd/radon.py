@@ -1,0 +1,213 @@
+"""PyTorch-facing API: Radon (parallel beam) and RadonFanbeam (flat-detector fan
+beam), mirroring TorchRadon's constructors and methods (Sec. 3.1.1, 3.1.2, 4.1),
+with autograd through the hand-written transpose kernels (Sec. 2, "Differentiability").
+
+Torch provides device memory and streams only; every projection runs in
+libradon.so.  Tensors must be CUDA (ROCm) tensors of float32, float16 or bfloat16.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import numpy as np
+import torch
+
+from . import _lib
+
+_DTYPES = {torch.float32: _lib.RADON_F32, torch.float16: _lib.RADON_F16,
+           torch.bfloat16: _lib.RADON_BF16}
+
+
+def dtype_code(t: torch.dtype) -> int:
+    try:
+        return _DTYPES[t]
+    except KeyError:
+        raise TypeError(f"unsupported dtype {t}; use float32, float16 or bfloat16") from None
+
+
+def _stream_ptr(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _check_tensor(t: torch.Tensor, what: str) -> None:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{what} must be on a GPU (got {t.device}); there is no CPU path")
+
+
+class _Base:
+    """Common plumbing of both geometries."""
+
+    beam = _lib.RADON_PARALLEL
+
+    def __init__(self, resolution, angles, det_count, det_spacing, step,
+                 source_distance=0.0, det_distance=0.0):
+        self.resolution = int(resolution)
+        self.angles = np.ascontiguousarray(np.asarray(angles, dtype=np.float64).ravel())
+        self.det_count = int(det_count)
+        self.det_spacing = float(det_spacing)
+        self.step = float(step)
+        self.source_distance = float(source_distance)
+        self.det_distance = float(det_distance)
+        self._geom = _lib.Geometry(
+            self.beam, self.resolution, int(self.angles.size), self.det_count,
+            self.angles.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            self.det_spacing, self.source_distance, self.det_distance, self.step)
+        _lib.check("radon_validate", _lib.lib.radon_validate(ctypes.byref(self._geom)))
+
+    # ---------------------------------------------------------------- shapes
+    @property
+    def n_angles(self) -> int:
+        return int(self.angles.size)
+
+    @property
+    def image_shape(self):
+        return (self.resolution, self.resolution)
+
+    @property
+    def sinogram_shape(self):
+        return (self.n_angles, self.det_count)
+
+    @property
+    def geometry(self) -> _lib.Geometry:
+        return self._geom
+
+    # ---------------------------------------------------------------- raw calls
+    def _raw(self, fn_name, inp: torch.Tensor, in_shape, out_shape, scale: float) -> torch.Tensor:
+        _check_tensor(inp, "input")
+        if tuple(inp.shape[-2:]) != tuple(in_shape):
+            raise ValueError(f"expected trailing shape {tuple(in_shape)}, got {tuple(inp.shape)}")
+        code = dtype_code(inp.dtype)
+        lead = inp.shape[:-2]
+        batch = int(np.prod(lead)) if len(lead) else 1
+        src = inp.contiguous()
+        if src.data_ptr() % 16:
+            src = src.clone()          # the library needs 16-byte aligned buffers
+        out = torch.empty(tuple(lead) + tuple(out_shape), dtype=inp.dtype, device=inp.device)
+        if batch == 0:
+            return out
+        with torch.cuda.device(inp.device):
+            rc = getattr(_lib.lib, fn_name)(ctypes.byref(self._geom), src.data_ptr(), out.data_ptr(),
+                                            batch, code, float(scale), _stream_ptr(inp.device))
+        _lib.check(fn_name, rc)
+        return out
+
+    def forward_raw(self, x: torch.Tensor, scale: float = 1.0) -> torch.Tensor:
+        """scale * R x without autograd; x has shape (..., N, N)."""
+        return self._raw("radon_forward", x, self.image_shape, self.sinogram_shape, scale)
+
+    def backprojection_raw(self, y: torch.Tensor, scale: float = 1.0) -> torch.Tensor:
+        """scale * R^T y without autograd; y has shape (..., A, D)."""
+        return self._raw("radon_backproject", y, self.sinogram_shape, self.image_shape, scale)
+
+    # ---------------------------------------------------------------- autograd-aware
+    def forward(self, x: torch.Tensor, scale: float = 1.0) -> torch.Tensor:
+        """Sinogram scale * R x; differentiable (the gradient is scale * R^T g)."""
+        return RadonForward.apply(x, self, float(scale))
+
+    def backprojection(self, y: torch.Tensor, scale: float = 1.0) -> torch.Tensor:
+        """Backprojection scale * R^T y; differentiable (the gradient is scale * R g)."""
+        return RadonBackprojection.apply(y, self, float(scale))
+
+    # the paper's ADMM example calls the backprojection `backward` (Sec. 4.3)
+    backward = backprojection
+
+    def prepare(self, dtype=torch.float32, batch: int = 1, device=None) -> None:
+        """Build the plan (tables, launch shapes) before stream capture."""
+        dev = torch.device("cuda") if device is None else torch.device(device)
+        with torch.cuda.device(dev):
+            _lib.check("radon_prepare", _lib.lib.radon_prepare(
+                ctypes.byref(self._geom), dtype_code(dtype), int(batch)))
+
+    def plan_info(self, dtype=torch.float32, batch: int = 1):
+        out = (ctypes.c_int32 * 8)()
+        _lib.check("radon_plan_info", _lib.lib.radon_plan_info(
+            ctypes.byref(self._geom), dtype_code(dtype), int(batch), out))
+        keys = ("images", "angles", "rays", "variant")
+        return {"forward": dict(zip(keys, out[0:4])), "backprojection": dict(zip(keys, out[4:8]))}
+
+
+class Radon(_Base):
+    """Parallel-beam projector: Radon(resolution, angles, det_count=resolution,
+    det_spacing=1.0, step=1.0) as in TorchRadon Sec. 3.1.1."""
+
+    beam = _lib.RADON_PARALLEL
+
+    def __init__(self, resolution, angles, det_count=None, det_spacing=1.0, step=1.0):
+        det_count = int(resolution) if det_count is None else int(det_count)
+        super().__init__(resolution, angles, det_count, det_spacing, step)
+
+
+def default_fan_spacing(resolution, source_distance, det_distance, det_count) -> float:
+    """Smallest detector spacing whose fan covers the image (Sec. 3.1.2):
+    (S + E) / S * N / D; 2.0 for N = 512, S = E = 512, D = 512."""
+    return (source_distance + det_distance) / source_distance * resolution / det_count
+
+
+class RadonFanbeam(_Base):
+    """Flat-detector fan-beam projector: RadonFanbeam(resolution, angles,
+    source_distance, det_distance=source_distance, det_count=resolution,
+    det_spacing=<covering spacing>, step=1.0) as in TorchRadon Sec. 3.1.2."""
+
+    beam = _lib.RADON_FANBEAM
+
+    def __init__(self, resolution, angles, source_distance, det_distance=None, det_count=None,
+                 det_spacing=None, step=1.0):
+        S = float(source_distance)
+        E = S if det_distance is None else float(det_distance)
+        D = int(resolution) if det_count is None else int(det_count)
+        sp = default_fan_spacing(resolution, S, E, D) if det_spacing is None else float(det_spacing)
+        super().__init__(resolution, angles, D, sp, step, S, E)
+
+
+class RadonForward(torch.autograd.Function):
+    """y = scale * R x; backward applies the hand-written transpose kernel."""
+
+    @staticmethod
+    def forward(ctx, x, op, scale):
+        ctx.op = op
+        ctx.scale = scale
+        return op.forward_raw(x, scale)
+
+    @staticmethod
+    def backward(ctx, g):
+        return ctx.op.backprojection_raw(g.contiguous(), ctx.scale), None, None
+
+
+class RadonBackprojection(torch.autograd.Function):
+    """x = scale * R^T y; backward applies the forward kernel."""
+
+    @staticmethod
+    def forward(ctx, y, op, scale):
+        ctx.op = op
+        ctx.scale = scale
+        return op.backprojection_raw(y, scale)
+
+    @staticmethod
+    def backward(ctx, g):
+        return ctx.op.forward_raw(g.contiguous(), ctx.scale), None, None
+
+
+def dot_f64(a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
+    """sum(a*b) accumulated in FP64 on the GPU (deterministic); returns a 0-d
+    float64 tensor on a's device."""
+    _check_tensor(a, "a")
+    _check_tensor(b, "b")
+    if a.shape != b.shape or a.dtype != b.dtype:
+        raise ValueError("a and b must have the same shape and dtype")
+    a = a.contiguous()
+    b = b.contiguous()
+    a = a.clone() if a.data_ptr() % 16 else a
+    b = b.clone() if b.data_ptr() % 16 else b
+    out = torch.empty((), dtype=torch.float64, device=a.device)
+    with torch.cuda.device(a.device):
+        rc = _lib.lib.radon_dot_f64(a.data_ptr(), b.data_ptr(), a.numel(), dtype_code(a.dtype),
+                                    out.data_ptr(), _stream_ptr(a.device))
+    _lib.check("radon_dot_f64", rc)
+    return out
+
+
+def release_plans() -> None:
+    _lib.check("radon_release_plans", _lib.lib.radon_release_plans())

@@ -1,0 +1,115 @@
+"""Host-only checks of the C ABI: the library loads, exports every function
+include/radon.h declares, and rejects bad arguments before touching a GPU."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2009_14788_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "radon.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(radon_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    names = _declared()
+    assert len(names) >= 11, names
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_header_struct_layout_matches_binding():
+    # radon_geometry_t: 4 x int32, pointer, 4 x double  -> 56 bytes on x86-64
+    assert ctypes.sizeof(_lib.Geometry) == 56
+    assert _lib.Geometry.angles.offset == 16
+    assert _lib.Geometry.step.offset == 48
+    assert ctypes.sizeof(_lib.Job) == 32
+
+
+def _geom(beam=0, n=16, angles=None, D=23, sp=1.0, S=0.0, E=0.0, step=1.0):
+    ang = np.asarray([0.0, 1.0] if angles is None else angles, dtype=np.float64)
+    g = _lib.Geometry(beam, n, ang.size, D, ang.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                      sp, S, E, step)
+    g._keep = ang
+    return g
+
+
+@pytest.mark.parametrize("kw,ok", [
+    ({}, True),
+    ({"n": 0}, False),
+    ({"D": 0}, False),
+    ({"sp": 0.0}, False),
+    ({"sp": -1.0}, False),
+    ({"step": 0.0}, False),
+    ({"step": float("nan")}, False),
+    ({"angles": [0.0, float("inf")]}, False),
+    ({"beam": 2}, False),
+    ({"beam": 1, "S": 100.0, "E": 50.0}, True),
+    ({"beam": 1, "S": 5.0, "E": 50.0}, False),       # source inside the image support
+    ({"beam": 1, "S": 100.0, "E": -1.0}, False),
+    ({"n": 1, "D": 1}, True),
+])
+def test_validate(kw, ok):
+    g = _geom(**kw)
+    rc = _lib.lib.radon_validate(ctypes.byref(g))
+    assert (rc == 0) == ok, rc
+
+
+def test_validate_null():
+    assert _lib.lib.radon_validate(None) == -1
+
+
+def test_status_strings():
+    for code in range(-7, 1):
+        s = _lib.string(code)
+        assert s and s != "unknown status"
+    assert _lib.string(-99) == "unknown status"
+    assert _lib.lib.radon_version() >= 100
+
+
+def test_argument_errors_before_device_use():
+    g = _geom()
+    f = _lib.lib.radon_forward
+    # batch 0 is a no-op
+    assert f(ctypes.byref(g), None, None, 0, 0, 1.0, None) == 0
+    assert _lib.lib.radon_backproject(ctypes.byref(g), None, None, 0, 0, 1.0, None) == 0
+    # null and misaligned pointers, bad dtype, negative batch, non-finite scale
+    assert f(ctypes.byref(g), None, None, 1, 0, 1.0, None) == -1
+    assert f(ctypes.byref(g), 0x1004, 0x2000, 1, 0, 1.0, None) == -2
+    assert f(ctypes.byref(g), 0x1000, 0x2000, 1, 7, 1.0, None) == -1
+    assert f(ctypes.byref(g), 0x1000, 0x2000, -1, 0, 1.0, None) == -1
+    assert f(ctypes.byref(g), 0x1000, 0x2000, 1, 0, float("inf"), None) == -1
+    bad = _geom(sp=0.0)
+    assert f(ctypes.byref(bad), 0x1000, 0x2000, 1, 0, 1.0, None) == -1
+    assert _lib.lib.radon_dot_f64(0x1000, 0x2000, -1, 0, 0x3000, None) == -1
+    assert _lib.lib.radon_dot_f64(0x1000, 0x2000, 4, 0, None, None) == -1
+    assert _lib.lib.radon_dot_f64(0x1004, 0x2000, 4, 0, 0x3000, None) == -2
+
+
+def test_default_fan_spacing_worked_example():
+    """tests/golden/fan_default_spacing.txt (Sec. 3.1.2 worked example)."""
+    from paper_2009_14788_amd.radon import default_fan_spacing
+    rows = [l.split() for l in open(os.path.join(ROOT, "tests", "golden", "fan_default_spacing.txt"))
+            if l.strip() and not l.startswith("#")]
+    for n, S, E, D, sp in rows:
+        assert math.isclose(default_fan_spacing(int(n), float(S), float(E), int(D)), float(sp))
+
+
+def test_python_facade_defaults():
+    from paper_2009_14788_amd.radon import Radon, RadonFanbeam
+    r = Radon(512, np.linspace(0, np.pi, 512, endpoint=False))
+    assert r.det_count == 512 and r.det_spacing == 1.0 and r.sinogram_shape == (512, 512)
+    f = RadonFanbeam(512, np.linspace(0, 2 * np.pi, 512, endpoint=False), source_distance=512)
+    assert f.det_distance == 512 and f.det_count == 512 and f.det_spacing == 2.0
+    with pytest.raises(_lib.RadonError):
+        Radon(16, [0.0], det_spacing=-1.0)
