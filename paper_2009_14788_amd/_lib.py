@@ -49,6 +49,13 @@ class Job(ctypes.Structure):
 
 
 def _load():
+    # PyTorch ships its own HIP runtime (same soname, libamdhip64.so.7).  Loading torch
+    # first makes libradon.so bind to that runtime, so that the library and torch share
+    # one HIP runtime, one device context and the same streams.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "

@@ -100,14 +100,14 @@ struct DeviceScratch { double *dot_partials = nullptr; };
 static std::unordered_map<int, DeviceScratch> g_scratch;
 constexpr int kDotPartials = 1024;
 
-// Host FP64 ray tables, rounded once to FP32.
-static void fill_tables(const radon_geometry_t *g, std::vector<float2> &trig,
-                        std::vector<float4> &rays) {
+// Host FP64 angle and ray tables.
+static void fill_tables(const radon_geometry_t *g, std::vector<double2> &trig,
+                        std::vector<double4> &rays) {
     const int A = g->n_angles, D = g->det_count;
     const double cn = 0.5 * (g->image_size - 1);
     trig.resize(A);
     for (int a = 0; a < A; ++a)
-        trig[a] = make_float2((float)std::cos(g->angles[a]), (float)std::sin(g->angles[a]));
+        trig[a] = make_double2(std::cos(g->angles[a]), std::sin(g->angles[a]));
     if (g->beam != RADON_FANBEAM) return;
     rays.resize((size_t)A * D);
     const double S = g->source_distance, E = g->det_distance;
@@ -124,8 +124,7 @@ static void fill_tables(const radon_geometry_t *g, std::vector<float2> &trig,
             wy /= len;
             const double along = sx * wx + sy * wy;
             const double fx = sx - along * wx, fy = sy - along * wy; // foot point
-            rays[(size_t)a * D + d] = make_float4((float)(fx + cn), (float)(fy + cn),
-                                                  (float)(g->step * wx), (float)(g->step * wy));
+            rays[(size_t)a * D + d] = make_double4(fx + cn, fy + cn, g->step * wx, g->step * wy);
         }
     }
 }
@@ -133,16 +132,16 @@ static void fill_tables(const radon_geometry_t *g, std::vector<float2> &trig,
 static int build_plan(const radon_geometry_t *g, int device, std::unique_ptr<Plan> &out) {
     std::unique_ptr<Plan> p(new (std::nothrow) Plan());
     if (!p) return RADON_ERR_ALLOC;
-    std::vector<float2> trig;
-    std::vector<float4> rays;
+    std::vector<double2> trig;
+    std::vector<double4> rays;
     fill_tables(g, trig, rays);
-    if (hipMalloc(&p->trig, trig.size() * sizeof(float2)) != hipSuccess) return RADON_ERR_ALLOC;
-    if (hipMemcpy(p->trig, trig.data(), trig.size() * sizeof(float2), hipMemcpyHostToDevice) !=
+    if (hipMalloc(&p->trig, trig.size() * sizeof(double2)) != hipSuccess) return RADON_ERR_ALLOC;
+    if (hipMemcpy(p->trig, trig.data(), trig.size() * sizeof(double2), hipMemcpyHostToDevice) !=
         hipSuccess)
         return RADON_ERR_HIP;
     if (!rays.empty()) {
-        if (hipMalloc(&p->rays, rays.size() * sizeof(float4)) != hipSuccess) return RADON_ERR_ALLOC;
-        if (hipMemcpy(p->rays, rays.data(), rays.size() * sizeof(float4),
+        if (hipMalloc(&p->rays, rays.size() * sizeof(double4)) != hipSuccess) return RADON_ERR_ALLOC;
+        if (hipMemcpy(p->rays, rays.data(), rays.size() * sizeof(double4),
                       hipMemcpyHostToDevice) != hipSuccess)
             return RADON_ERR_HIP;
     }
@@ -151,14 +150,14 @@ static int build_plan(const radon_geometry_t *g, int device, std::unique_ptr<Pla
     G.n_angles = g->n_angles;
     G.det_count = g->det_count;
     G.fan = g->beam == RADON_FANBEAM ? 1 : 0;
-    G.cn = (float)(0.5 * (g->image_size - 1));
-    G.half_d = (float)(0.5 * (g->det_count - 1));
-    G.spacing = (float)g->det_spacing;
-    G.inv_spacing = (float)(1.0 / g->det_spacing);
-    G.step = (float)g->step;
-    G.inv_step = (float)(1.0 / g->step);
-    G.sd = (float)g->source_distance;
-    G.sde = (float)(g->source_distance + g->det_distance);
+    G.cn = 0.5 * (g->image_size - 1);
+    G.half_d = 0.5 * (g->det_count - 1);
+    G.spacing = g->det_spacing;
+    G.inv_spacing = 1.0 / g->det_spacing;
+    G.step = g->step;
+    G.inv_step = 1.0 / g->step;
+    G.sd = g->source_distance;
+    G.sde = g->source_distance + g->det_distance;
     G.trig = p->trig;
     G.rays = p->rays;
     p->device = device;

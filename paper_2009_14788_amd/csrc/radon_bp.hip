@@ -12,47 +12,46 @@ namespace radon {
 // Bins [dlo, dhi] whose rays can pass through the 2x2-pixel footprint of the pixel
 // with centred coordinates (qx, qy) at angle cs = (cos, sin).  A sample inside the
 // footprint differs from the pixel centre by less than 1 in x and in y, so its
-// detector coordinate is within |cos|+|sin| (parallel), or between the projections
-// of the footprint corners (fan), of the pixel's.  The 1e-3 margin covers FP32
-// rounding of the sample positions.
-__device__ __forceinline__ void bin_window(const Geom &g, float qx, float qy, float2 cs,
+// detector coordinate is within |cos|+|sin| of the pixel's (parallel), or between
+// the projections of the footprint corners (fan).  The margin covers rounding.
+__device__ __forceinline__ void bin_window(const Geom &g, double qx, double qy, double2 cs,
                                            int &dlo, int &dhi) {
-    float lo, hi;
+    double lo, hi;
     if (!g.fan) {
-        const float t = fmaf(qx, cs.x, qy * cs.y);
-        const float h = fabsf(cs.x) + fabsf(cs.y);
+        const double t = fma(qx, cs.x, qy * cs.y);
+        const double h = fabs(cs.x) + fabs(cs.y);
         lo = (t - h) * g.inv_spacing + g.half_d;
         hi = (t + h) * g.inv_spacing + g.half_d;
     } else {
-        lo = 3.0e7f;
-        hi = -3.0e7f;
+        lo = 1.0e9;
+        hi = -1.0e9;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const float px = qx + ((j & 1) ? 1.0f : -1.0f);
-            const float py = qy + ((j & 2) ? 1.0f : -1.0f);
-            const float pu = fmaf(px, cs.x, py * cs.y);
-            const float pv = fmaf(-px, cs.y, py * cs.x);
-            const float s = g.sde * pu / (g.sd + pv) * g.inv_spacing + g.half_d;
-            lo = fminf(lo, s);
-            hi = fmaxf(hi, s);
+            const double px = qx + ((j & 1) ? 1.0 : -1.0);
+            const double py = qy + ((j & 2) ? 1.0 : -1.0);
+            const double pu = fma(px, cs.x, py * cs.y);
+            const double pv = fma(-px, cs.y, py * cs.x);
+            const double s = g.sde * pu / (g.sd + pv) * g.inv_spacing + g.half_d;
+            lo = fmin(lo, s);
+            hi = fmax(hi, s);
         }
     }
-    dlo = max(0, (int)ceilf(lo - 1e-3f));
-    dhi = min(g.det_count - 1, (int)floorf(hi + 1e-3f));
+    dlo = max(0, (int)ceil(lo - 1e-6));
+    dhi = min(g.det_count - 1, (int)floor(hi + 1e-6));
 }
 
-// Sum over the samples k of ray rp of the bilinear weight they give pixel (rf, cf).
-__device__ __forceinline__ float footprint_weight(const Geom &g, const float4 &rp, float cf,
-                                                  float rf) {
-    const float is2 = g.inv_step * g.inv_step;
-    const float kc = fmaf(cf - rp.x, rp.z, (rf - rp.y) * rp.w) * is2;
-    const float hk = (fabsf(rp.z) + fabsf(rp.w)) * is2;
-    const int klo = (int)ceilf(kc - hk - 1e-3f), khi = (int)floorf(kc + hk + 1e-3f);
+// Sum over the samples k of ray rp of the bilinear weight they give pixel (r, c),
+// with the sample positions and FP32 weights formed exactly as in the forward kernel.
+__device__ __forceinline__ float footprint_weight(const Geom &g, const double4 &rp, int c, int r) {
+    const double is2 = g.inv_step * g.inv_step;
+    const double kc = fma((double)c - rp.x, rp.z, ((double)r - rp.y) * rp.w) * is2;
+    const double hk = (fabs(rp.z) + fabs(rp.w)) * is2;
+    const int klo = (int)ceil(kc - hk - 1e-6), khi = (int)floor(kc + hk + 1e-6);
     float w = 0.0f;
     for (int k = klo; k <= khi; ++k) {
-        const float kf = (float)k;
-        const float px = fmaf(kf, rp.z, rp.x), py = fmaf(kf, rp.w, rp.y);
-        w += __fmul_rn(tent(px, cf), tent(py, rf));
+        const double kd = (double)k;
+        const Cell cx = cell_of(fma(kd, rp.z, rp.x)), cy = cell_of(fma(kd, rp.w, rp.y));
+        w += __fmul_rn(axis_weight(cx, c), axis_weight(cy, r));
     }
     return w;
 }
@@ -67,8 +66,7 @@ __global__ __launch_bounds__(256) void bp_direct(Geom g, const T *__restrict__ y
     const int b0 = blockIdx.z * BC;
     const int n = g.n;
     if (c >= n || r >= n) return;
-    const float cf = (float)c, rf = (float)r;
-    const float qx = cf - g.cn, qy = rf - g.cn;
+    const double qx = (double)c - g.cn, qy = (double)r - g.cn;
     const size_t sino = (size_t)g.n_angles * g.det_count;
 
     const T *src[BC];
@@ -80,12 +78,12 @@ __global__ __launch_bounds__(256) void bp_direct(Geom g, const T *__restrict__ y
     for (int i = 0; i < BC; ++i) acc[i] = 0.0f;
 
     for (int a = 0; a < g.n_angles; ++a) {
-        const float2 cs = g.trig[a];
+        const double2 cs = g.trig[a];
         int dlo, dhi;
         bin_window(g, qx, qy, cs, dlo, dhi);
         const size_t row = (size_t)a * g.det_count;
         for (int d = dlo; d <= dhi; ++d) {
-            const float w = footprint_weight(g, ray_params(g, a, d), cf, rf);
+            const float w = footprint_weight(g, ray_params(g, a, d), c, r);
 #pragma unroll
             for (int i = 0; i < BC; ++i) acc[i] = fmaf(w, Store<T>::load(src[i] + row + d), acc[i]);
         }
@@ -110,10 +108,12 @@ static hipError_t launch_bp_direct(const Geom &g, const void *y, void *x, int ba
 hipError_t launch_backproject(const Geom &g, int dtype, const LaunchShape &shape, const void *y,
                               void *x, int batch, float scale, hipStream_t s) {
     (void)shape;
+    // every matrix entry carries the step length: R = step * (sum of sample weights)
+    const float scale_dt = (float)(scale * g.step);
     switch (dtype) {
-    case F32: return launch_bp_direct<float, 4>(g, y, x, batch, scale, s);
-    case F16: return launch_bp_direct<__half, 4>(g, y, x, batch, scale, s);
-    case BF16: return launch_bp_direct<bf16_t, 4>(g, y, x, batch, scale, s);
+    case F32: return launch_bp_direct<float, 4>(g, y, x, batch, scale_dt, s);
+    case F16: return launch_bp_direct<__half, 4>(g, y, x, batch, scale_dt, s);
+    case BF16: return launch_bp_direct<bf16_t, 4>(g, y, x, batch, scale_dt, s);
     default: return hipErrorInvalidValue;
     }
 }

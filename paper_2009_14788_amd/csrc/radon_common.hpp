@@ -8,9 +8,9 @@
 // A ray is (ox, oy) = its foot point F in index coordinates and (sx, sy) =
 // step * its unit direction w; sample k sits at (fma(k, sx, ox), fma(k, sy, oy)).
 // Forward and backprojection evaluate sample positions with exactly this
-// expression from the same FP32 ray parameters, and the bilinear weights as the
-// products (1-fx or fx) * (1-fy or fy) of the same factors, so the two kernels
-// use bit-identical matrix entries and differ only in summation order.
+// expression from the same ray parameters, and the bilinear weights as the
+// products (1-fx or fx) * (1-fy or fy) of the same FP32 factors, so the two
+// kernels use bit-identical sample weights and differ only in summation order.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -56,61 +56,73 @@ template <> struct Store<bf16_t> {
 
 // ---------------------------------------------------------------- geometry
 struct Geom {
-    int n;              // image side N
-    int n_angles;       // A
-    int det_count;      // D
-    int fan;            // 0 parallel, 1 fan
-    float cn;           // (N-1)/2
-    float half_d;       // (D-1)/2
-    float spacing;      // detector spacing
-    float inv_spacing;
-    float step;         // sample spacing along a ray
-    float inv_step;
-    float sd;           // fan: source distance S
-    float sde;          // fan: S + E
-    const float2 *trig; // [A] (cos, sin) of each angle, FP32 rounded from FP64
-    const float4 *rays; // fan: [A*D] (ox, oy, sx, sy), FP32 rounded from FP64
+    int n;               // image side N
+    int n_angles;        // A
+    int det_count;       // D
+    int fan;             // 0 parallel, 1 fan
+    double cn;           // (N-1)/2
+    double half_d;       // (D-1)/2
+    double spacing;      // detector spacing
+    double inv_spacing;
+    double step;         // sample spacing along a ray
+    double inv_step;
+    double sd;           // fan: source distance S
+    double sde;          // fan: S + E
+    const double2 *trig; // [A] (cos, sin) of each angle
+    const double4 *rays; // fan: [A*D] (ox, oy, sx, sy)
 };
 
-// Ray parameters of (angle a, bin d).
-__device__ __forceinline__ float4 ray_params(const Geom &g, int a, int d) {
+// Ray parameters of (angle a, bin d), FP64: foot point in index coordinates and
+// step * unit direction.  Sample positions are formed in FP64 and only their
+// fractional parts (the bilinear weights) drop to FP32, so a sample's weights are
+// accurate to FP32 rounding wherever it lies in the image.
+__device__ __forceinline__ double4 ray_params(const Geom &g, int a, int d) {
     if (g.fan) return g.rays[(size_t)a * g.det_count + d];
-    float2 cs = g.trig[a];
-    float s = ((float)d - g.half_d) * g.spacing;
-    return make_float4(fmaf(s, cs.x, g.cn), fmaf(s, cs.y, g.cn), -cs.y * g.step, cs.x * g.step);
+    const double2 cs = g.trig[a];
+    const double s = ((double)d - g.half_d) * g.spacing;
+    return make_double4(fma(s, cs.x, g.cn), fma(s, cs.y, g.cn), -cs.y * g.step, cs.x * g.step);
 }
 
 // Integer k range [klo, khi] (a superset) of the samples with px, py in (-1, N),
 // i.e. inside the support of the bilinear interpolant.  Empty when klo > khi.
-__device__ __forceinline__ void sample_range(const float4 &r, int n, int &klo, int &khi) {
-    float lo = -3.0e7f, hi = 3.0e7f;
-    const float fn = (float)n;
-    // x axis
-    if (fabsf(r.z) > 1e-12f) {
-        float inv = 1.0f / r.z;
-        float t1 = (-1.0f - r.x) * inv, t2 = (fn - r.x) * inv;
-        lo = fmaxf(lo, fminf(t1, t2));
-        hi = fminf(hi, fmaxf(t1, t2));
-    } else if (!(r.x > -1.0f && r.x < fn)) {
-        lo = 1.0f; hi = -1.0f;
-    }
-    if (fabsf(r.w) > 1e-12f) {
-        float inv = 1.0f / r.w;
-        float t1 = (-1.0f - r.y) * inv, t2 = (fn - r.y) * inv;
-        lo = fmaxf(lo, fminf(t1, t2));
-        hi = fminf(hi, fmaxf(t1, t2));
-    } else if (!(r.y > -1.0f && r.y < fn)) {
-        lo = 1.0f; hi = -1.0f;
+__device__ __forceinline__ void sample_range(const double4 &r, int n, int &klo, int &khi) {
+    double lo = -1.0e9, hi = 1.0e9;
+    const double fn = (double)n;
+    const double o[2] = {r.x, r.y}, w[2] = {r.z, r.w};
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        if (fabs(w[i]) > 1e-300) {
+            const double inv = 1.0 / w[i];
+            const double t1 = (-1.0 - o[i]) * inv, t2 = (fn - o[i]) * inv;
+            lo = fmax(lo, fmin(t1, t2));
+            hi = fmin(hi, fmax(t1, t2));
+        } else if (!(o[i] > -1.0 && o[i] < fn)) {
+            lo = 1.0;
+            hi = -1.0;
+        }
     }
     if (lo > hi) { klo = 1; khi = 0; return; }
-    klo = (int)floorf(lo);
-    khi = (int)ceilf(hi);
+    klo = (int)floor(lo);
+    khi = (int)ceil(hi);
 }
 
-// Tent factor for the pixel at integer index q of a sample at fractional index p:
-// max(0, 1 - |p - q|); equals 1-frac(p) for q = floor(p) and frac(p) for q = floor(p)+1.
-__device__ __forceinline__ float tent(float p, float q) {
-    return fmaxf(0.0f, 1.0f - fabsf(p - q));
+// Sample position along one axis: integer cell index (floor) and FP32 fraction.
+// The pixel at index floor(p) gets weight 1 - frac, the next one frac.
+struct Cell {
+    int i;
+    float f;
+};
+__device__ __forceinline__ Cell cell_of(double p) {
+    const double fl = floor(p);
+    Cell c;
+    c.i = (int)fl;
+    c.f = (float)(p - fl);
+    return c;
+}
+
+// Weight that a sample in cell c gives pixel index q along one axis.
+__device__ __forceinline__ float axis_weight(const Cell &c, int q) {
+    return q == c.i ? 1.0f - c.f : (q == c.i + 1 ? c.f : 0.0f);
 }
 
 }  // namespace radon

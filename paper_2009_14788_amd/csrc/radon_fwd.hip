@@ -19,7 +19,7 @@ __global__ __launch_bounds__(256) void fwd_direct(Geom g, const T *__restrict__ 
     if (d >= g.det_count) return;
     const int n = g.n;
     const size_t img = (size_t)n * n;
-    const float4 r = ray_params(g, a, d);
+    const double4 r = ray_params(g, a, d);
     int klo, khi;
     sample_range(r, n, klo, khi);
 
@@ -32,12 +32,10 @@ __global__ __launch_bounds__(256) void fwd_direct(Geom g, const T *__restrict__ 
     for (int i = 0; i < BC; ++i) acc[i] = 0.0f;
 
     for (int k = klo; k <= khi; ++k) {
-        const float kf = (float)k;
-        const float px = fmaf(kf, r.z, r.x), py = fmaf(kf, r.w, r.y);
-        const float c0f = floorf(px), r0f = floorf(py);
-        const float wx0 = tent(px, c0f), wx1 = tent(px, c0f + 1.0f);
-        const float wy0 = tent(py, r0f), wy1 = tent(py, r0f + 1.0f);
-        const int c0 = (int)c0f, r0 = (int)r0f;
+        const double kd = (double)k;
+        const Cell cx = cell_of(fma(kd, r.z, r.x)), cy = cell_of(fma(kd, r.w, r.y));
+        const float wx0 = 1.0f - cx.f, wx1 = cx.f, wy0 = 1.0f - cy.f, wy1 = cy.f;
+        const int c0 = cx.i, r0 = cy.i;
         const bool vc0 = (unsigned)c0 < (unsigned)n, vc1 = (unsigned)(c0 + 1) < (unsigned)n;
         const bool vr0 = (unsigned)r0 < (unsigned)n, vr1 = (unsigned)(r0 + 1) < (unsigned)n;
         const float w00 = (vr0 && vc0) ? __fmul_rn(wx0, wy0) : 0.0f;
@@ -79,7 +77,7 @@ static hipError_t launch_fwd_direct(const Geom &g, const void *x, void *y, int b
 
 hipError_t launch_forward(const Geom &g, int dtype, const LaunchShape &shape, const void *x,
                           void *y, int batch, float scale, hipStream_t s) {
-    const float scale_dt = scale * g.step;
+    const float scale_dt = (float)(scale * g.step);
     (void)shape;
     switch (dtype) {
     case F32: return launch_fwd_direct<float, 4>(g, x, y, batch, scale_dt, s);

@@ -28,8 +28,8 @@ struct PlanKeyHash {
 struct Plan {
     int device = 0;
     Geom geom{};
-    float2 *trig = nullptr;   // device [A]
-    float4 *rays = nullptr;   // device [A*D], fan beam only
+    double2 *trig = nullptr;  // device [A]
+    double4 *rays = nullptr;  // device [A*D], fan beam only
     LaunchShape fwd_shape, bp_shape;
     Plan() = default;
     Plan(const Plan &) = delete;
