@@ -3,6 +3,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -29,6 +30,8 @@ int validate(const radon_geometry_t *g) {
         if (!std::isfinite(g->angles[a])) return RADON_ERR_INVALID_ARG;
     if (!(g->det_spacing > 0.0) || !std::isfinite(g->det_spacing)) return RADON_ERR_INVALID_ARG;
     if (!(g->step > 0.0) || !std::isfinite(g->step)) return RADON_ERR_INVALID_ARG;
+    // keep per-ray sample counts and sample indices well inside 32-bit range
+    if (g->step < 1e-3 || g->step > 1e3 || g->det_spacing > 1e6) return RADON_ERR_UNSUPPORTED;
     if (g->beam == RADON_FANBEAM) {
         const double support = 0.5 * (g->image_size + 1) * std::sqrt(2.0);
         if (!(g->source_distance > support) || !std::isfinite(g->source_distance))
@@ -92,6 +95,8 @@ bool PlanKey::operator==(const PlanKey &o) const {
 Plan::~Plan() {
     if (trig) (void)hipFree(trig);
     if (rays) (void)hipFree(rays);
+    if (fwd_items) (void)hipFree(fwd_items);
+    if (fwd_ranges) (void)hipFree(fwd_ranges);
 }
 
 static std::mutex g_mutex;
@@ -101,6 +106,7 @@ static std::unordered_map<int, DeviceScratch> g_scratch;
 constexpr int kDotPartials = 1024;
 
 // Host FP64 angle and ray tables.
+// rays[a*D+d] = (ox, oy, sx, sy): foot point in index coordinates, step * direction.
 static void fill_tables(const radon_geometry_t *g, std::vector<double2> &trig,
                         std::vector<double4> &rays) {
     const int A = g->n_angles, D = g->det_count;
@@ -108,8 +114,17 @@ static void fill_tables(const radon_geometry_t *g, std::vector<double2> &trig,
     trig.resize(A);
     for (int a = 0; a < A; ++a)
         trig[a] = make_double2(std::cos(g->angles[a]), std::sin(g->angles[a]));
-    if (g->beam != RADON_FANBEAM) return;
     rays.resize((size_t)A * D);
+    if (g->beam != RADON_FANBEAM) {
+        for (int a = 0; a < A; ++a)
+            for (int d = 0; d < D; ++d) {
+                const double s = (d - 0.5 * (D - 1)) * g->det_spacing;
+                const double c = trig[a].x, sn = trig[a].y;
+                rays[(size_t)a * D + d] =
+                    make_double4(std::fma(s, c, cn), std::fma(s, sn, cn), -sn * g->step, c * g->step);
+            }
+        return;
+    }
     const double S = g->source_distance, E = g->det_distance;
     for (int a = 0; a < A; ++a) {
         const double ux = std::cos(g->angles[a]), uy = std::sin(g->angles[a]);
@@ -139,11 +154,39 @@ static int build_plan(const radon_geometry_t *g, int device, std::unique_ptr<Pla
     if (hipMemcpy(p->trig, trig.data(), trig.size() * sizeof(double2), hipMemcpyHostToDevice) !=
         hipSuccess)
         return RADON_ERR_HIP;
-    if (!rays.empty()) {
+    if (g->beam == RADON_FANBEAM) {
         if (hipMalloc(&p->rays, rays.size() * sizeof(double4)) != hipSuccess) return RADON_ERR_ALLOC;
         if (hipMemcpy(p->rays, rays.data(), rays.size() * sizeof(double4),
                       hipMemcpyHostToDevice) != hipSuccess)
             return RADON_ERR_HIP;
+    }
+    // tiled forward work items
+    std::vector<FwdItem> items;
+    std::vector<int2> ranges;
+    int tile_t = 0;
+    const char *force = std::getenv("RADON_VARIANT");
+    const bool want_direct = force && std::strcmp(force, "direct") == 0;
+    if (!want_direct &&
+        plan_forward_tiles(g->image_size, g->n_angles, g->det_count, rays, items, ranges, tile_t) &&
+        !items.empty()) {
+        if (hipMalloc(&p->fwd_items, items.size() * sizeof(FwdItem)) != hipSuccess)
+            return RADON_ERR_ALLOC;
+        if (hipMemcpy(p->fwd_items, items.data(), items.size() * sizeof(FwdItem),
+                      hipMemcpyHostToDevice) != hipSuccess)
+            return RADON_ERR_HIP;
+        const size_t nr = std::max<size_t>(ranges.size(), 1);
+        if (hipMalloc(&p->fwd_ranges, nr * sizeof(int2)) != hipSuccess) return RADON_ERR_ALLOC;
+        if (!ranges.empty() && hipMemcpy(p->fwd_ranges, ranges.data(), ranges.size() * sizeof(int2),
+                                         hipMemcpyHostToDevice) != hipSuccess)
+            return RADON_ERR_HIP;
+        p->fwd_work.items = p->fwd_items;
+        p->fwd_work.ranges = p->fwd_ranges;
+        p->fwd_work.n_items = (int)items.size();
+        p->fwd_work.tile_t = tile_t | 1;
+        p->fwd_shape.variant = VARIANT_TILED;
+        p->fwd_shape.images = 8;
+        p->fwd_shape.angles = kFwdWaves;
+        p->fwd_shape.rays = kFwdLanes;
     }
     Geom &G = p->geom;
     G.n = g->image_size;
@@ -243,7 +286,7 @@ int radon_forward(const radon_geometry_t *geometry, const void *x, void *y, int3
     hipStream_t s = static_cast<hipStream_t>(stream);
     Plan *p = nullptr;
     if ((rc = get_plan(geometry, s, &p)) != RADON_OK) return rc;
-    hipError_t e = launch_forward(p->geom, dtype, p->fwd_shape, x, y, batch, scale, s);
+    hipError_t e = launch_forward(p->geom, p->fwd_work, dtype, p->fwd_shape, x, y, batch, scale, s);
     return e == hipSuccess ? RADON_OK : RADON_ERR_HIP;
 }
 

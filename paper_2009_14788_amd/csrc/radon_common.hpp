@@ -54,6 +54,73 @@ template <> struct Store<bf16_t> {
     }
 };
 
+// ---------------------------------------------------------------- 16-byte LDS chunks
+// A chunk holds one pixel of kImages images (4 FP32 or 8 FP16/BF16 values); the
+// tiled kernels move image and sinogram data through LDS in such chunks so that
+// every LDS read is a full 16-byte lane access.
+template <typename T> struct Chunk;
+
+template <> struct Chunk<float> {
+    static constexpr int kImages = 4;
+    static __device__ __forceinline__ float zero() { return 0.0f; }
+    static __device__ __forceinline__ uint4 pack(const float *v) {
+        return make_uint4(__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]),
+                          __float_as_uint(v[3]));
+    }
+    static __device__ __forceinline__ void fma(float w, const uint4 &t, float *acc) {
+        acc[0] = fmaf(w, __uint_as_float(t.x), acc[0]);
+        acc[1] = fmaf(w, __uint_as_float(t.y), acc[1]);
+        acc[2] = fmaf(w, __uint_as_float(t.z), acc[2]);
+        acc[3] = fmaf(w, __uint_as_float(t.w), acc[3]);
+    }
+};
+
+__device__ __forceinline__ float half_lo(uint32_t u) {
+    return __half2float(__ushort_as_half((unsigned short)(u & 0xffffu)));
+}
+__device__ __forceinline__ float half_hi(uint32_t u) {
+    return __half2float(__ushort_as_half((unsigned short)(u >> 16)));
+}
+
+template <> struct Chunk<__half> {
+    static constexpr int kImages = 8;
+    static __device__ __forceinline__ __half zero() { return __ushort_as_half(0); }
+    static __device__ __forceinline__ uint4 pack(const __half *v) {
+        uint32_t w[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            w[k] = (uint32_t)__half_as_ushort(v[2 * k]) | ((uint32_t)__half_as_ushort(v[2 * k + 1]) << 16);
+        return make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    static __device__ __forceinline__ void fma(float w, const uint4 &t, float *acc) {
+        const uint32_t u[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            acc[2 * k] = fmaf(w, half_lo(u[k]), acc[2 * k]);
+            acc[2 * k + 1] = fmaf(w, half_hi(u[k]), acc[2 * k + 1]);
+        }
+    }
+};
+
+template <> struct Chunk<bf16_t> {
+    static constexpr int kImages = 8;
+    static __device__ __forceinline__ bf16_t zero() { return bf16_t{0}; }
+    static __device__ __forceinline__ uint4 pack(const bf16_t *v) {
+        uint32_t w[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) w[k] = (uint32_t)v[2 * k].bits | ((uint32_t)v[2 * k + 1].bits << 16);
+        return make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    static __device__ __forceinline__ void fma(float w, const uint4 &t, float *acc) {
+        const uint32_t u[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            acc[2 * k] = fmaf(w, __uint_as_float(u[k] << 16), acc[2 * k]);
+            acc[2 * k + 1] = fmaf(w, __uint_as_float(u[k] & 0xffff0000u), acc[2 * k + 1]);
+        }
+    }
+};
+
 // ---------------------------------------------------------------- geometry
 struct Geom {
     int n;               // image side N
@@ -104,6 +171,29 @@ __device__ __forceinline__ void sample_range(const double4 &r, int n, int &klo, 
     if (lo > hi) { klo = 1; khi = 0; return; }
     klo = (int)floor(lo);
     khi = (int)ceil(hi);
+}
+
+// Exact k range [klo, khi] of the samples strictly inside the support box
+// (-1, N)^2 (up to FP64 rounding at the boundary, where a sample's weight is ~0).
+__device__ __forceinline__ void support_range(const double4 &r, int n, int &klo, int &khi) {
+    double lo = -1.0e9, hi = 1.0e9;
+    const double fn = (double)n;
+    const double o[2] = {r.x, r.y}, w[2] = {r.z, r.w};
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        if (fabs(w[i]) > 1e-300) {
+            const double inv = 1.0 / w[i];
+            const double t1 = (-1.0 - o[i]) * inv, t2 = (fn - o[i]) * inv;
+            lo = fmax(lo, fmin(t1, t2));
+            hi = fmin(hi, fmax(t1, t2));
+        } else if (!(o[i] > -1.0 && o[i] < fn)) {
+            lo = 1.0;
+            hi = -1.0;
+        }
+    }
+    if (lo > hi) { klo = 1; khi = 0; return; }
+    klo = (int)ceil(lo);
+    khi = (int)floor(hi);
 }
 
 // Sample position along one axis: integer cell index (floor) and FP32 fraction.

@@ -65,6 +65,119 @@ __global__ __launch_bounds__(256) void fwd_direct(Geom g, const T *__restrict__ 
     }
 }
 
+// ------------------------------------------------------------------ tiled variant
+// One block = one work item (up to 4 angles x 64 bins; wave w <-> angle a0+w, lane
+// l <-> bin d0+l) x BC images.  The rays march through the image in slabs of
+// kSlabH rows (or columns); per slab the block stages the slab's pixel window
+// into LDS as 16-byte chunks holding Chunk<T>::kImages images each ("planes"),
+// then every lane walks its ray's samples inside the slab.  A sample costs one
+// address and weight computation shared by the BC images and four 16-byte LDS
+// reads per plane.  The split of each ray's samples between slabs is fixed by
+// FP64 boundary crossings (consistent across slabs), and each slab's samples are
+// stepped in FP32 from an FP64 anchor taken relative to the lane's own cell, so
+// positions stay accurate to ~1e-6 pixel anywhere in the image.
+template <typename T, int BC>
+__global__ __launch_bounds__(256) void fwd_tiled(Geom g, FwdWork work, const T *__restrict__ x,
+                                                 T *__restrict__ y, int batch, float scale_dt,
+                                                 int tile_t) {
+    extern __shared__ uint4 lds[];
+    constexpr int CH = Chunk<T>::kImages;
+    constexpr int PLANES = BC / CH;
+    static_assert(BC % CH == 0, "BC must be a multiple of the images per chunk");
+    const int plane_chunks = (kSlabH + 3) * tile_t;
+
+    const FwdItem it = work.items[blockIdx.x];
+    const int b0 = blockIdx.y * BC;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const bool active = wave < it.na && lane < it.nd;
+    const int a = it.a0 + min(wave, it.na - 1), d = it.d0 + min(lane, it.nd - 1);
+    const int n = g.n;
+    const size_t img = (size_t)n * n;
+
+    // the lane's ray, oriented so that the march coordinate grows with the sample index
+    double4 r = ray_params(g, a, d);
+    const double sm_raw = it.axis ? r.z : r.w;
+    if (sm_raw < 0.0) { r.z = -r.z; r.w = -r.w; }
+    const double om = it.axis ? r.x : r.y;
+    const double inv_sm = 1.0 / fabs(sm_raw);
+    int jlo, jhi;
+    support_range(r, n, jlo, jhi);
+    const float stx = (float)r.z, sty = (float)r.w;
+    const int pitch = it.axis ? (kSlabH + 3) : tile_t;
+
+    float acc[BC];
+#pragma unroll
+    for (int i = 0; i < BC; ++i) acc[i] = 0.0f;
+
+    for (int si = 0; si < it.nslab; ++si) {
+        const int2 tr = work.ranges[it.range + si];
+        if (tr.x > tr.y) continue;                      // uniform over the block
+        const int m_lo = -1 + (it.slab0 + si) * kSlabH;
+        // tile element (0, 0) sits at image (ox0, oy0); tile is rows x cols pixels
+        const int ox0 = it.axis ? m_lo - 1 : tr.x;
+        const int oy0 = it.axis ? tr.x : m_lo - 1;
+        const int cols = it.axis ? kSlabH + 3 : tr.y - tr.x + 1;
+        const int rows = it.axis ? tr.y - tr.x + 1 : kSlabH + 3;
+
+        __syncthreads();                                // previous slab fully consumed
+        const int per_plane = rows * cols;
+        for (int c = threadIdx.x; c < PLANES * per_plane; c += 256) {
+            const int q = c / per_plane;
+            const int rem = c - q * per_plane;
+            const int i = rem / cols, jj = rem - i * cols;
+            const int gx = ox0 + jj, gy = oy0 + i;
+            const bool inside = (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n;
+            const size_t off = inside ? (size_t)gy * n + gx : 0;
+            T v[CH];
+#pragma unroll
+            for (int e = 0; e < CH; ++e) {
+                const T *src = x + (size_t)min(b0 + q * CH + e, batch - 1) * img;
+                v[e] = inside ? src[off] : Chunk<T>::zero();
+            }
+            lds[q * plane_chunks + i * pitch + jj] = Chunk<T>::pack(v);
+        }
+        __syncthreads();
+
+        // samples of this ray whose march coordinate lies in [m_lo, m_lo + kSlabH)
+        const int jb = max(jlo, (int)ceil(((double)m_lo - om) * inv_sm));
+        const int je = min(jhi + 1, (int)ceil(((double)(m_lo + kSlabH) - om) * inv_sm));
+        if (jb >= je) continue;
+        const double px64 = fma((double)jb, r.z, r.x) - (double)ox0;
+        const double py64 = fma((double)jb, r.w, r.y) - (double)oy0;
+        const double bx = floor(px64), by = floor(py64);
+        const float fxa = (float)(px64 - bx), fya = (float)(py64 - by);
+        const int base = (int)by * pitch + (int)bx;
+        const int max_addr = max((rows - 2) * pitch + (cols - 2), 0);
+        for (int j = 0; j < je - jb; ++j) {
+            const float jf = (float)j;
+            const float px = fmaf(jf, stx, fxa), py = fmaf(jf, sty, fya);
+            const float cx = floorf(px), cy = floorf(py);
+            const float fx = px - cx, fy = py - cy;
+            const float gx = 1.0f - fx, gy = 1.0f - fy;
+            const float w00 = __fmul_rn(gx, gy), w01 = __fmul_rn(fx, gy);
+            const float w10 = __fmul_rn(gx, fy), w11 = __fmul_rn(fx, fy);
+            int addr = base + (int)cy * pitch + (int)cx;
+            addr = min(max(addr, 0), max_addr);         // memory safety; real samples are inside
+#pragma unroll
+            for (int q = 0; q < PLANES; ++q) {
+                const uint4 *pl = lds + q * plane_chunks + addr;
+                const uint4 t00 = pl[0], t01 = pl[1], t10 = pl[pitch], t11 = pl[pitch + 1];
+                float *aq = acc + q * CH;
+                Chunk<T>::fma(w00, t00, aq);
+                Chunk<T>::fma(w01, t01, aq);
+                Chunk<T>::fma(w10, t10, aq);
+                Chunk<T>::fma(w11, t11, aq);
+            }
+        }
+    }
+    if (!active) return;
+#pragma unroll
+    for (int i = 0; i < BC; ++i)
+        if (b0 + i < batch)
+            Store<T>::store(y + ((size_t)(b0 + i) * g.n_angles + a) * g.det_count + d,
+                            acc[i] * scale_dt);
+}
+
 template <typename T, int BC>
 static hipError_t launch_fwd_direct(const Geom &g, const void *x, void *y, int batch,
                                     float scale_dt, hipStream_t s) {
@@ -75,10 +188,28 @@ static hipError_t launch_fwd_direct(const Geom &g, const void *x, void *y, int b
     return hipGetLastError();
 }
 
-hipError_t launch_forward(const Geom &g, int dtype, const LaunchShape &shape, const void *x,
-                          void *y, int batch, float scale, hipStream_t s) {
+template <typename T, int BC>
+static hipError_t launch_fwd_tiled(const Geom &g, const FwdWork &work, const void *x, void *y,
+                                   int batch, float scale_dt, hipStream_t s) {
+    constexpr int PLANES = BC / Chunk<T>::kImages;
+    const size_t lds = (size_t)PLANES * (kSlabH + 3) * work.tile_t * sizeof(uint4);
+    dim3 grid(work.n_items, (batch + BC - 1) / BC);
+    hipLaunchKernelGGL((fwd_tiled<T, BC>), grid, dim3(256), lds, s, g, work, (const T *)x, (T *)y,
+                       batch, scale_dt, work.tile_t);
+    return hipGetLastError();
+}
+
+hipError_t launch_forward(const Geom &g, const FwdWork &work, int dtype, const LaunchShape &shape,
+                          const void *x, void *y, int batch, float scale, hipStream_t s) {
     const float scale_dt = (float)(scale * g.step);
-    (void)shape;
+    if (shape.variant == VARIANT_TILED && work.n_items > 0) {
+        switch (dtype) {
+        case F32: return launch_fwd_tiled<float, 8>(g, work, x, y, batch, scale_dt, s);
+        case F16: return launch_fwd_tiled<__half, 8>(g, work, x, y, batch, scale_dt, s);
+        case BF16: return launch_fwd_tiled<bf16_t, 8>(g, work, x, y, batch, scale_dt, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
     switch (dtype) {
     case F32: return launch_fwd_direct<float, 4>(g, x, y, batch, scale_dt, s);
     case F16: return launch_fwd_direct<__half, 4>(g, x, y, batch, scale_dt, s);

@@ -3,20 +3,58 @@
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "radon_common.hpp"
 
 namespace radon {
 
+// Kernel families.
+enum Variant { VARIANT_DIRECT = 0, VARIANT_TILED = 1 };
+
 // Launch shape of one direction, chosen per plan (fixed default or autotuned).
 struct LaunchShape {
-    int variant = 0;      // kernel family (0 = direct)
-    int images = 4;       // images per thread
-    int angles = 1;       // angles per block
-    int rays = 256;       // rays (forward) or pixels (backprojection) per block
+    int variant = VARIANT_DIRECT;
+    int images = 4;       // images per thread (accumulators per lane)
+    int angles = 1;       // angles per block (forward: waves; backprojection: LDS angle block)
+    int rays = 256;       // forward: bins per block; backprojection: pixels per block
 };
 
-hipError_t launch_forward(const Geom &g, int dtype, const LaunchShape &shape, const void *x,
-                          void *y, int batch, float scale, hipStream_t s);
+// ------------------------------------------------------------------ tiled forward work
+// One work item of the tiled forward projector: up to 4 angles (one wave each) x up
+// to 64 consecutive bins (one lane each), marched through the image in slabs of
+// kSlabH pixel rows (axis 0) or columns (axis 1).  For every slab the item stages
+// into LDS the pixel rows/columns [m_lo-1, m_lo+kSlabH+1] along the march axis and
+// the transverse index range ranges[range + s - slab0] (inclusive, clamped to
+// [-2, N+1]), where m_lo = -1 + s*kSlabH.
+struct FwdItem {
+    int a0, na;
+    int d0, nd;
+    int axis;
+    int slab0, nslab;
+    int range;
+};
+
+constexpr int kSlabH = 8;          // pixel rows (columns) per slab
+constexpr int kFwdWaves = 4;       // angles per forward item
+constexpr int kFwdLanes = 64;      // bins per forward item
+constexpr int kTileTMax = 192;     // largest transverse extent of a staged slab
+
+struct FwdWork {
+    const FwdItem *items = nullptr;   // device
+    const int2 *ranges = nullptr;     // device
+    int n_items = 0;
+    int tile_t = 0;                   // transverse extent to allocate (odd, <= kTileTMax+1)
+};
+
+// Host planning of the tiled forward projector from FP64 ray parameters
+// (rays[a*D+d] = (ox, oy, sx, sy) in index coordinates).  Returns false when some
+// block of rays does not fit the tiled kernel; the direct kernel is used then.
+bool plan_forward_tiles(int n, int n_angles, int det_count, const std::vector<double4> &rays,
+                        std::vector<FwdItem> &items, std::vector<int2> &ranges, int &tile_t);
+
+hipError_t launch_forward(const Geom &g, const FwdWork &work, int dtype, const LaunchShape &shape,
+                          const void *x, void *y, int batch, float scale, hipStream_t s);
 hipError_t launch_backproject(const Geom &g, int dtype, const LaunchShape &shape,
                               const void *y, void *x, int batch, float scale, hipStream_t s);
 hipError_t launch_dot_f64(const void *a, const void *b, long long n, int dtype, double *out,

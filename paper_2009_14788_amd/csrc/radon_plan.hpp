@@ -30,6 +30,9 @@ struct Plan {
     Geom geom{};
     double2 *trig = nullptr;  // device [A]
     double4 *rays = nullptr;  // device [A*D], fan beam only
+    FwdItem *fwd_items = nullptr;  // device, tiled forward work items
+    int2 *fwd_ranges = nullptr;    // device, per item and slab transverse ranges
+    FwdWork fwd_work;
     LaunchShape fwd_shape, bp_shape;
     Plan() = default;
     Plan(const Plan &) = delete;

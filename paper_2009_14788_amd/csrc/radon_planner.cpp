@@ -1,0 +1,115 @@
+// Host planning of the tiled forward projector (FP64, once per geometry).
+//
+// The rays of a work item (up to 4 angles x 64 bins) march through the image in
+// slabs of kSlabH pixel rows (or columns, whichever axis the rays are closer to).
+// For each slab the planner computes the transverse pixel range every ray of the
+// item can touch there, so the kernel stages exactly that window into LDS.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "radon_launch.hpp"
+
+namespace radon {
+
+namespace {
+
+struct Span {
+    int lo, hi;
+};
+
+// Transverse tap range [lo, hi] of one ray over march coordinates [m0, m1], with a
+// one-pixel margin on each side for FP32 rounding in the kernel.
+Span ray_span(const double4 &r, int axis, double m0, double m1) {
+    const double om = axis ? r.x : r.y, ot = axis ? r.y : r.x;
+    const double sm = axis ? r.z : r.w, st = axis ? r.w : r.z;
+    const double t0 = ot + (m0 - om) * (st / sm);
+    const double t1 = ot + (m1 - om) * (st / sm);
+    const double lo = std::min(t0, t1), hi = std::max(t0, t1);
+    return {(int)std::floor(lo) - 1, (int)std::floor(hi) + 2};
+}
+
+bool plan_item(int n, int det_count, const std::vector<double4> &rays, int a0, int na, int d0,
+               int nd, std::vector<FwdItem> &items, std::vector<int2> &ranges, int &tile_t) {
+    const double4 &mid = rays[(size_t)(a0 + na / 2) * det_count + d0 + nd / 2];
+    const int axis = std::fabs(mid.w) >= std::fabs(mid.z) ? 0 : 1;
+    // every ray must advance along the march axis by at least half a step per sample
+    for (int a = a0; a < a0 + na; ++a)
+        for (int d = d0; d < d0 + nd; ++d) {
+            const double4 &r = rays[(size_t)a * det_count + d];
+            const double sm = axis ? r.z : r.w;
+            if (std::fabs(sm) < 0.5 * std::hypot(r.z, r.w)) return false;
+        }
+    const int nslabs = (n + 1 + kSlabH - 1) / kSlabH;
+    std::vector<int2> local(nslabs);
+    int first = -1, last = -1, width = 0;
+    for (int s = 0; s < nslabs; ++s) {
+        const double m_lo = -1.0 + (double)s * kSlabH;
+        int lo = 1 << 30, hi = -(1 << 30);
+        for (int a = a0; a < a0 + na; ++a)
+            for (int d : {d0, d0 + nd - 1}) {
+                const Span sp = ray_span(rays[(size_t)a * det_count + d], axis, m_lo, m_lo + kSlabH);
+                lo = std::min(lo, sp.lo);
+                hi = std::max(hi, sp.hi);
+            }
+        // taps of samples inside the support lie in [-1, N]; one more zero pixel on
+        // each side absorbs FP32 rounding of boundary samples
+        lo = std::max(lo, -2);
+        hi = std::min(hi, n + 1);
+        if (lo == hi) lo = hi - 1;          // keep every staged window at least 2 wide
+        local[s] = make_int2(lo, hi);
+        if (lo <= hi) {
+            if (first < 0) first = s;
+            last = s;
+            width = std::max(width, hi - lo + 1);
+        }
+    }
+    if (width > kTileTMax) return false;
+    if (first < 0) first = 0, last = -1;   // the rays miss the image: the item writes zeros
+    FwdItem it;
+    it.a0 = a0;
+    it.na = na;
+    it.d0 = d0;
+    it.nd = nd;
+    it.axis = axis;
+    it.slab0 = first;
+    it.nslab = last - first + 1;
+    it.range = (int)ranges.size();
+    for (int s = first; s <= last; ++s) ranges.push_back(local[s]);
+    items.push_back(it);
+    tile_t = std::max(tile_t, width);
+    return true;
+}
+
+}  // namespace
+
+bool plan_forward_tiles(int n, int n_angles, int det_count, const std::vector<double4> &rays,
+                        std::vector<FwdItem> &items, std::vector<int2> &ranges, int &tile_t) {
+    items.clear();
+    ranges.clear();
+    tile_t = 0;
+    for (int a0 = 0; a0 < n_angles; a0 += kFwdWaves) {
+        const int na = std::min(kFwdWaves, n_angles - a0);
+        for (int d0 = 0; d0 < det_count; d0 += kFwdLanes) {
+            const int nd = std::min(kFwdLanes, det_count - d0);
+            if (plan_item(n, det_count, rays, a0, na, d0, nd, items, ranges, tile_t)) continue;
+            // split: one angle per item, then fewer bins per item
+            for (int a = a0; a < a0 + na; ++a) {
+                int step = nd;
+                for (int d = d0; d < d0 + nd;) {
+                    const int cnt = std::min(step, d0 + nd - d);
+                    if (plan_item(n, det_count, rays, a, 1, d, cnt, items, ranges, tile_t)) {
+                        d += cnt;
+                    } else if (step > 8) {
+                        step /= 2;
+                    } else {
+                        return false;
+                    }
+                }
+            }
+        }
+    }
+    return true;
+}
+
+}  // namespace radon
