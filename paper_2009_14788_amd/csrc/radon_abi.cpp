@@ -188,6 +188,16 @@ static int build_plan(const radon_geometry_t *g, int device, std::unique_ptr<Pla
         p->fwd_shape.angles = kFwdWaves;
         p->fwd_shape.rays = kFwdLanes;
     }
+    // tiled backprojection
+    if (!want_direct) {
+        p->bp_work.window = plan_backproject_window(g->beam, trig, g->det_spacing, g->step);
+        if (p->bp_work.window > 0) {
+            p->bp_shape.variant = VARIANT_TILED;
+            p->bp_shape.images = 32;
+            p->bp_shape.angles = kBpAngles;
+            p->bp_shape.rays = kBpTile * kBpTile;
+        }
+    }
     Geom &G = p->geom;
     G.n = g->image_size;
     G.n_angles = g->n_angles;
@@ -301,7 +311,7 @@ int radon_backproject(const radon_geometry_t *geometry, const void *y, void *x, 
     hipStream_t s = static_cast<hipStream_t>(stream);
     Plan *p = nullptr;
     if ((rc = get_plan(geometry, s, &p)) != RADON_OK) return rc;
-    hipError_t e = launch_backproject(p->geom, dtype, p->bp_shape, y, x, batch, scale, s);
+    hipError_t e = launch_backproject(p->geom, p->bp_work, dtype, p->bp_shape, y, x, batch, scale, s);
     return e == hipSuccess ? RADON_OK : RADON_ERR_HIP;
 }
 

@@ -95,6 +95,114 @@ __global__ __launch_bounds__(256) void bp_direct(Geom g, const T *__restrict__ y
     }
 }
 
+// ------------------------------------------------------------------ tiled variant
+// Parallel beam.  One block = a 16x16 pixel tile (lane <-> pixel) x BC images.
+// Angles are processed in blocks of kBpAngles: for each, the block stages into LDS
+// the window of W bins its tile can touch, as 16-byte chunks of Chunk<T>::kImages
+// images ("planes").  Each pixel then finds, per angle, the lattice samples
+// (bin d, step k) whose bilinear footprint covers it: the pixel's continuous
+// lattice coordinates (u*, v*) are formed in FP64, the NB x NK candidates
+// d = floor(u* - hu) + 1 + i, k = floor(v* - hv) + 1 + j cover every sample within
+// the footprint, and their offsets from the pixel are small FP32 numbers, so the
+// tent weights are accurate to FP32 rounding.  The NB bin weights are then applied
+// to BC images with 16-byte LDS reads.  No atomics.
+template <typename T, int BC, int NB, int NK>
+__global__ __launch_bounds__(256) void bp_tiled_par(Geom g, const T *__restrict__ y,
+                                                    T *__restrict__ x, int batch, float scale_dt,
+                                                    int W) {
+    extern __shared__ uint4 lds[];
+    __shared__ int wlo_s[kBpAngles];
+    constexpr int CH = Chunk<T>::kImages;
+    constexpr int PLANES = BC / CH;
+    static_assert(BC % CH == 0, "BC must be a multiple of the images per chunk");
+    const int n = g.n, A = g.n_angles, D = g.det_count;
+    const int tiles_x = (n + kBpTile - 1) / kBpTile;
+    const int tx0 = (blockIdx.x % tiles_x) * kBpTile, ty0 = (blockIdx.x / tiles_x) * kBpTile;
+    const int c = tx0 + (threadIdx.x % kBpTile), r = ty0 + (threadIdx.x / kBpTile);
+    const int b0 = blockIdx.y * BC;
+    const double qx = (double)c - g.cn, qy = (double)r - g.cn;
+    const double tcx = tx0 + 0.5 * (kBpTile - 1) - g.cn, tcy = ty0 + 0.5 * (kBpTile - 1) - g.cn;
+    const size_t sino = (size_t)A * D;
+    const int per_plane = kBpAngles * W;
+    const float dt = (float)g.step, sp = (float)g.spacing;
+
+    float acc[BC];
+#pragma unroll
+    for (int i = 0; i < BC; ++i) acc[i] = 0.0f;
+
+    for (int a0 = 0; a0 < A; a0 += kBpAngles) {
+        const int na = min(kBpAngles, A - a0);
+        __syncthreads();                                // previous block consumed
+        if (threadIdx.x < na) {
+            const double2 cs = g.trig[a0 + threadIdx.x];
+            const double h = fabs(cs.x) + fabs(cs.y);
+            const double uc = fma(fma(tcx, cs.x, tcy * cs.y), g.inv_spacing, g.half_d);
+            wlo_s[threadIdx.x] = (int)floor(uc - (0.5 * (kBpTile - 1) + 1.0) * h * g.inv_spacing) - 1;
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < PLANES * na * W; idx += 256) {
+            const int q = idx / (na * W);
+            const int rem = idx - q * na * W;
+            const int al = rem / W, j = rem - al * W;
+            const int d = wlo_s[al] + j;
+            const bool inside = (unsigned)d < (unsigned)D;
+            const size_t off = (size_t)(a0 + al) * D + (inside ? d : 0);
+            T v[CH];
+#pragma unroll
+            for (int e = 0; e < CH; ++e) {
+                const T *src = y + (size_t)min(b0 + q * CH + e, batch - 1) * sino;
+                v[e] = inside ? src[off] : Chunk<T>::zero();
+            }
+            lds[q * per_plane + al * W + j] = Chunk<T>::pack(v);
+        }
+        __syncthreads();
+
+        for (int al = 0; al < na; ++al) {
+            const double2 cs = g.trig[a0 + al];
+            const double h = fabs(cs.x) + fabs(cs.y);
+            // continuous bin (u) and step (v) coordinates of the pixel centre
+            const double u = fma(fma(qx, cs.x, qy * cs.y), g.inv_spacing, g.half_d);
+            const double v = fma(qy, cs.x, -qx * cs.y) * g.inv_step;
+            const double db = floor(u - h * g.inv_spacing), kb = floor(v - h * g.inv_step);
+            // offset of candidate (d = db+1+i, k = kb+1+j) from the pixel, along u and v
+            const float e0 = (float)(db + 1.0 - u) * sp, t0 = (float)(kb + 1.0 - v) * dt;
+            const float cf = (float)cs.x, sf = (float)cs.y;
+            const float ux = sp * cf, uy = sp * sf;      // one bin along u
+            const float vx = -dt * sf, vy = dt * cf;     // one step along v
+            float dx_i = fmaf(e0, cf, -t0 * sf), dy_i = fmaf(e0, sf, t0 * cf);
+            float wgt[NB];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                float dx = dx_i, dy = dy_i, w = 0.0f;
+#pragma unroll
+                for (int jj = 0; jj < NK; ++jj) {
+                    const float tx = __builtin_amdgcn_fmed3f(1.0f - fabsf(dx), 0.0f, 1.0f);
+                    const float ty = __builtin_amdgcn_fmed3f(1.0f - fabsf(dy), 0.0f, 1.0f);
+                    w = fmaf(tx, ty, w);
+                    dx += vx;
+                    dy += vy;
+                }
+                wgt[i] = w;
+                dx_i += ux;
+                dy_i += uy;
+            }
+            int lb = (int)db + 1 - wlo_s[al];
+            lb = min(max(lb, 0), W - NB);               // memory safety; real pixels are inside
+            const uint4 *row = lds + al * W + lb;
+#pragma unroll
+            for (int qq = 0; qq < PLANES; ++qq) {
+#pragma unroll
+                for (int i = 0; i < NB; ++i) Chunk<T>::fma(wgt[i], row[qq * per_plane + i], acc + qq * CH);
+            }
+        }
+    }
+    if (c >= n || r >= n) return;
+#pragma unroll
+    for (int i = 0; i < BC; ++i)
+        if (b0 + i < batch)
+            Store<T>::store(x + (size_t)(b0 + i) * n * n + (size_t)r * n + c, acc[i] * scale_dt);
+}
+
 template <typename T, int BC>
 static hipError_t launch_bp_direct(const Geom &g, const void *y, void *x, int batch, float scale,
                                    hipStream_t s) {
@@ -105,11 +213,30 @@ static hipError_t launch_bp_direct(const Geom &g, const void *y, void *x, int ba
     return hipGetLastError();
 }
 
-hipError_t launch_backproject(const Geom &g, int dtype, const LaunchShape &shape, const void *y,
-                              void *x, int batch, float scale, hipStream_t s) {
-    (void)shape;
+template <typename T, int BC>
+static hipError_t launch_bp_tiled(const Geom &g, const BpWork &work, const void *y, void *x,
+                                  int batch, float scale_dt, hipStream_t s) {
+    constexpr int PLANES = BC / Chunk<T>::kImages;
+    const size_t lds = (size_t)PLANES * kBpAngles * work.window * sizeof(uint4);
+    const int tiles = ((g.n + kBpTile - 1) / kBpTile) * ((g.n + kBpTile - 1) / kBpTile);
+    dim3 grid(tiles, (batch + BC - 1) / BC);
+    hipLaunchKernelGGL((bp_tiled_par<T, BC, 3, 3>), grid, dim3(256), lds, s, g, (const T *)y,
+                       (T *)x, batch, scale_dt, work.window);
+    return hipGetLastError();
+}
+
+hipError_t launch_backproject(const Geom &g, const BpWork &work, int dtype, const LaunchShape &shape,
+                              const void *y, void *x, int batch, float scale, hipStream_t s) {
     // every matrix entry carries the step length: R = step * (sum of sample weights)
     const float scale_dt = (float)(scale * g.step);
+    if (shape.variant == VARIANT_TILED && work.window > 0) {
+        switch (dtype) {
+        case F32: return launch_bp_tiled<float, 32>(g, work, y, x, batch, scale_dt, s);
+        case F16: return launch_bp_tiled<__half, 32>(g, work, y, x, batch, scale_dt, s);
+        case BF16: return launch_bp_tiled<bf16_t, 32>(g, work, y, x, batch, scale_dt, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
     switch (dtype) {
     case F32: return launch_bp_direct<float, 4>(g, y, x, batch, scale_dt, s);
     case F16: return launch_bp_direct<__half, 4>(g, y, x, batch, scale_dt, s);

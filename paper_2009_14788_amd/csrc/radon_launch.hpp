@@ -55,7 +55,20 @@ bool plan_forward_tiles(int n, int n_angles, int det_count, const std::vector<do
 
 hipError_t launch_forward(const Geom &g, const FwdWork &work, int dtype, const LaunchShape &shape,
                           const void *x, void *y, int batch, float scale, hipStream_t s);
-hipError_t launch_backproject(const Geom &g, int dtype, const LaunchShape &shape,
+// ------------------------------------------------------------------ tiled backprojection
+constexpr int kBpTile = 16;        // pixels per tile side (one lane per pixel)
+constexpr int kBpAngles = 8;       // angles per LDS block
+
+struct BpWork {
+    int window = 0;                // bins staged per (tile, angle); 0 = use the direct kernel
+};
+
+// Window of bins a 16x16 tile can touch at any angle of a parallel-beam geometry
+// with 3 x 3 candidate samples per pixel (bin spacing and step length 1 or more
+// coarse than sqrt(2)-covering); 0 when the tiled kernel does not apply.
+int plan_backproject_window(int beam, const std::vector<double2> &trig, double spacing, double step);
+
+hipError_t launch_backproject(const Geom &g, const BpWork &work, int dtype, const LaunchShape &shape,
                               const void *y, void *x, int batch, float scale, hipStream_t s);
 hipError_t launch_dot_f64(const void *a, const void *b, long long n, int dtype, double *out,
                           double *partials, int n_partials, hipStream_t s);

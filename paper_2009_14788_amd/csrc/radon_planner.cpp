@@ -112,4 +112,15 @@ bool plan_forward_tiles(int n, int n_angles, int det_count, const std::vector<do
     return true;
 }
 
+int plan_backproject_window(int beam, const std::vector<double2> &trig, double spacing, double step) {
+    if (beam != 0) return 0;
+    double hmax = 0.0;
+    for (const double2 &cs : trig) hmax = std::max(hmax, std::fabs(cs.x) + std::fabs(cs.y));
+    // 3 candidate bins and 3 candidate steps must cover the footprint (width 2*hmax)
+    if (2.0 * hmax / spacing > 3.0 || 2.0 * hmax / step > 3.0) return 0;
+    const int nb = 3;
+    const int w = (int)std::floor((kBpTile - 1) * hmax / spacing) + nb + 3;
+    return (w + 3) & ~3;
+}
+
 }  // namespace radon
