@@ -23,7 +23,8 @@ int validate(const radon_geometry_t *g) {
     if (g->beam != RADON_PARALLEL && g->beam != RADON_FANBEAM) return RADON_ERR_INVALID_ARG;
     if (g->image_size < 1 || g->n_angles < 1 || g->det_count < 1) return RADON_ERR_INVALID_ARG;
     // sizes whose index arithmetic would leave 32-bit float/int exactness
-    if (g->image_size > 16384 || g->det_count > (1 << 20) || g->n_angles > (1 << 20))
+    if (g->image_size > 16384 || g->det_count > (1 << 20) || g->n_angles > (1 << 20) ||
+        (int64_t)g->n_angles * g->det_count > INT32_MAX)
         return RADON_ERR_UNSUPPORTED;
     if (!g->angles) return RADON_ERR_INVALID_ARG;
     for (int a = 0; a < g->n_angles; ++a)
@@ -184,7 +185,8 @@ static int build_plan(const radon_geometry_t *g, int device, std::unique_ptr<Pla
         p->fwd_work.n_items = (int)items.size();
         p->fwd_work.tile_t = tile_t | 1;
         p->fwd_shape.variant = VARIANT_TILED;
-        p->fwd_shape.images = 8;
+        const char *imgs = std::getenv("RADON_FWD_IMAGES");
+        p->fwd_shape.images = (imgs && std::atoi(imgs) >= 16) ? 16 : 8;
         p->fwd_shape.angles = kFwdWaves;
         p->fwd_shape.rays = kFwdLanes;
     }

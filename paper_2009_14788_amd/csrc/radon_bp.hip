@@ -124,6 +124,9 @@ __global__ __launch_bounds__(256) void bp_tiled_par(Geom g, const T *__restrict_
     const double tcx = tx0 + 0.5 * (kBpTile - 1) - g.cn, tcy = ty0 + 0.5 * (kBpTile - 1) - g.cn;
     const size_t sino = (size_t)A * D;
     const int per_plane = kBpAngles * W;
+    const T *img_base[BC];
+#pragma unroll
+    for (int e = 0; e < BC; ++e) img_base[e] = y + (size_t)min(b0 + e, batch - 1) * sino;
     const float dt = (float)g.step, sp = (float)g.spacing;
 
     float acc[BC];
@@ -140,23 +143,29 @@ __global__ __launch_bounds__(256) void bp_tiled_par(Geom g, const T *__restrict_
             wlo_s[threadIdx.x] = (int)floor(uc - (0.5 * (kBpTile - 1) + 1.0) * h * g.inv_spacing) - 1;
         }
         __syncthreads();
-        for (int idx = threadIdx.x; idx < PLANES * na * W; idx += 256) {
-            const int q = idx / (na * W);
-            const int rem = idx - q * na * W;
-            const int al = rem / W, j = rem - al * W;
+        for (int p = threadIdx.x; p < na * W; p += 256) {
+            const int al = p / W, j = p - al * W;
             const int d = wlo_s[al] + j;
             const bool inside = (unsigned)d < (unsigned)D;
-            const size_t off = (size_t)(a0 + al) * D + (inside ? d : 0);
-            T v[CH];
+            const unsigned off = (unsigned)((a0 + al) * D + (inside ? d : 0));
 #pragma unroll
-            for (int e = 0; e < CH; ++e) {
-                const T *src = y + (size_t)min(b0 + q * CH + e, batch - 1) * sino;
-                v[e] = inside ? src[off] : Chunk<T>::zero();
+            for (int q = 0; q < PLANES; ++q) {
+                T v[CH];
+#pragma unroll
+                for (int e = 0; e < CH; ++e) {
+                    const T val = img_base[q * CH + e][off];   // always a valid address
+                    v[e] = inside ? val : Chunk<T>::zero();
+                }
+                lds[q * per_plane + al * W + j] = Chunk<T>::pack(v);
             }
-            lds[q * per_plane + al * W + j] = Chunk<T>::pack(v);
         }
         __syncthreads();
 
+        // the angle block's contributions are summed separately, then added to the
+        // pixel total (two-level summation keeps FP32 rounding small)
+        float part[BC];
+#pragma unroll
+        for (int i = 0; i < BC; ++i) part[i] = 0.0f;
         for (int al = 0; al < na; ++al) {
             const double2 cs = g.trig[a0 + al];
             const double h = fabs(cs.x) + fabs(cs.y);
@@ -192,9 +201,11 @@ __global__ __launch_bounds__(256) void bp_tiled_par(Geom g, const T *__restrict_
 #pragma unroll
             for (int qq = 0; qq < PLANES; ++qq) {
 #pragma unroll
-                for (int i = 0; i < NB; ++i) Chunk<T>::fma(wgt[i], row[qq * per_plane + i], acc + qq * CH);
+                for (int i = 0; i < NB; ++i) Chunk<T>::fma(wgt[i], row[qq * per_plane + i], part + qq * CH);
             }
         }
+#pragma unroll
+        for (int i = 0; i < BC; ++i) acc[i] += part[i];
     }
     if (c >= n || r >= n) return;
 #pragma unroll

@@ -66,6 +66,42 @@ __global__ __launch_bounds__(256) void fwd_direct(Geom g, const T *__restrict__ 
 }
 
 // ------------------------------------------------------------------ tiled variant
+// Stage a rows x cols pixel window whose element (0, 0) is image pixel (ox0, oy0)
+// into LDS as PLANES planes of 16-byte chunks (Chunk<T>::kImages images per chunk,
+// zero outside the image).  Image base pointers are uniform per plane and image,
+// so loads use 32-bit pixel offsets; the (row, col) walk is incremental.
+template <typename T, int PLANES>
+__device__ __forceinline__ void stage_window(uint4 *lds, int plane_chunks, int pitch,
+                                             const T *const *img_base, int n, int ox0, int oy0,
+                                             int rows, int cols) {
+    constexpr int CH = Chunk<T>::kImages;
+    const int total = rows * cols;
+    const int step_i = 256 / cols, step_j = 256 - step_i * cols;
+    int i0 = threadIdx.x / cols, j0 = threadIdx.x - (threadIdx.x / cols) * cols;
+#pragma unroll
+    for (int q = 0; q < PLANES; ++q) {
+        int i = i0, jj = j0;
+        for (int idx = threadIdx.x; idx < total; idx += 256) {
+            const int gx = ox0 + jj, gy = oy0 + i;
+            const bool inside = (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n;
+            const unsigned off = inside ? (unsigned)(gy * n + gx) : 0u;
+            T v[CH];
+#pragma unroll
+            for (int e = 0; e < CH; ++e) {
+                const T val = img_base[q * CH + e][off];     // always a valid address
+                v[e] = inside ? val : Chunk<T>::zero();
+            }
+            lds[q * plane_chunks + i * pitch + jj] = Chunk<T>::pack(v);
+            jj += step_j;
+            i += step_i;
+            if (jj >= cols) {
+                jj -= cols;
+                ++i;
+            }
+        }
+    }
+}
+
 // One block = one work item (up to 4 angles x 64 bins; wave w <-> angle a0+w, lane
 // l <-> bin d0+l) x BC images.  The rays march through the image in slabs of
 // kSlabH rows (or columns); per slab the block stages the slab's pixel window
@@ -73,9 +109,9 @@ __global__ __launch_bounds__(256) void fwd_direct(Geom g, const T *__restrict__ 
 // then every lane walks its ray's samples inside the slab.  A sample costs one
 // address and weight computation shared by the BC images and four 16-byte LDS
 // reads per plane.  The split of each ray's samples between slabs is fixed by
-// FP64 boundary crossings (consistent across slabs), and each slab's samples are
-// stepped in FP32 from an FP64 anchor taken relative to the lane's own cell, so
-// positions stay accurate to ~1e-6 pixel anywhere in the image.
+// FP64 boundary crossings (consistent across slabs); sample positions are FP64
+// offsets from the lane's first cell in the slab and only the bilinear fractions
+// drop to FP32, so weights are accurate to FP32 rounding anywhere in the image.
 template <typename T, int BC>
 __global__ __launch_bounds__(256) void fwd_tiled(Geom g, FwdWork work, const T *__restrict__ x,
                                                  T *__restrict__ y, int batch, float scale_dt,
@@ -93,6 +129,9 @@ __global__ __launch_bounds__(256) void fwd_tiled(Geom g, FwdWork work, const T *
     const int a = it.a0 + min(wave, it.na - 1), d = it.d0 + min(lane, it.nd - 1);
     const int n = g.n;
     const size_t img = (size_t)n * n;
+    const T *img_base[BC];
+#pragma unroll
+    for (int e = 0; e < BC; ++e) img_base[e] = x + (size_t)min(b0 + e, batch - 1) * img;
 
     // the lane's ray, oriented so that the march coordinate grows with the sample index
     double4 r = ray_params(g, a, d);
@@ -102,7 +141,6 @@ __global__ __launch_bounds__(256) void fwd_tiled(Geom g, FwdWork work, const T *
     const double inv_sm = 1.0 / fabs(sm_raw);
     int jlo, jhi;
     support_range(r, n, jlo, jhi);
-    const float stx = (float)r.z, sty = (float)r.w;
     const int pitch = it.axis ? (kSlabH + 3) : tile_t;
 
     float acc[BC];
@@ -120,22 +158,7 @@ __global__ __launch_bounds__(256) void fwd_tiled(Geom g, FwdWork work, const T *
         const int rows = it.axis ? tr.y - tr.x + 1 : kSlabH + 3;
 
         __syncthreads();                                // previous slab fully consumed
-        const int per_plane = rows * cols;
-        for (int c = threadIdx.x; c < PLANES * per_plane; c += 256) {
-            const int q = c / per_plane;
-            const int rem = c - q * per_plane;
-            const int i = rem / cols, jj = rem - i * cols;
-            const int gx = ox0 + jj, gy = oy0 + i;
-            const bool inside = (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n;
-            const size_t off = inside ? (size_t)gy * n + gx : 0;
-            T v[CH];
-#pragma unroll
-            for (int e = 0; e < CH; ++e) {
-                const T *src = x + (size_t)min(b0 + q * CH + e, batch - 1) * img;
-                v[e] = inside ? src[off] : Chunk<T>::zero();
-            }
-            lds[q * plane_chunks + i * pitch + jj] = Chunk<T>::pack(v);
-        }
+        stage_window<T, PLANES>(lds, plane_chunks, pitch, img_base, n, ox0, oy0, rows, cols);
         __syncthreads();
 
         // samples of this ray whose march coordinate lies in [m_lo, m_lo + kSlabH)
@@ -145,30 +168,37 @@ __global__ __launch_bounds__(256) void fwd_tiled(Geom g, FwdWork work, const T *
         const double px64 = fma((double)jb, r.z, r.x) - (double)ox0;
         const double py64 = fma((double)jb, r.w, r.y) - (double)oy0;
         const double bx = floor(px64), by = floor(py64);
-        const float fxa = (float)(px64 - bx), fya = (float)(py64 - by);
+        const double fxa = px64 - bx, fya = py64 - by;
         const int base = (int)by * pitch + (int)bx;
         const int max_addr = max((rows - 2) * pitch + (cols - 2), 0);
-        for (int j = 0; j < je - jb; ++j) {
-            const float jf = (float)j;
-            const float px = fmaf(jf, stx, fxa), py = fmaf(jf, sty, fya);
-            const float cx = floorf(px), cy = floorf(py);
-            const float fx = px - cx, fy = py - cy;
+        // the slab's samples are summed separately and then added to the ray total
+        // (two-level summation keeps FP32 rounding of long rays small)
+        float part[BC];
+#pragma unroll
+        for (int i = 0; i < BC; ++i) part[i] = 0.0f;
+        double jd = 0.0;
+        for (int j = jb; j < je; ++j, jd += 1.0) {
+            const double px = fma(jd, r.z, fxa), py = fma(jd, r.w, fya);
+            const double cx = floor(px), cy = floor(py);
+            const float fx = (float)(px - cx), fy = (float)(py - cy);
             const float gx = 1.0f - fx, gy = 1.0f - fy;
             const float w00 = __fmul_rn(gx, gy), w01 = __fmul_rn(fx, gy);
             const float w10 = __fmul_rn(gx, fy), w11 = __fmul_rn(fx, fy);
-            int addr = base + (int)cy * pitch + (int)cx;
+            int addr = base + __mul24((int)cy, pitch) + (int)cx;
             addr = min(max(addr, 0), max_addr);         // memory safety; real samples are inside
 #pragma unroll
             for (int q = 0; q < PLANES; ++q) {
                 const uint4 *pl = lds + q * plane_chunks + addr;
                 const uint4 t00 = pl[0], t01 = pl[1], t10 = pl[pitch], t11 = pl[pitch + 1];
-                float *aq = acc + q * CH;
+                float *aq = part + q * CH;
                 Chunk<T>::fma(w00, t00, aq);
                 Chunk<T>::fma(w01, t01, aq);
                 Chunk<T>::fma(w10, t10, aq);
                 Chunk<T>::fma(w11, t11, aq);
             }
         }
+#pragma unroll
+        for (int i = 0; i < BC; ++i) acc[i] += part[i];
     }
     if (!active) return;
 #pragma unroll
@@ -203,10 +233,17 @@ hipError_t launch_forward(const Geom &g, const FwdWork &work, int dtype, const L
                           const void *x, void *y, int batch, float scale, hipStream_t s) {
     const float scale_dt = (float)(scale * g.step);
     if (shape.variant == VARIANT_TILED && work.n_items > 0) {
+        const bool wide = shape.images >= 16;
         switch (dtype) {
-        case F32: return launch_fwd_tiled<float, 8>(g, work, x, y, batch, scale_dt, s);
-        case F16: return launch_fwd_tiled<__half, 8>(g, work, x, y, batch, scale_dt, s);
-        case BF16: return launch_fwd_tiled<bf16_t, 8>(g, work, x, y, batch, scale_dt, s);
+        case F32:
+            return wide ? launch_fwd_tiled<float, 16>(g, work, x, y, batch, scale_dt, s)
+                        : launch_fwd_tiled<float, 8>(g, work, x, y, batch, scale_dt, s);
+        case F16:
+            return wide ? launch_fwd_tiled<__half, 16>(g, work, x, y, batch, scale_dt, s)
+                        : launch_fwd_tiled<__half, 8>(g, work, x, y, batch, scale_dt, s);
+        case BF16:
+            return wide ? launch_fwd_tiled<bf16_t, 16>(g, work, x, y, batch, scale_dt, s)
+                        : launch_fwd_tiled<bf16_t, 8>(g, work, x, y, batch, scale_dt, s);
         default: return hipErrorInvalidValue;
         }
     }
