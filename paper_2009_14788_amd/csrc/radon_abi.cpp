@@ -192,11 +192,12 @@ static int build_plan(const radon_geometry_t *g, int device, std::unique_ptr<Pla
     }
     // tiled backprojection
     if (!want_direct) {
-        p->bp_work.window = plan_backproject_window(g->beam, trig, g->det_spacing, g->step);
+        p->bp_work = plan_backproject(g->beam, g->image_size, trig, g->det_spacing, g->step,
+                                      g->source_distance, g->det_distance);
         if (p->bp_work.window > 0) {
             p->bp_shape.variant = VARIANT_TILED;
             p->bp_shape.images = 32;
-            p->bp_shape.angles = kBpAngles;
+            p->bp_shape.angles = g->beam == RADON_FANBEAM ? kBpAnglesFan : kBpAngles;
             p->bp_shape.rays = kBpTile * kBpTile;
         }
     }

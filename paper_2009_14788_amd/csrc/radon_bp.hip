@@ -214,6 +214,130 @@ __global__ __launch_bounds__(256) void bp_tiled_par(Geom g, const T *__restrict_
             Store<T>::store(x + (size_t)(b0 + i) * n * n + (size_t)r * n + c, acc[i] * scale_dt);
 }
 
+// Fan beam.  Same tiling as the parallel kernel; every bin has its own ray, so the
+// block also stages the rays (FP64 foot point and step) of its bin window.  Per
+// (pixel, angle) the candidate bins are those within the projected half-width of
+// the pixel's footprint around the projection of its centre (first-order bound
+// plus a margin far larger than the footprint's curvature); per bin, the NK
+// candidate samples around the pixel's position along that ray are evaluated with
+// FP64 anchors and FP32 offsets, exactly as in the parallel kernel.
+template <typename T, int BC, int NB, int NK>
+__global__ __launch_bounds__(256) void bp_tiled_fan(Geom g, const T *__restrict__ y,
+                                                    T *__restrict__ x, int batch, float scale_dt,
+                                                    int W) {
+    extern __shared__ uint4 lds[];
+    __shared__ int wlo_s[kBpAnglesFan];
+    constexpr int CH = Chunk<T>::kImages;
+    constexpr int PLANES = BC / CH;
+    static_assert(BC % CH == 0, "BC must be a multiple of the images per chunk");
+    const int n = g.n, A = g.n_angles, D = g.det_count;
+    const int tiles_x = (n + kBpTile - 1) / kBpTile;
+    const int tx0 = (blockIdx.x % tiles_x) * kBpTile, ty0 = (blockIdx.x / tiles_x) * kBpTile;
+    const int c = tx0 + (threadIdx.x % kBpTile), r = ty0 + (threadIdx.x / kBpTile);
+    const int b0 = blockIdx.y * BC;
+    const double qx = (double)c - g.cn, qy = (double)r - g.cn;
+    const size_t sino = (size_t)A * D;
+    const int per_plane = kBpAnglesFan * W;
+    double4 *rays_s = reinterpret_cast<double4 *>(lds + PLANES * per_plane);
+    const T *img_base[BC];
+#pragma unroll
+    for (int e = 0; e < BC; ++e) img_base[e] = y + (size_t)min(b0 + e, batch - 1) * sino;
+    const double is2 = g.inv_step * g.inv_step;
+
+    float acc[BC];
+#pragma unroll
+    for (int i = 0; i < BC; ++i) acc[i] = 0.0f;
+
+    for (int a0 = 0; a0 < A; a0 += kBpAnglesFan) {
+        const int na = min(kBpAnglesFan, A - a0);
+        __syncthreads();
+        if (threadIdx.x < na) {
+            // bin window of the tile: projections of the corners of its footprint
+            const double2 cs = g.trig[a0 + threadIdx.x];
+            double lo = 1e30;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const double px = tx0 - 1.0 + ((k & 1) ? kBpTile + 1.0 : 0.0) - g.cn;
+                const double py = ty0 - 1.0 + ((k & 2) ? kBpTile + 1.0 : 0.0) - g.cn;
+                const double pu = fma(px, cs.x, py * cs.y), pv = fma(-px, cs.y, py * cs.x);
+                lo = fmin(lo, g.sde * pu / (g.sd + pv) * g.inv_spacing + g.half_d);
+            }
+            wlo_s[threadIdx.x] = (int)floor(lo) - 1;
+        }
+        __syncthreads();
+        for (int p = threadIdx.x; p < na * W; p += 256) {
+            const int al = p / W, j = p - al * W;
+            const int d = wlo_s[al] + j;
+            const bool inside = (unsigned)d < (unsigned)D;
+            const unsigned off = (unsigned)((a0 + al) * D + (inside ? d : 0));
+#pragma unroll
+            for (int q = 0; q < PLANES; ++q) {
+                T v[CH];
+#pragma unroll
+                for (int e = 0; e < CH; ++e) {
+                    const T val = img_base[q * CH + e][off];
+                    v[e] = inside ? val : Chunk<T>::zero();
+                }
+                lds[q * per_plane + al * W + j] = Chunk<T>::pack(v);
+            }
+            // a bin outside the detector gets a ray far from every pixel (weight 0)
+            rays_s[al * W + j] = inside ? g.rays[off] : make_double4(-1e9, -1e9, 0.0, 0.0);
+        }
+        __syncthreads();
+
+        float part[BC];
+#pragma unroll
+        for (int i = 0; i < BC; ++i) part[i] = 0.0f;
+        for (int al = 0; al < na; ++al) {
+            const double2 cs = g.trig[a0 + al];
+            // detector coordinate of the pixel centre and its gradient (bins per pixel)
+            const double pu = fma(qx, cs.x, qy * cs.y), pv = fma(-qx, cs.y, qy * cs.x);
+            const double den = 1.0 / (g.sd + pv);
+            const double sb = g.sde * pu * den * g.inv_spacing + g.half_d;
+            const double gsx = g.sde * (cs.x * (g.sd + pv) + pu * cs.y) * den * den * g.inv_spacing;
+            const double gsy = g.sde * (cs.y * (g.sd + pv) - pu * cs.x) * den * den * g.inv_spacing;
+            const double hb = fabs(gsx) + fabs(gsy);
+            const int dfirst = (int)ceil(sb - hb * 1.01 - 0.05);
+            int lb = dfirst - wlo_s[al];
+            lb = min(max(lb, 0), W - NB);               // memory safety; real pixels are inside
+            float wgt[NB];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                const double4 rp = rays_s[al * W + lb + i];
+                const double ex = rp.x - (double)c, ey = rp.y - (double)r;   // F - Q
+                const double kc = -fma(ex, rp.z, ey * rp.w) * is2;           // pixel along the ray
+                const double hk = (fabs(rp.z) + fabs(rp.w)) * is2;
+                const double k0 = floor(kc - hk);
+                float dx = (float)fma(k0 + 1.0, rp.z, ex), dy = (float)fma(k0 + 1.0, rp.w, ey);
+                const float sx = (float)rp.z, sy = (float)rp.w;
+                float w = 0.0f;
+#pragma unroll
+                for (int jj = 0; jj < NK; ++jj) {
+                    const float tx = __builtin_amdgcn_fmed3f(1.0f - fabsf(dx), 0.0f, 1.0f);
+                    const float ty = __builtin_amdgcn_fmed3f(1.0f - fabsf(dy), 0.0f, 1.0f);
+                    w = fmaf(tx, ty, w);
+                    dx += sx;
+                    dy += sy;
+                }
+                wgt[i] = w;
+            }
+            const uint4 *row = lds + al * W + lb;
+#pragma unroll
+            for (int qq = 0; qq < PLANES; ++qq) {
+#pragma unroll
+                for (int i = 0; i < NB; ++i) Chunk<T>::fma(wgt[i], row[qq * per_plane + i], part + qq * CH);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < BC; ++i) acc[i] += part[i];
+    }
+    if (c >= n || r >= n) return;
+#pragma unroll
+    for (int i = 0; i < BC; ++i)
+        if (b0 + i < batch)
+            Store<T>::store(x + (size_t)(b0 + i) * n * n + (size_t)r * n + c, acc[i] * scale_dt);
+}
+
 template <typename T, int BC>
 static hipError_t launch_bp_direct(const Geom &g, const void *y, void *x, int batch, float scale,
                                    hipStream_t s) {
@@ -228,11 +352,22 @@ template <typename T, int BC>
 static hipError_t launch_bp_tiled(const Geom &g, const BpWork &work, const void *y, void *x,
                                   int batch, float scale_dt, hipStream_t s) {
     constexpr int PLANES = BC / Chunk<T>::kImages;
-    const size_t lds = (size_t)PLANES * kBpAngles * work.window * sizeof(uint4);
     const int tiles = ((g.n + kBpTile - 1) / kBpTile) * ((g.n + kBpTile - 1) / kBpTile);
     dim3 grid(tiles, (batch + BC - 1) / BC);
-    hipLaunchKernelGGL((bp_tiled_par<T, BC, 3, 3>), grid, dim3(256), lds, s, g, (const T *)y,
-                       (T *)x, batch, scale_dt, work.window);
+    if (!g.fan) {
+        const size_t lds = (size_t)PLANES * kBpAngles * work.window * sizeof(uint4);
+        hipLaunchKernelGGL((bp_tiled_par<T, BC, 3, 3>), grid, dim3(256), lds, s, g, (const T *)y,
+                           (T *)x, batch, scale_dt, work.window);
+    } else {
+        const size_t lds = (size_t)PLANES * kBpAnglesFan * work.window * sizeof(uint4) +
+                           (size_t)kBpAnglesFan * work.window * sizeof(double4);
+        if (work.bins <= 4)
+            hipLaunchKernelGGL((bp_tiled_fan<T, BC, 4, 3>), grid, dim3(256), lds, s, g,
+                               (const T *)y, (T *)x, batch, scale_dt, work.window);
+        else
+            hipLaunchKernelGGL((bp_tiled_fan<T, BC, 6, 3>), grid, dim3(256), lds, s, g,
+                               (const T *)y, (T *)x, batch, scale_dt, work.window);
+    }
     return hipGetLastError();
 }
 

@@ -57,16 +57,20 @@ hipError_t launch_forward(const Geom &g, const FwdWork &work, int dtype, const L
                           const void *x, void *y, int batch, float scale, hipStream_t s);
 // ------------------------------------------------------------------ tiled backprojection
 constexpr int kBpTile = 16;        // pixels per tile side (one lane per pixel)
-constexpr int kBpAngles = 8;       // angles per LDS block
+constexpr int kBpAngles = 8;       // angles per LDS block (parallel beam)
+constexpr int kBpAnglesFan = 4;    // angles per LDS block (fan beam; rays are staged too)
 
 struct BpWork {
     int window = 0;                // bins staged per (tile, angle); 0 = use the direct kernel
+    int bins = 3;                  // candidate bins per (pixel, angle)
 };
 
-// Window of bins a 16x16 tile can touch at any angle of a parallel-beam geometry
-// with 3 x 3 candidate samples per pixel (bin spacing and step length 1 or more
-// coarse than sqrt(2)-covering); 0 when the tiled kernel does not apply.
-int plan_backproject_window(int beam, const std::vector<double2> &trig, double spacing, double step);
+// Tiled backprojection plan: the bin window a 16x16 tile can touch at any angle and
+// the number of candidate bins per pixel, such that the candidates (3 steps per bin)
+// cover every sample within a pixel's footprint.  window = 0 when the tiled kernels
+// do not apply (the direct kernel is used).
+BpWork plan_backproject(int beam, int n, const std::vector<double2> &trig, double spacing,
+                        double step, double source_distance, double det_distance);
 
 hipError_t launch_backproject(const Geom &g, const BpWork &work, int dtype, const LaunchShape &shape,
                               const void *y, void *x, int batch, float scale, hipStream_t s);

@@ -112,15 +112,41 @@ bool plan_forward_tiles(int n, int n_angles, int det_count, const std::vector<do
     return true;
 }
 
-int plan_backproject_window(int beam, const std::vector<double2> &trig, double spacing, double step) {
-    if (beam != 0) return 0;
+BpWork plan_backproject(int beam, int n, const std::vector<double2> &trig, double spacing,
+                        double step, double source_distance, double det_distance) {
+    BpWork w;
     double hmax = 0.0;
     for (const double2 &cs : trig) hmax = std::max(hmax, std::fabs(cs.x) + std::fabs(cs.y));
-    // 3 candidate bins and 3 candidate steps must cover the footprint (width 2*hmax)
-    if (2.0 * hmax / spacing > 3.0 || 2.0 * hmax / step > 3.0) return 0;
-    const int nb = 3;
-    const int w = (int)std::floor((kBpTile - 1) * hmax / spacing) + nb + 3;
-    return (w + 3) & ~3;
+    // 3 candidate steps must cover the footprint's extent along a ray (2*(|wx|+|wy|))
+    if (2.0 * std::sqrt(2.0) / step > 3.0) return w;
+    if (beam == 0) {
+        // 3 candidate bins must cover the footprint's extent across the rays
+        if (2.0 * hmax / spacing > 3.0) return w;
+        const int win = (int)std::floor((kBpTile - 1) * hmax / spacing) + 3 + 3;
+        w.window = (win + 3) & ~3;
+        w.bins = 3;
+        return w;
+    }
+    // fan beam: bound on the gradient of the detector coordinate s(P) over the image:
+    // magnification at the image point nearest the source, times the secant of the
+    // widest ray angle there
+    const double S = source_distance, SE = source_distance + det_distance;
+    const double reach = 0.5 * (n + 1) * std::sqrt(2.0) + 1.0;
+    if (!(S > reach)) return w;
+    const double grad = SE / (S - reach) * std::sqrt(1.0 + (reach / (S - reach)) * (reach / (S - reach)));
+    // the kernel bounds s over a pixel footprint to first order with a margin of
+    // 1% + 0.05 bins; the second-order term (|d|^2 |s''| / 2 <= 2 grad / (S - reach))
+    // must stay inside that margin
+    if (2.0 * grad / (S - reach) / spacing > 0.05) return w;
+    const double span = 2.0 * std::sqrt(2.0) * grad / spacing * 1.01 + 0.1;
+    const int nb = (int)std::floor(span) + 1;
+    if (nb > 6) return w;
+    w.bins = nb <= 4 ? 4 : 6;
+    // window of a 16x16 tile footprint (corner to corner) plus the candidate span
+    const double tile_span = (kBpTile + 1) * std::sqrt(2.0) * grad / spacing;
+    const int win = (int)std::ceil(tile_span) + w.bins + 4;
+    w.window = (win + 3) & ~3;
+    return w;
 }
 
 }  // namespace radon
