@@ -5,13 +5,17 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
+#include <deque>
 #include <memory>
+#include <string>
 #include <mutex>
 #include <new>
 #include <unordered_map>
 #include <vector>
 
 #include "../../include/radon.h"
+#include "radon_batched.hpp"
 #include "radon_launch.hpp"
 #include "radon_plan.hpp"
 
@@ -180,6 +184,7 @@ static int build_plan(const radon_geometry_t *g, int device, std::unique_ptr<Pla
         if (!ranges.empty() && hipMemcpy(p->fwd_ranges, ranges.data(), ranges.size() * sizeof(int2),
                                          hipMemcpyHostToDevice) != hipSuccess)
             return RADON_ERR_HIP;
+        p->fwd_items_host = items;
         p->fwd_work.items = p->fwd_items;
         p->fwd_work.ranges = p->fwd_ranges;
         p->fwd_work.n_items = (int)items.size();
@@ -259,9 +264,193 @@ static int dot_scratch(hipStream_t stream, double **out) {
     return RADON_OK;
 }
 
+// ---------------------------------------------------------------- uneven batches
+// Device job/work tables of one uneven batch, built once per job list (by content:
+// plans, buffers, batch sizes, scales) and reused, so later calls (and graph
+// captures) only launch.
+struct BatchTable {
+    BatchJob *jobs = nullptr;
+    WorkUnit *work = nullptr;
+    int *counter = nullptr;
+    BatchLaunch launch;
+    std::vector<int> fallback;   // jobs without a tiled plan, run with per-call kernels
+    BatchTable() = default;
+    BatchTable(const BatchTable &) = delete;
+    BatchTable &operator=(const BatchTable &) = delete;
+    ~BatchTable() {
+        if (jobs) (void)hipFree(jobs);
+        if (work) (void)hipFree(work);
+        if (counter) (void)hipFree(counter);
+    }
+};
+static std::unordered_map<std::string, std::unique_ptr<BatchTable>> g_batches;
+static std::deque<std::string> g_batch_order;
+constexpr size_t kMaxBatchTables = 32;
+
+static int build_batch_table(const std::vector<Plan *> &plans, const radon_job_t *jobs, int n,
+                             int dtype, int direction, int device, std::unique_ptr<BatchTable> &out) {
+    std::unique_ptr<BatchTable> t(new (std::nothrow) BatchTable());
+    if (!t) return RADON_ERR_ALLOC;
+    const int ch = dtype == RADON_F32 ? 4 : 8;
+    std::vector<BatchJob> bj;
+    struct Unit { WorkUnit u; double cost; };
+    std::vector<Unit> units;
+    size_t lds = 16;
+    for (int i = 0; i < n; ++i) {
+        const Plan *p = plans[i];
+        if (jobs[i].batch == 0) continue;
+        const bool tiled = direction == 0
+                               ? (p->fwd_shape.variant == VARIANT_TILED && p->fwd_work.n_items > 0)
+                               : (p->bp_shape.variant == VARIANT_TILED && p->bp_work.window > 0);
+        if (!tiled) {
+            t->fallback.push_back(i);
+            continue;
+        }
+        BatchJob j{};
+        j.g = p->geom;
+        j.items = p->fwd_work.items;
+        j.ranges = p->fwd_work.ranges;
+        j.tile_t = p->fwd_work.tile_t;
+        j.window = p->bp_work.window;
+        j.bins = p->bp_work.bins;
+        j.batch = jobs[i].batch;
+        j.in = jobs[i].input;
+        j.out = jobs[i].output;
+        j.scale_dt = (float)(jobs[i].scale * jobs[i].geometry->step);
+        const int jid = (int)bj.size();
+        bj.push_back(j);
+        if (direction == 0) {
+            const int planes = kBatchFwdImages / ch;
+            lds = std::max(lds, (size_t)planes * (kSlabH + 3) * j.tile_t * sizeof(uint4));
+            for (size_t k = 0; k < p->fwd_items_host.size(); ++k) {
+                const FwdItem &it = p->fwd_items_host[k];
+                const double cost = (double)(it.nslab + 1) * it.na * it.nd;
+                for (int b0 = 0; b0 < j.batch; b0 += kBatchFwdImages)
+                    units.push_back({{jid, (int)k, b0, 0}, cost});
+            }
+        } else {
+            const int planes = kBatchBpImages / ch;
+            const int n_img = p->geom.n;
+            const int tiles = ((n_img + kBpTile - 1) / kBpTile) * ((n_img + kBpTile - 1) / kBpTile);
+            size_t need;
+            double cost;
+            if (!p->geom.fan) {
+                need = (size_t)planes * kBpAngles * j.window * sizeof(uint4);
+                cost = (double)p->geom.n_angles * 3;
+            } else {
+                need = (size_t)planes * kBpAnglesFan * j.window * sizeof(uint4) +
+                       (size_t)kBpAnglesFan * j.window * sizeof(double4);
+                cost = (double)p->geom.n_angles * j.bins;
+            }
+            lds = std::max(lds, need);
+            for (int tile = 0; tile < tiles; ++tile)
+                for (int b0 = 0; b0 < j.batch; b0 += kBatchBpImages)
+                    units.push_back({{jid, tile, b0, 0}, cost});
+        }
+    }
+    std::stable_sort(units.begin(), units.end(),
+                     [](const Unit &a, const Unit &b) { return a.cost > b.cost; });
+    std::vector<WorkUnit> wu(units.size());
+    for (size_t k = 0; k < units.size(); ++k) wu[k] = units[k].u;
+    if (!bj.empty()) {
+        if (hipMalloc(&t->jobs, bj.size() * sizeof(BatchJob)) != hipSuccess) return RADON_ERR_ALLOC;
+        if (hipMalloc(&t->work, std::max<size_t>(wu.size(), 1) * sizeof(WorkUnit)) != hipSuccess)
+            return RADON_ERR_ALLOC;
+        if (hipMalloc(&t->counter, 64) != hipSuccess) return RADON_ERR_ALLOC;
+        if (hipMemcpy(t->jobs, bj.data(), bj.size() * sizeof(BatchJob), hipMemcpyHostToDevice) !=
+            hipSuccess)
+            return RADON_ERR_HIP;
+        if (!wu.empty() && hipMemcpy(t->work, wu.data(), wu.size() * sizeof(WorkUnit),
+                                     hipMemcpyHostToDevice) != hipSuccess)
+            return RADON_ERR_HIP;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, device) != hipSuccess) return RADON_ERR_HIP;
+        const int per_cu = batched_blocks_per_cu(direction, dtype, lds);
+        t->launch.jobs = t->jobs;
+        t->launch.work = t->work;
+        t->launch.counter = t->counter;
+        t->launch.n_work = (int)wu.size();
+        t->launch.grid = std::max(1, std::min((int)wu.size(), per_cu * prop.multiProcessorCount));
+        t->launch.lds = lds;
+    }
+    out = std::move(t);
+    return RADON_OK;
+}
+
+static int run_batched(const radon_job_t *jobs, int32_t n, int32_t dtype, int direction,
+                       void *stream) {
+    int rc = check_dtype(dtype);
+    if (rc != RADON_OK) return rc;
+    if (n < 0 || (n > 0 && !jobs)) return RADON_ERR_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<Plan *> plans(n, nullptr);
+    for (int i = 0; i < n; ++i) {
+        const radon_job_t &j = jobs[i];
+        if ((rc = validate(j.geometry)) != RADON_OK) return rc;
+        if (j.batch < 0 || !std::isfinite(j.scale)) return RADON_ERR_INVALID_ARG;
+        if (j.batch == 0) continue;
+        if ((rc = check_ptr(j.input)) != RADON_OK || (rc = check_ptr(j.output)) != RADON_OK) return rc;
+        if ((rc = get_plan(j.geometry, s, &plans[i])) != RADON_OK) return rc;
+    }
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return RADON_ERR_NO_DEVICE;
+    std::string key;
+    key.reserve(16 + (size_t)n * 40);
+    auto put = [&key](const void *p, size_t k) { key.append(static_cast<const char *>(p), k); };
+    put(&device, sizeof device);
+    put(&dtype, sizeof dtype);
+    put(&direction, sizeof direction);
+    for (int i = 0; i < n; ++i) {
+        put(&plans[i], sizeof(Plan *));
+        put(&jobs[i].input, sizeof(void *));
+        put(&jobs[i].output, sizeof(void *));
+        put(&jobs[i].batch, sizeof(int32_t));
+        put(&jobs[i].scale, sizeof(float));
+    }
+    BatchTable *t = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_mutex);
+        auto it = g_batches.find(key);
+        if (it != g_batches.end()) {
+            t = it->second.get();
+        } else {
+            hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+            if (hipStreamIsCapturing(s, &cap) != hipSuccess) return RADON_ERR_HIP;
+            if (cap != hipStreamCaptureStatusNone) return RADON_ERR_NOT_PREPARED;
+            std::unique_ptr<BatchTable> nt;
+            if ((rc = build_batch_table(plans, jobs, n, dtype, direction, device, nt)) != RADON_OK)
+                return rc;
+            if (g_batch_order.size() >= kMaxBatchTables) {
+                (void)hipDeviceSynchronize();   // an evicted table may still be in use
+                g_batches.erase(g_batch_order.front());
+                g_batch_order.pop_front();
+            }
+            t = nt.get();
+            g_batches.emplace(key, std::move(nt));
+            g_batch_order.push_back(key);
+        }
+    }
+    if (t->launch.n_work > 0) {
+        hipError_t e = launch_batched(direction, dtype, t->launch, s);
+        if (e != hipSuccess) return RADON_ERR_HIP;
+    }
+    for (int i : t->fallback) {
+        const Plan *p = plans[i];
+        hipError_t e = direction == 0
+            ? launch_forward(p->geom, p->fwd_work, dtype, p->fwd_shape, jobs[i].input,
+                             jobs[i].output, jobs[i].batch, jobs[i].scale, s)
+            : launch_backproject(p->geom, p->bp_work, dtype, p->bp_shape, jobs[i].input,
+                                 jobs[i].output, jobs[i].batch, jobs[i].scale, s);
+        if (e != hipSuccess) return RADON_ERR_HIP;
+    }
+    return RADON_OK;
+}
+
 static int release_all() {
     std::lock_guard<std::mutex> lock(g_mutex);
-    if (!g_plans.empty() || !g_scratch.empty()) (void)hipDeviceSynchronize();
+    if (!g_plans.empty() || !g_scratch.empty() || !g_batches.empty()) (void)hipDeviceSynchronize();
+    g_batches.clear();
+    g_batch_order.clear();
     g_plans.clear();
     for (auto &kv : g_scratch)
         if (kv.second.dot_partials) (void)hipFree(kv.second.dot_partials);
@@ -319,14 +508,12 @@ int radon_backproject(const radon_geometry_t *geometry, const void *y, void *x, 
 }
 
 int radon_forward_batched(const radon_job_t *jobs, int32_t n_jobs, int32_t dtype, void *stream) {
-    (void)jobs; (void)n_jobs; (void)dtype; (void)stream;
-    return RADON_ERR_UNSUPPORTED;
+    return run_batched(jobs, n_jobs, dtype, 0, stream);
 }
 
 int radon_backproject_batched(const radon_job_t *jobs, int32_t n_jobs, int32_t dtype,
                               void *stream) {
-    (void)jobs; (void)n_jobs; (void)dtype; (void)stream;
-    return RADON_ERR_UNSUPPORTED;
+    return run_batched(jobs, n_jobs, dtype, 1, stream);
 }
 
 int radon_dot_f64(const void *a, const void *b, int64_t n, int32_t dtype, double *out,

@@ -1,0 +1,103 @@
+// Uneven batches in one persistent launch (TorchRadon's batch processing, Sec. 4.1,
+// extended to jobs of different image sizes and angle sets).
+//
+// The host flattens every job into work units -- forward: (job, plan item, image
+// group); backprojection: (job, pixel tile, image group) -- sorted longest first.
+// A grid sized to the resident capacity of the GPU pulls units from a device
+// counter (the only atomic) until the list is exhausted; each unit runs the same
+// per-item device function as the per-call kernels, so results are identical.
+#include "radon_batched.hpp"
+#include "radon_tiles.hpp"
+
+namespace radon {
+
+__global__ void batch_counter_reset(int *counter) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) counter[0] = 0;
+}
+
+// Next work unit for the whole block (thread 0 takes it from the counter).
+__device__ __forceinline__ int next_unit(int *counter, int *slot) {
+    __syncthreads();                     // everyone is done with the previous unit and slot
+    if (threadIdx.x == 0) *slot = atomicAdd(counter, 1);
+    __syncthreads();
+    return *slot;
+}
+
+template <typename T, int BC>
+__global__ __launch_bounds__(256) void fwd_batched(const BatchJob *__restrict__ jobs,
+                                                   const WorkUnit *__restrict__ work, int n_work,
+                                                   int *counter) {
+    extern __shared__ uint4 lds[];
+    __shared__ int slot;
+    for (;;) {
+        const int w = next_unit(counter, &slot);
+        if (w >= n_work) break;
+        const WorkUnit u = work[w];
+        const BatchJob &j = jobs[u.job];
+        const FwdItem it = j.items[u.unit];
+        fwd_item<T, BC>(j.g, it, j.ranges, (const T *)j.in, (T *)j.out, j.batch, u.b0, j.scale_dt,
+                        j.tile_t, lds);
+    }
+}
+
+template <typename T, int BC>
+__global__ __launch_bounds__(256) void bp_batched(const BatchJob *__restrict__ jobs,
+                                                  const WorkUnit *__restrict__ work, int n_work,
+                                                  int *counter) {
+    extern __shared__ uint4 lds[];
+    __shared__ int slot;
+    for (;;) {
+        const int w = next_unit(counter, &slot);
+        if (w >= n_work) break;
+        const WorkUnit u = work[w];
+        const BatchJob &j = jobs[u.job];
+        const T *in = (const T *)j.in;
+        T *out = (T *)j.out;
+        if (!j.g.fan)
+            bp_tile_par<T, BC, 3, 3>(j.g, u.unit, u.b0, in, out, j.batch, j.scale_dt, j.window, lds);
+        else if (j.bins <= 4)
+            bp_tile_fan<T, BC, 4, 3>(j.g, u.unit, u.b0, in, out, j.batch, j.scale_dt, j.window, lds);
+        else
+            bp_tile_fan<T, BC, 6, 3>(j.g, u.unit, u.b0, in, out, j.batch, j.scale_dt, j.window, lds);
+    }
+}
+
+template <typename T>
+static hipError_t launch_batched_t(int direction, const BatchLaunch &L, hipStream_t s) {
+    hipLaunchKernelGGL(batch_counter_reset, dim3(1), dim3(64), 0, s, L.counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (direction == 0)
+        hipLaunchKernelGGL((fwd_batched<T, kBatchFwdImages>), dim3(L.grid), dim3(256), L.lds, s,
+                           L.jobs, L.work, L.n_work, L.counter);
+    else
+        hipLaunchKernelGGL((bp_batched<T, kBatchBpImages>), dim3(L.grid), dim3(256), L.lds, s,
+                           L.jobs, L.work, L.n_work, L.counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_batched(int direction, int dtype, const BatchLaunch &L, hipStream_t s) {
+    switch (dtype) {
+    case F32: return launch_batched_t<float>(direction, L, s);
+    case F16: return launch_batched_t<__half>(direction, L, s);
+    case BF16: return launch_batched_t<bf16_t>(direction, L, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int batched_blocks_per_cu(int direction, int dtype, size_t lds) {
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (dtype * 2 + direction) {
+    case F32 * 2 + 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fwd_batched<float, kBatchFwdImages>, 256, lds); break;
+    case F32 * 2 + 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, bp_batched<float, kBatchBpImages>, 256, lds); break;
+    case F16 * 2 + 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fwd_batched<__half, kBatchFwdImages>, 256, lds); break;
+    case F16 * 2 + 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, bp_batched<__half, kBatchBpImages>, 256, lds); break;
+    case BF16 * 2 + 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fwd_batched<bf16_t, kBatchFwdImages>, 256, lds); break;
+    case BF16 * 2 + 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, bp_batched<bf16_t, kBatchBpImages>, 256, lds); break;
+    default: break;
+    }
+    return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+}  // namespace radon

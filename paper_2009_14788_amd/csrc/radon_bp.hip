@@ -6,6 +6,7 @@
 // covers the pixel.  No atomics; results are deterministic.
 #include "radon_common.hpp"
 #include "radon_launch.hpp"
+#include "radon_tiles.hpp"
 
 namespace radon {
 
@@ -96,246 +97,21 @@ __global__ __launch_bounds__(256) void bp_direct(Geom g, const T *__restrict__ y
 }
 
 // ------------------------------------------------------------------ tiled variant
-// Parallel beam.  One block = a 16x16 pixel tile (lane <-> pixel) x BC images.
-// Angles are processed in blocks of kBpAngles: for each, the block stages into LDS
-// the window of W bins its tile can touch, as 16-byte chunks of Chunk<T>::kImages
-// images ("planes").  Each pixel then finds, per angle, the lattice samples
-// (bin d, step k) whose bilinear footprint covers it: the pixel's continuous
-// lattice coordinates (u*, v*) are formed in FP64, the NB x NK candidates
-// d = floor(u* - hu) + 1 + i, k = floor(v* - hv) + 1 + j cover every sample within
-// the footprint, and their offsets from the pixel are small FP32 numbers, so the
-// tent weights are accurate to FP32 rounding.  The NB bin weights are then applied
-// to BC images with 16-byte LDS reads.  No atomics.
+// One block = one 16x16 pixel tile x BC images (blockIdx.y selects the images).
 template <typename T, int BC, int NB, int NK>
 __global__ __launch_bounds__(256) void bp_tiled_par(Geom g, const T *__restrict__ y,
                                                     T *__restrict__ x, int batch, float scale_dt,
                                                     int W) {
     extern __shared__ uint4 lds[];
-    __shared__ int wlo_s[kBpAngles];
-    constexpr int CH = Chunk<T>::kImages;
-    constexpr int PLANES = BC / CH;
-    static_assert(BC % CH == 0, "BC must be a multiple of the images per chunk");
-    const int n = g.n, A = g.n_angles, D = g.det_count;
-    const int tiles_x = (n + kBpTile - 1) / kBpTile;
-    const int tx0 = (blockIdx.x % tiles_x) * kBpTile, ty0 = (blockIdx.x / tiles_x) * kBpTile;
-    const int c = tx0 + (threadIdx.x % kBpTile), r = ty0 + (threadIdx.x / kBpTile);
-    const int b0 = blockIdx.y * BC;
-    const double qx = (double)c - g.cn, qy = (double)r - g.cn;
-    const double tcx = tx0 + 0.5 * (kBpTile - 1) - g.cn, tcy = ty0 + 0.5 * (kBpTile - 1) - g.cn;
-    const size_t sino = (size_t)A * D;
-    const int per_plane = kBpAngles * W;
-    const T *img_base[BC];
-#pragma unroll
-    for (int e = 0; e < BC; ++e) img_base[e] = y + (size_t)min(b0 + e, batch - 1) * sino;
-    const float dt = (float)g.step, sp = (float)g.spacing;
-
-    float acc[BC];
-#pragma unroll
-    for (int i = 0; i < BC; ++i) acc[i] = 0.0f;
-
-    for (int a0 = 0; a0 < A; a0 += kBpAngles) {
-        const int na = min(kBpAngles, A - a0);
-        __syncthreads();                                // previous block consumed
-        if (threadIdx.x < na) {
-            const double2 cs = g.trig[a0 + threadIdx.x];
-            const double h = fabs(cs.x) + fabs(cs.y);
-            const double uc = fma(fma(tcx, cs.x, tcy * cs.y), g.inv_spacing, g.half_d);
-            wlo_s[threadIdx.x] = (int)floor(uc - (0.5 * (kBpTile - 1) + 1.0) * h * g.inv_spacing) - 1;
-        }
-        __syncthreads();
-        for (int p = threadIdx.x; p < na * W; p += 256) {
-            const int al = p / W, j = p - al * W;
-            const int d = wlo_s[al] + j;
-            const bool inside = (unsigned)d < (unsigned)D;
-            const unsigned off = (unsigned)((a0 + al) * D + (inside ? d : 0));
-#pragma unroll
-            for (int q = 0; q < PLANES; ++q) {
-                T v[CH];
-#pragma unroll
-                for (int e = 0; e < CH; ++e) {
-                    const T val = img_base[q * CH + e][off];   // always a valid address
-                    v[e] = inside ? val : Chunk<T>::zero();
-                }
-                lds[q * per_plane + al * W + j] = Chunk<T>::pack(v);
-            }
-        }
-        __syncthreads();
-
-        // the angle block's contributions are summed separately, then added to the
-        // pixel total (two-level summation keeps FP32 rounding small)
-        float part[BC];
-#pragma unroll
-        for (int i = 0; i < BC; ++i) part[i] = 0.0f;
-        for (int al = 0; al < na; ++al) {
-            const double2 cs = g.trig[a0 + al];
-            const double h = fabs(cs.x) + fabs(cs.y);
-            // continuous bin (u) and step (v) coordinates of the pixel centre
-            const double u = fma(fma(qx, cs.x, qy * cs.y), g.inv_spacing, g.half_d);
-            const double v = fma(qy, cs.x, -qx * cs.y) * g.inv_step;
-            const double db = floor(u - h * g.inv_spacing), kb = floor(v - h * g.inv_step);
-            // offset of candidate (d = db+1+i, k = kb+1+j) from the pixel, along u and v
-            const float e0 = (float)(db + 1.0 - u) * sp, t0 = (float)(kb + 1.0 - v) * dt;
-            const float cf = (float)cs.x, sf = (float)cs.y;
-            const float ux = sp * cf, uy = sp * sf;      // one bin along u
-            const float vx = -dt * sf, vy = dt * cf;     // one step along v
-            float dx_i = fmaf(e0, cf, -t0 * sf), dy_i = fmaf(e0, sf, t0 * cf);
-            float wgt[NB];
-#pragma unroll
-            for (int i = 0; i < NB; ++i) {
-                float dx = dx_i, dy = dy_i, w = 0.0f;
-#pragma unroll
-                for (int jj = 0; jj < NK; ++jj) {
-                    const float tx = __builtin_amdgcn_fmed3f(1.0f - fabsf(dx), 0.0f, 1.0f);
-                    const float ty = __builtin_amdgcn_fmed3f(1.0f - fabsf(dy), 0.0f, 1.0f);
-                    w = fmaf(tx, ty, w);
-                    dx += vx;
-                    dy += vy;
-                }
-                wgt[i] = w;
-                dx_i += ux;
-                dy_i += uy;
-            }
-            int lb = (int)db + 1 - wlo_s[al];
-            lb = min(max(lb, 0), W - NB);               // memory safety; real pixels are inside
-            const uint4 *row = lds + al * W + lb;
-#pragma unroll
-            for (int qq = 0; qq < PLANES; ++qq) {
-#pragma unroll
-                for (int i = 0; i < NB; ++i) Chunk<T>::fma(wgt[i], row[qq * per_plane + i], part + qq * CH);
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < BC; ++i) acc[i] += part[i];
-    }
-    if (c >= n || r >= n) return;
-#pragma unroll
-    for (int i = 0; i < BC; ++i)
-        if (b0 + i < batch)
-            Store<T>::store(x + (size_t)(b0 + i) * n * n + (size_t)r * n + c, acc[i] * scale_dt);
+    bp_tile_par<T, BC, NB, NK>(g, blockIdx.x, blockIdx.y * BC, y, x, batch, scale_dt, W, lds);
 }
 
-// Fan beam.  Same tiling as the parallel kernel; every bin has its own ray, so the
-// block also stages the rays (FP64 foot point and step) of its bin window.  Per
-// (pixel, angle) the candidate bins are those within the projected half-width of
-// the pixel's footprint around the projection of its centre (first-order bound
-// plus a margin far larger than the footprint's curvature); per bin, the NK
-// candidate samples around the pixel's position along that ray are evaluated with
-// FP64 anchors and FP32 offsets, exactly as in the parallel kernel.
 template <typename T, int BC, int NB, int NK>
 __global__ __launch_bounds__(256) void bp_tiled_fan(Geom g, const T *__restrict__ y,
                                                     T *__restrict__ x, int batch, float scale_dt,
                                                     int W) {
     extern __shared__ uint4 lds[];
-    __shared__ int wlo_s[kBpAnglesFan];
-    constexpr int CH = Chunk<T>::kImages;
-    constexpr int PLANES = BC / CH;
-    static_assert(BC % CH == 0, "BC must be a multiple of the images per chunk");
-    const int n = g.n, A = g.n_angles, D = g.det_count;
-    const int tiles_x = (n + kBpTile - 1) / kBpTile;
-    const int tx0 = (blockIdx.x % tiles_x) * kBpTile, ty0 = (blockIdx.x / tiles_x) * kBpTile;
-    const int c = tx0 + (threadIdx.x % kBpTile), r = ty0 + (threadIdx.x / kBpTile);
-    const int b0 = blockIdx.y * BC;
-    const double qx = (double)c - g.cn, qy = (double)r - g.cn;
-    const size_t sino = (size_t)A * D;
-    const int per_plane = kBpAnglesFan * W;
-    double4 *rays_s = reinterpret_cast<double4 *>(lds + PLANES * per_plane);
-    const T *img_base[BC];
-#pragma unroll
-    for (int e = 0; e < BC; ++e) img_base[e] = y + (size_t)min(b0 + e, batch - 1) * sino;
-    const double is2 = g.inv_step * g.inv_step;
-
-    float acc[BC];
-#pragma unroll
-    for (int i = 0; i < BC; ++i) acc[i] = 0.0f;
-
-    for (int a0 = 0; a0 < A; a0 += kBpAnglesFan) {
-        const int na = min(kBpAnglesFan, A - a0);
-        __syncthreads();
-        if (threadIdx.x < na) {
-            // bin window of the tile: projections of the corners of its footprint
-            const double2 cs = g.trig[a0 + threadIdx.x];
-            double lo = 1e30;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const double px = tx0 - 1.0 + ((k & 1) ? kBpTile + 1.0 : 0.0) - g.cn;
-                const double py = ty0 - 1.0 + ((k & 2) ? kBpTile + 1.0 : 0.0) - g.cn;
-                const double pu = fma(px, cs.x, py * cs.y), pv = fma(-px, cs.y, py * cs.x);
-                lo = fmin(lo, g.sde * pu / (g.sd + pv) * g.inv_spacing + g.half_d);
-            }
-            wlo_s[threadIdx.x] = (int)floor(lo) - 1;
-        }
-        __syncthreads();
-        for (int p = threadIdx.x; p < na * W; p += 256) {
-            const int al = p / W, j = p - al * W;
-            const int d = wlo_s[al] + j;
-            const bool inside = (unsigned)d < (unsigned)D;
-            const unsigned off = (unsigned)((a0 + al) * D + (inside ? d : 0));
-#pragma unroll
-            for (int q = 0; q < PLANES; ++q) {
-                T v[CH];
-#pragma unroll
-                for (int e = 0; e < CH; ++e) {
-                    const T val = img_base[q * CH + e][off];
-                    v[e] = inside ? val : Chunk<T>::zero();
-                }
-                lds[q * per_plane + al * W + j] = Chunk<T>::pack(v);
-            }
-            // a bin outside the detector gets a ray far from every pixel (weight 0)
-            rays_s[al * W + j] = inside ? g.rays[off] : make_double4(-1e9, -1e9, 0.0, 0.0);
-        }
-        __syncthreads();
-
-        float part[BC];
-#pragma unroll
-        for (int i = 0; i < BC; ++i) part[i] = 0.0f;
-        for (int al = 0; al < na; ++al) {
-            const double2 cs = g.trig[a0 + al];
-            // detector coordinate of the pixel centre and its gradient (bins per pixel)
-            const double pu = fma(qx, cs.x, qy * cs.y), pv = fma(-qx, cs.y, qy * cs.x);
-            const double den = 1.0 / (g.sd + pv);
-            const double sb = g.sde * pu * den * g.inv_spacing + g.half_d;
-            const double gsx = g.sde * (cs.x * (g.sd + pv) + pu * cs.y) * den * den * g.inv_spacing;
-            const double gsy = g.sde * (cs.y * (g.sd + pv) - pu * cs.x) * den * den * g.inv_spacing;
-            const double hb = fabs(gsx) + fabs(gsy);
-            const int dfirst = (int)ceil(sb - hb * 1.01 - 0.05);
-            int lb = dfirst - wlo_s[al];
-            lb = min(max(lb, 0), W - NB);               // memory safety; real pixels are inside
-            float wgt[NB];
-#pragma unroll
-            for (int i = 0; i < NB; ++i) {
-                const double4 rp = rays_s[al * W + lb + i];
-                const double ex = rp.x - (double)c, ey = rp.y - (double)r;   // F - Q
-                const double kc = -fma(ex, rp.z, ey * rp.w) * is2;           // pixel along the ray
-                const double hk = (fabs(rp.z) + fabs(rp.w)) * is2;
-                const double k0 = floor(kc - hk);
-                float dx = (float)fma(k0 + 1.0, rp.z, ex), dy = (float)fma(k0 + 1.0, rp.w, ey);
-                const float sx = (float)rp.z, sy = (float)rp.w;
-                float w = 0.0f;
-#pragma unroll
-                for (int jj = 0; jj < NK; ++jj) {
-                    const float tx = __builtin_amdgcn_fmed3f(1.0f - fabsf(dx), 0.0f, 1.0f);
-                    const float ty = __builtin_amdgcn_fmed3f(1.0f - fabsf(dy), 0.0f, 1.0f);
-                    w = fmaf(tx, ty, w);
-                    dx += sx;
-                    dy += sy;
-                }
-                wgt[i] = w;
-            }
-            const uint4 *row = lds + al * W + lb;
-#pragma unroll
-            for (int qq = 0; qq < PLANES; ++qq) {
-#pragma unroll
-                for (int i = 0; i < NB; ++i) Chunk<T>::fma(wgt[i], row[qq * per_plane + i], part + qq * CH);
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < BC; ++i) acc[i] += part[i];
-    }
-    if (c >= n || r >= n) return;
-#pragma unroll
-    for (int i = 0; i < BC; ++i)
-        if (b0 + i < batch)
-            Store<T>::store(x + (size_t)(b0 + i) * n * n + (size_t)r * n + c, acc[i] * scale_dt);
+    bp_tile_fan<T, BC, NB, NK>(g, blockIdx.x, blockIdx.y * BC, y, x, batch, scale_dt, W, lds);
 }
 
 template <typename T, int BC>

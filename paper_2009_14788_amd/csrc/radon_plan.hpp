@@ -33,6 +33,7 @@ struct Plan {
     FwdItem *fwd_items = nullptr;  // device, tiled forward work items
     int2 *fwd_ranges = nullptr;    // device, per item and slab transverse ranges
     FwdWork fwd_work;
+    std::vector<FwdItem> fwd_items_host;   // host copy (work-unit costs of uneven batches)
     BpWork bp_work;
     LaunchShape fwd_shape, bp_shape;
     Plan() = default;

@@ -1,0 +1,390 @@
+// Per-work-item device functions of the tiled projectors, shared by the per-call
+// kernels and the persistent uneven-batch kernels.  Every function is called by all
+// 256 threads of a block with block-uniform arguments (they contain barriers).
+#pragma once
+
+#include "radon_common.hpp"
+#include "radon_launch.hpp"
+
+namespace radon {
+
+// ------------------------------------------------------------------ forward
+// Stage a rows x cols pixel window whose element (0, 0) is image pixel (ox0, oy0)
+// into LDS as PLANES planes of 16-byte chunks (Chunk<T>::kImages images per chunk,
+// zero outside the image).  Image base pointers are uniform per plane and image,
+// so loads use 32-bit pixel offsets; the (row, col) walk is incremental.
+template <typename T, int PLANES>
+__device__ __forceinline__ void stage_window(uint4 *lds, int plane_chunks, int pitch,
+                                             const T *const *img_base, int n, int ox0, int oy0,
+                                             int rows, int cols) {
+    constexpr int CH = Chunk<T>::kImages;
+    const int total = rows * cols;
+    const int step_i = 256 / cols, step_j = 256 - step_i * cols;
+    int i0 = threadIdx.x / cols, j0 = threadIdx.x - (threadIdx.x / cols) * cols;
+#pragma unroll
+    for (int q = 0; q < PLANES; ++q) {
+        int i = i0, jj = j0;
+        for (int idx = threadIdx.x; idx < total; idx += 256) {
+            const int gx = ox0 + jj, gy = oy0 + i;
+            const bool inside = (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n;
+            const unsigned off = inside ? (unsigned)(gy * n + gx) : 0u;
+            T v[CH];
+#pragma unroll
+            for (int e = 0; e < CH; ++e) {
+                const T val = img_base[q * CH + e][off];     // always a valid address
+                v[e] = inside ? val : Chunk<T>::zero();
+            }
+            lds[q * plane_chunks + i * pitch + jj] = Chunk<T>::pack(v);
+            jj += step_j;
+            i += step_i;
+            if (jj >= cols) {
+                jj -= cols;
+                ++i;
+            }
+        }
+    }
+}
+
+// One block processes one work item (up to 4 angles x 64 bins; wave w <-> angle a0+w, lane
+// l <-> bin d0+l) x BC images.  The rays march through the image in slabs of
+// kSlabH rows (or columns); per slab the block stages the slab's pixel window
+// into LDS as 16-byte chunks holding Chunk<T>::kImages images each ("planes"),
+// then every lane walks its ray's samples inside the slab.  A sample costs one
+// address and weight computation shared by the BC images and four 16-byte LDS
+// reads per plane.  The split of each ray's samples between slabs is fixed by
+// FP64 boundary crossings (consistent across slabs); sample positions are FP64
+// offsets from the lane's first cell in the slab and only the bilinear fractions
+// drop to FP32, so weights are accurate to FP32 rounding anywhere in the image.
+template <typename T, int BC>
+__device__ __forceinline__ void fwd_item(const Geom &g, const FwdItem &it, const int2 *__restrict__ ranges,
+                                         const T *__restrict__ x, T *__restrict__ y, int batch,
+                                         int b0, float scale_dt, int tile_t, uint4 *lds) {
+    constexpr int CH = Chunk<T>::kImages;
+    constexpr int PLANES = BC / CH;
+    static_assert(BC % CH == 0, "BC must be a multiple of the images per chunk");
+    const int plane_chunks = (kSlabH + 3) * tile_t;
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const bool active = wave < it.na && lane < it.nd;
+    const int a = it.a0 + min(wave, it.na - 1), d = it.d0 + min(lane, it.nd - 1);
+    const int n = g.n;
+    const size_t img = (size_t)n * n;
+    const T *img_base[BC];
+#pragma unroll
+    for (int e = 0; e < BC; ++e) img_base[e] = x + (size_t)min(b0 + e, batch - 1) * img;
+
+    // the lane's ray, oriented so that the march coordinate grows with the sample index
+    double4 r = ray_params(g, a, d);
+    const double sm_raw = it.axis ? r.z : r.w;
+    if (sm_raw < 0.0) { r.z = -r.z; r.w = -r.w; }
+    const double om = it.axis ? r.x : r.y;
+    const double inv_sm = 1.0 / fabs(sm_raw);
+    int jlo, jhi;
+    support_range(r, n, jlo, jhi);
+    const int pitch = it.axis ? (kSlabH + 3) : tile_t;
+
+    float acc[BC];
+#pragma unroll
+    for (int i = 0; i < BC; ++i) acc[i] = 0.0f;
+
+    for (int si = 0; si < it.nslab; ++si) {
+        const int2 tr = ranges[it.range + si];
+        if (tr.x > tr.y) continue;                      // uniform over the block
+        const int m_lo = -1 + (it.slab0 + si) * kSlabH;
+        // tile element (0, 0) sits at image (ox0, oy0); tile is rows x cols pixels
+        const int ox0 = it.axis ? m_lo - 1 : tr.x;
+        const int oy0 = it.axis ? tr.x : m_lo - 1;
+        const int cols = it.axis ? kSlabH + 3 : tr.y - tr.x + 1;
+        const int rows = it.axis ? tr.y - tr.x + 1 : kSlabH + 3;
+
+        __syncthreads();                                // previous slab fully consumed
+        stage_window<T, PLANES>(lds, plane_chunks, pitch, img_base, n, ox0, oy0, rows, cols);
+        __syncthreads();
+
+        // samples of this ray whose march coordinate lies in [m_lo, m_lo + kSlabH)
+        const int jb = max(jlo, (int)ceil(((double)m_lo - om) * inv_sm));
+        const int je = min(jhi + 1, (int)ceil(((double)(m_lo + kSlabH) - om) * inv_sm));
+        if (jb >= je) continue;
+        const double px64 = fma((double)jb, r.z, r.x) - (double)ox0;
+        const double py64 = fma((double)jb, r.w, r.y) - (double)oy0;
+        const double bx = floor(px64), by = floor(py64);
+        const double fxa = px64 - bx, fya = py64 - by;
+        const int base = (int)by * pitch + (int)bx;
+        const int max_addr = max((rows - 2) * pitch + (cols - 2), 0);
+        // the slab's samples are summed separately and then added to the ray total
+        // (two-level summation keeps FP32 rounding of long rays small)
+        float part[BC];
+#pragma unroll
+        for (int i = 0; i < BC; ++i) part[i] = 0.0f;
+        double jd = 0.0;
+        for (int j = jb; j < je; ++j, jd += 1.0) {
+            const double px = fma(jd, r.z, fxa), py = fma(jd, r.w, fya);
+            const double cx = floor(px), cy = floor(py);
+            const float fx = (float)(px - cx), fy = (float)(py - cy);
+            const float gx = 1.0f - fx, gy = 1.0f - fy;
+            const float w00 = __fmul_rn(gx, gy), w01 = __fmul_rn(fx, gy);
+            const float w10 = __fmul_rn(gx, fy), w11 = __fmul_rn(fx, fy);
+            int addr = base + __mul24((int)cy, pitch) + (int)cx;
+            addr = min(max(addr, 0), max_addr);         // memory safety; real samples are inside
+#pragma unroll
+            for (int q = 0; q < PLANES; ++q) {
+                const uint4 *pl = lds + q * plane_chunks + addr;
+                const uint4 t00 = pl[0], t01 = pl[1], t10 = pl[pitch], t11 = pl[pitch + 1];
+                float *aq = part + q * CH;
+                Chunk<T>::fma(w00, t00, aq);
+                Chunk<T>::fma(w01, t01, aq);
+                Chunk<T>::fma(w10, t10, aq);
+                Chunk<T>::fma(w11, t11, aq);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < BC; ++i) acc[i] += part[i];
+    }
+    if (!active) return;
+#pragma unroll
+    for (int i = 0; i < BC; ++i)
+        if (b0 + i < batch)
+            Store<T>::store(y + ((size_t)(b0 + i) * g.n_angles + a) * g.det_count + d,
+                            acc[i] * scale_dt);
+}
+
+// ------------------------------------------------------------------ backprojection
+// Parallel beam.  One block = a 16x16 pixel tile (lane <-> pixel) x BC images.
+// Angles are processed in blocks of kBpAngles: for each, the block stages into LDS
+// the window of W bins its tile can touch, as 16-byte chunks of Chunk<T>::kImages
+// images ("planes").  Each pixel then finds, per angle, the lattice samples
+// (bin d, step k) whose bilinear footprint covers it: the pixel's continuous
+// lattice coordinates (u*, v*) are formed in FP64, the NB x NK candidates
+// d = floor(u* - hu) + 1 + i, k = floor(v* - hv) + 1 + j cover every sample within
+// the footprint, and their offsets from the pixel are small FP32 numbers, so the
+// tent weights are accurate to FP32 rounding.  The NB bin weights are then applied
+// to BC images with 16-byte LDS reads.  No atomics.
+template <typename T, int BC, int NB, int NK>
+__device__ __forceinline__ void bp_tile_par(const Geom &g, int tile, int b0, const T *__restrict__ y,
+                                            T *__restrict__ x, int batch, float scale_dt, int W,
+                                            uint4 *lds) {
+    __shared__ int wlo_s[kBpAngles];
+    constexpr int CH = Chunk<T>::kImages;
+    constexpr int PLANES = BC / CH;
+    static_assert(BC % CH == 0, "BC must be a multiple of the images per chunk");
+    const int n = g.n, A = g.n_angles, D = g.det_count;
+    const int tiles_x = (n + kBpTile - 1) / kBpTile;
+    const int tx0 = (tile % tiles_x) * kBpTile, ty0 = (tile / tiles_x) * kBpTile;
+    const int c = tx0 + (threadIdx.x % kBpTile), r = ty0 + (threadIdx.x / kBpTile);
+    const double qx = (double)c - g.cn, qy = (double)r - g.cn;
+    const double tcx = tx0 + 0.5 * (kBpTile - 1) - g.cn, tcy = ty0 + 0.5 * (kBpTile - 1) - g.cn;
+    const size_t sino = (size_t)A * D;
+    const int per_plane = kBpAngles * W;
+    const T *img_base[BC];
+#pragma unroll
+    for (int e = 0; e < BC; ++e) img_base[e] = y + (size_t)min(b0 + e, batch - 1) * sino;
+    const float dt = (float)g.step, sp = (float)g.spacing;
+
+    float acc[BC];
+#pragma unroll
+    for (int i = 0; i < BC; ++i) acc[i] = 0.0f;
+
+    for (int a0 = 0; a0 < A; a0 += kBpAngles) {
+        const int na = min(kBpAngles, A - a0);
+        __syncthreads();                                // previous block consumed
+        if (threadIdx.x < na) {
+            const double2 cs = g.trig[a0 + threadIdx.x];
+            const double h = fabs(cs.x) + fabs(cs.y);
+            const double uc = fma(fma(tcx, cs.x, tcy * cs.y), g.inv_spacing, g.half_d);
+            wlo_s[threadIdx.x] = (int)floor(uc - (0.5 * (kBpTile - 1) + 1.0) * h * g.inv_spacing) - 1;
+        }
+        __syncthreads();
+        for (int p = threadIdx.x; p < na * W; p += 256) {
+            const int al = p / W, j = p - al * W;
+            const int d = wlo_s[al] + j;
+            const bool inside = (unsigned)d < (unsigned)D;
+            const unsigned off = (unsigned)((a0 + al) * D + (inside ? d : 0));
+#pragma unroll
+            for (int q = 0; q < PLANES; ++q) {
+                T v[CH];
+#pragma unroll
+                for (int e = 0; e < CH; ++e) {
+                    const T val = img_base[q * CH + e][off];   // always a valid address
+                    v[e] = inside ? val : Chunk<T>::zero();
+                }
+                lds[q * per_plane + al * W + j] = Chunk<T>::pack(v);
+            }
+        }
+        __syncthreads();
+
+        // the angle block's contributions are summed separately, then added to the
+        // pixel total (two-level summation keeps FP32 rounding small)
+        float part[BC];
+#pragma unroll
+        for (int i = 0; i < BC; ++i) part[i] = 0.0f;
+        for (int al = 0; al < na; ++al) {
+            const double2 cs = g.trig[a0 + al];
+            const double h = fabs(cs.x) + fabs(cs.y);
+            // continuous bin (u) and step (v) coordinates of the pixel centre
+            const double u = fma(fma(qx, cs.x, qy * cs.y), g.inv_spacing, g.half_d);
+            const double v = fma(qy, cs.x, -qx * cs.y) * g.inv_step;
+            const double db = floor(u - h * g.inv_spacing), kb = floor(v - h * g.inv_step);
+            // offset of candidate (d = db+1+i, k = kb+1+j) from the pixel, along u and v
+            const float e0 = (float)(db + 1.0 - u) * sp, t0 = (float)(kb + 1.0 - v) * dt;
+            const float cf = (float)cs.x, sf = (float)cs.y;
+            const float ux = sp * cf, uy = sp * sf;      // one bin along u
+            const float vx = -dt * sf, vy = dt * cf;     // one step along v
+            float dx_i = fmaf(e0, cf, -t0 * sf), dy_i = fmaf(e0, sf, t0 * cf);
+            float wgt[NB];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                float dx = dx_i, dy = dy_i, w = 0.0f;
+#pragma unroll
+                for (int jj = 0; jj < NK; ++jj) {
+                    const float tx = __builtin_amdgcn_fmed3f(1.0f - fabsf(dx), 0.0f, 1.0f);
+                    const float ty = __builtin_amdgcn_fmed3f(1.0f - fabsf(dy), 0.0f, 1.0f);
+                    w = fmaf(tx, ty, w);
+                    dx += vx;
+                    dy += vy;
+                }
+                wgt[i] = w;
+                dx_i += ux;
+                dy_i += uy;
+            }
+            int lb = (int)db + 1 - wlo_s[al];
+            lb = min(max(lb, 0), W - NB);               // memory safety; real pixels are inside
+            const uint4 *row = lds + al * W + lb;
+#pragma unroll
+            for (int qq = 0; qq < PLANES; ++qq) {
+#pragma unroll
+                for (int i = 0; i < NB; ++i) Chunk<T>::fma(wgt[i], row[qq * per_plane + i], part + qq * CH);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < BC; ++i) acc[i] += part[i];
+    }
+    if (c >= n || r >= n) return;
+#pragma unroll
+    for (int i = 0; i < BC; ++i)
+        if (b0 + i < batch)
+            Store<T>::store(x + (size_t)(b0 + i) * n * n + (size_t)r * n + c, acc[i] * scale_dt);
+}
+
+// Fan beam.  Same tiling as the parallel kernel; every bin has its own ray, so the
+// block also stages the rays (FP64 foot point and step) of its bin window.  Per
+// (pixel, angle) the candidate bins are those within the projected half-width of
+// the pixel's footprint around the projection of its centre (first-order bound
+// plus a margin far larger than the footprint's curvature); per bin, the NK
+// candidate samples around the pixel's position along that ray are evaluated with
+// FP64 anchors and FP32 offsets, exactly as in the parallel kernel.
+template <typename T, int BC, int NB, int NK>
+__device__ __forceinline__ void bp_tile_fan(const Geom &g, int tile, int b0, const T *__restrict__ y,
+                                            T *__restrict__ x, int batch, float scale_dt, int W,
+                                            uint4 *lds) {
+    __shared__ int wlo_s[kBpAnglesFan];
+    constexpr int CH = Chunk<T>::kImages;
+    constexpr int PLANES = BC / CH;
+    static_assert(BC % CH == 0, "BC must be a multiple of the images per chunk");
+    const int n = g.n, A = g.n_angles, D = g.det_count;
+    const int tiles_x = (n + kBpTile - 1) / kBpTile;
+    const int tx0 = (tile % tiles_x) * kBpTile, ty0 = (tile / tiles_x) * kBpTile;
+    const int c = tx0 + (threadIdx.x % kBpTile), r = ty0 + (threadIdx.x / kBpTile);
+    const double qx = (double)c - g.cn, qy = (double)r - g.cn;
+    const size_t sino = (size_t)A * D;
+    const int per_plane = kBpAnglesFan * W;
+    double4 *rays_s = reinterpret_cast<double4 *>(lds + PLANES * per_plane);
+    const T *img_base[BC];
+#pragma unroll
+    for (int e = 0; e < BC; ++e) img_base[e] = y + (size_t)min(b0 + e, batch - 1) * sino;
+    const double is2 = g.inv_step * g.inv_step;
+
+    float acc[BC];
+#pragma unroll
+    for (int i = 0; i < BC; ++i) acc[i] = 0.0f;
+
+    for (int a0 = 0; a0 < A; a0 += kBpAnglesFan) {
+        const int na = min(kBpAnglesFan, A - a0);
+        __syncthreads();
+        if (threadIdx.x < na) {
+            // bin window of the tile: projections of the corners of its footprint
+            const double2 cs = g.trig[a0 + threadIdx.x];
+            double lo = 1e30;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const double px = tx0 - 1.0 + ((k & 1) ? kBpTile + 1.0 : 0.0) - g.cn;
+                const double py = ty0 - 1.0 + ((k & 2) ? kBpTile + 1.0 : 0.0) - g.cn;
+                const double pu = fma(px, cs.x, py * cs.y), pv = fma(-px, cs.y, py * cs.x);
+                lo = fmin(lo, g.sde * pu / (g.sd + pv) * g.inv_spacing + g.half_d);
+            }
+            wlo_s[threadIdx.x] = (int)floor(lo) - 1;
+        }
+        __syncthreads();
+        for (int p = threadIdx.x; p < na * W; p += 256) {
+            const int al = p / W, j = p - al * W;
+            const int d = wlo_s[al] + j;
+            const bool inside = (unsigned)d < (unsigned)D;
+            const unsigned off = (unsigned)((a0 + al) * D + (inside ? d : 0));
+#pragma unroll
+            for (int q = 0; q < PLANES; ++q) {
+                T v[CH];
+#pragma unroll
+                for (int e = 0; e < CH; ++e) {
+                    const T val = img_base[q * CH + e][off];
+                    v[e] = inside ? val : Chunk<T>::zero();
+                }
+                lds[q * per_plane + al * W + j] = Chunk<T>::pack(v);
+            }
+            // a bin outside the detector gets a ray far from every pixel (weight 0)
+            rays_s[al * W + j] = inside ? g.rays[off] : make_double4(-1e9, -1e9, 0.0, 0.0);
+        }
+        __syncthreads();
+
+        float part[BC];
+#pragma unroll
+        for (int i = 0; i < BC; ++i) part[i] = 0.0f;
+        for (int al = 0; al < na; ++al) {
+            const double2 cs = g.trig[a0 + al];
+            // detector coordinate of the pixel centre and its gradient (bins per pixel)
+            const double pu = fma(qx, cs.x, qy * cs.y), pv = fma(-qx, cs.y, qy * cs.x);
+            const double den = 1.0 / (g.sd + pv);
+            const double sb = g.sde * pu * den * g.inv_spacing + g.half_d;
+            const double gsx = g.sde * (cs.x * (g.sd + pv) + pu * cs.y) * den * den * g.inv_spacing;
+            const double gsy = g.sde * (cs.y * (g.sd + pv) - pu * cs.x) * den * den * g.inv_spacing;
+            const double hb = fabs(gsx) + fabs(gsy);
+            const int dfirst = (int)ceil(sb - hb * 1.01 - 0.05);
+            int lb = dfirst - wlo_s[al];
+            lb = min(max(lb, 0), W - NB);               // memory safety; real pixels are inside
+            float wgt[NB];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                const double4 rp = rays_s[al * W + lb + i];
+                const double ex = rp.x - (double)c, ey = rp.y - (double)r;   // F - Q
+                const double kc = -fma(ex, rp.z, ey * rp.w) * is2;           // pixel along the ray
+                const double hk = (fabs(rp.z) + fabs(rp.w)) * is2;
+                const double k0 = floor(kc - hk);
+                float dx = (float)fma(k0 + 1.0, rp.z, ex), dy = (float)fma(k0 + 1.0, rp.w, ey);
+                const float sx = (float)rp.z, sy = (float)rp.w;
+                float w = 0.0f;
+#pragma unroll
+                for (int jj = 0; jj < NK; ++jj) {
+                    const float tx = __builtin_amdgcn_fmed3f(1.0f - fabsf(dx), 0.0f, 1.0f);
+                    const float ty = __builtin_amdgcn_fmed3f(1.0f - fabsf(dy), 0.0f, 1.0f);
+                    w = fmaf(tx, ty, w);
+                    dx += sx;
+                    dy += sy;
+                }
+                wgt[i] = w;
+            }
+            const uint4 *row = lds + al * W + lb;
+#pragma unroll
+            for (int qq = 0; qq < PLANES; ++qq) {
+#pragma unroll
+                for (int i = 0; i < NB; ++i) Chunk<T>::fma(wgt[i], row[qq * per_plane + i], part + qq * CH);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < BC; ++i) acc[i] += part[i];
+    }
+    if (c >= n || r >= n) return;
+#pragma unroll
+    for (int i = 0; i < BC; ++i)
+        if (b0 + i < batch)
+            Store<T>::store(x + (size_t)(b0 + i) * n * n + (size_t)r * n + c, acc[i] * scale_dt);
+}
+
+}  // namespace radon
