@@ -8,7 +8,7 @@ projections/s (images x angles per second through forward+backprojection), rays/
 algorithmic HBM GB/s, the roofline of the dominant kernel (timed with HIP events on
 the stream the kernels run on), and the FP64 CPU oracle timed on a bounded sample.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--variants]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick]
 """
 import argparse
 import json
@@ -88,8 +88,11 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--variants", action="store_true",
-                    help="also time FP16/BF16 storage and the autograd step")
+    ap.add_argument("--quick", action="store_true",
+                    help="only the headline workload (skip the other workloads and forms)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the benchmark, run a plain 1 GiB device-to-device copy three times "
+                         "(reference dispatch for scaling HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only (the transform is single-GPU; batch sharding "
@@ -181,56 +184,196 @@ def main():
         "sampled_rel_l2_vs_oracle": err,
         "roofline": roof,
     }
-    if args.variants:
-        out["variants"] = variants(op, x, B, A, D)
+    if not args.quick:
+        out["workloads"] = variants(op, x, x_np, B, A, D)
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)     # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(angles, N, D, x_np)
     print(json.dumps(out), flush=True)
 
 
-def variants(op, x, B, A, D, reps=5):
-    """FP16/BF16 storage and the differentiable step, each against the plain FP32 path."""
+def _timed(fn, reps=5, warm=1):
+    """Average ms of fn() over reps runs on the current stream (HIP events)."""
     import torch
-    res = {}
-
-    def timed(fn):
+    for _ in range(warm):
         fn()
-        torch.cuda.synchronize()
-        s = torch.cuda.Event(enable_timing=True)
-        e = torch.cuda.Event(enable_timing=True)
-        s.record()
-        for _ in range(reps):
-            fn()
-        e.record()
-        torch.cuda.synchronize()
-        return s.elapsed_time(e) / reps
+    torch.cuda.synchronize()
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps
 
+
+def _graph_ms(fn, reps=20):
+    """Average ms per replay of fn() captured into a graph."""
+    import torch
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    return _timed(g.replay, reps=reps, warm=2)
+
+
+def _sampled_err(og, x_np, y_dev, n=16, seed=0):
+    """Relative L2 error of n sampled forward outputs against the FP64 oracle."""
+    import oracle
+    B, A, D = y_dev.shape
+    rng = np.random.default_rng(seed)
+    idx = np.stack([rng.integers(0, B, n), rng.integers(0, A, n), rng.integers(0, D, n)], 1)
+    yg = y_dev[idx[:, 0], idx[:, 1], idx[:, 2]].double().cpu().numpy()
+    yr = oracle.forward_rays(og, x_np, idx)
+    return float(np.linalg.norm(yg - yr) / np.linalg.norm(yr))
+
+
+def variants(op, x, x_np, B, A, D):
+    """The other workloads and forms, each timed on this GPU with its error stated:
+    16-bit storage and the differentiable step on the headline batch; the single 64^2
+    image (latency, eager and graph-replayed); the 16 x 256^2 batch; 200 uneven jobs
+    in one persistent launch (eager, graph, and one call per job); the 64 x 512^2
+    fan beam with 16-bit storage and a 10-step unrolled gradient descent
+    differentiated end to end."""
+    import math
+    import torch
+    import oracle
+    from paper_2009_14788_amd import inputs
+    from paper_2009_14788_amd.batched import BatchedRadon
+    from paper_2009_14788_amd.radon import Radon, RadonFanbeam, dot_f64
+    from paper_2009_14788_amd.solvers import power_iteration, unrolled_gd
+    res = {}
+    og = oracle.Geometry(op.resolution, op.angles, D, 1.0)
+
+    # -- 16-bit storage on the headline batch
     y32 = op.forward_raw(x)
-    b32 = op.backprojection_raw(y32)
     for name, dt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
         xh = x.to(dt)
-        ms = timed(lambda: op.backprojection_raw(op.forward_raw(xh)))
+        ms = _timed(lambda: op.backprojection_raw(op.forward_raw(xh)))
         yh = op.forward_raw(xh)
-        bh = op.backprojection_raw(op.forward_raw(xh, scale=1e-3)) if dt == torch.float16 else \
-            op.backprojection_raw(yh)
-        ref_b = b32 * 1e-3 if dt == torch.float16 else b32
-        res[name] = {
+        res[f"batch128_512_{name}"] = {
             "ms_per_step": round(ms, 4), "projections_per_s": round(B * A / (ms * 1e-3), 1),
-            "fwd_rel_l2_vs_f32": float((yh.float() - y32).norm() / y32.norm()),
-            "bp_rel_l2_vs_f32": float((bh.float() - ref_b).norm() / ref_b.norm()),
-        }
-    xg = x.clone().requires_grad_(True)
-    yt = op.forward_raw(x)
+            "fwd_rel_l2_vs_f32_path": float((yh.float() - y32).norm() / y32.norm()),
+            "fwd_rel_l2_vs_oracle_sampled": _sampled_err(og, x_np, yh, seed=1)}
+        print(f"[bench] {name}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+        del xh, yh
+
+    # -- differentiable step: loss ||R x - y||^2 (FP64 reduction), backward via R^T
+    rng_noise = np.random.default_rng([2, 10 ** 6])
+    ymeas = y32 + torch.from_numpy(
+        (rng_noise.standard_normal(tuple(y32.shape)) * 0.01 *
+         y32.amax(dim=(1, 2)).cpu().numpy()[:, None, None]).astype(np.float32)).cuda()
+    xg = torch.zeros_like(x).requires_grad_(True)
 
     def ad_step():
         xg.grad = None
-        loss = (op.forward(xg) - yt).pow(2).sum()
-        loss.backward()
+        r = op.forward(xg) - ymeas
+        (r * r).sum().backward()
+        return dot_f64(r.detach(), r.detach())
 
-    ms = timed(ad_step)
-    res["autograd_loss_step"] = {"ms_per_step": round(ms, 4),
-                                 "projections_per_s": round(B * A / (ms * 1e-3), 1)}
+    ms = _timed(ad_step)
+    res["batch128_512_autograd_loss_step"] = {
+        "ms_per_step": round(ms, 4), "projections_per_s": round(B * A / (ms * 1e-3), 1),
+        "note": "forward + loss + backward (transpose kernel) + FP64 loss reduction"}
+    print(f"[bench] autograd loss step: {ms:.3f} ms", file=sys.stderr, flush=True)
+    del ymeas, xg, y32
+
+    # -- single 64x64 image (latency)
+    w0 = inputs.WORKLOADS["single64"]
+    op0 = Radon(64, w0.angles(), 91)
+    x0_np = inputs.phantom(64, 10, [0, 0])[0][None]
+    x0 = torch.from_numpy(x0_np).cuda()
+    y0 = torch.empty((1, 64, 91), device="cuda")
+    eager = _timed(lambda: op0.backprojection_raw(op0.forward_raw(x0)), reps=50, warm=5)
+    graph = _graph_ms(lambda: op0.backprojection_raw(op0.forward_raw(x0)), reps=100)
+    og0 = oracle.Geometry(64, w0.angles(), 91, 1.0)
+    e0 = float(np.linalg.norm(op0.forward_raw(x0)[0].double().cpu().numpy() - oracle.forward(og0, x0_np[0].astype(np.float64)))
+               / np.linalg.norm(oracle.forward(og0, x0_np[0].astype(np.float64))))
+    res["single64"] = {"us_per_step_eager": round(eager * 1e3, 2), "us_per_step_graph": round(graph * 1e3, 2),
+                       "fwd_rel_l2_vs_oracle": e0}
+
+    # -- 16 x 256^2
+    w1 = inputs.WORKLOADS["batch16_256"]
+    op1 = Radon(256, w1.angles(), 363)
+    x1_np = inputs.phantom_batch(1, 16, 256)
+    x1 = torch.from_numpy(x1_np).cuda()
+    ms = _timed(lambda: op1.backprojection_raw(op1.forward_raw(x1)), reps=20)
+    res["batch16_256"] = {"ms_per_step": round(ms, 4), "projections_per_s": round(16 * 256 / (ms * 1e-3), 1),
+                          "fwd_rel_l2_vs_oracle_sampled": _sampled_err(oracle.Geometry(256, w1.angles(), 363, 1.0), x1_np, op1.forward_raw(x1), seed=2)}
+
+    # -- 200 uneven jobs in one persistent launch
+    jobs = inputs.uneven_jobs(200)
+    ops = [Radon(j.n, j.angles(), j.det_count, 1.0) for j in jobs]
+    proj = sum(j.n_angles for j in jobs)
+    br = BatchedRadon(ops)
+    for name, dt in (("f32", torch.float32), ("f16", torch.float16)):
+        xs = [torch.from_numpy(inputs.uneven_phantom(j)[None]).cuda().to(dt) for j in jobs]
+        ys = [torch.empty((1,) + o.sinogram_shape, device="cuda", dtype=dt) for o in ops]
+        bs = [torch.empty((1,) + o.image_shape, device="cuda", dtype=dt) for o in ops]
+
+        def step():
+            br.forward(xs, out=ys)
+            br.backprojection(ys, out=bs)
+
+        ms_e = _timed(step, reps=10)
+        ms_g = _graph_ms(step, reps=10)
+        ms_seq = _timed(lambda: [o.backprojection_raw(o.forward_raw(xx)) for o, xx in zip(ops, xs)], reps=3)
+        step()
+        errs = []
+        for k in (0, 1, 2):
+            jk = jobs[k]
+            ogk = oracle.Geometry(jk.n, jk.angles(), jk.det_count, 1.0)
+            errs.append(_sampled_err(ogk, inputs.uneven_phantom(jk)[None].astype(np.float64), ys[k], seed=3 + k))
+        res[f"uneven200_{name}"] = {
+            "ms_per_step_eager": round(ms_e, 4), "ms_per_step_graph": round(ms_g, 4),
+            "ms_per_step_one_call_per_job": round(ms_seq, 4),
+            "projections_per_s_graph": round(proj / (ms_g * 1e-3), 1),
+            "fwd_rel_l2_vs_oracle_sampled_jobs0to2": max(errs)}
+        print(f"[bench] uneven200 {name}: eager {ms_e:.3f} graph {ms_g:.3f} per-job {ms_seq:.3f} ms",
+              file=sys.stderr, flush=True)
+        del xs, ys, bs
+
+    # -- fan beam 64 x 512^2, 16-bit storage; unrolled GD differentiated end to end
+    w4 = inputs.WORKLOADS["fan64_512"]
+    op4 = RadonFanbeam(512, w4.angles(), 1000.0, 500.0, 1024, 1.5)
+    x4_np = inputs.phantom_batch(4, 64, 512)
+    og4 = oracle.Geometry(512, w4.angles(), 1024, 1.5, beam=oracle.FANBEAM, source_distance=1000.0,
+                          det_distance=500.0)
+    lam = power_iteration(op4)
+    alpha = 1.0 / lam
+    for name, dt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
+        x4 = torch.from_numpy(x4_np).cuda().to(dt)
+        ms = _timed(lambda: op4.backprojection_raw(op4.forward_raw(x4), scale=alpha), reps=5)
+        y4 = op4.forward_raw(x4)
+        e4 = _sampled_err(og4, x4_np, y4, seed=7)
+        yreq = y4.clone().requires_grad_(True)
+
+        def gd_backward():
+            yreq.grad = None
+            xk = unrolled_gd(op4, yreq, alpha, iters=10, checkpoint=True)
+            ((xk.float() - x4.float()) ** 2).sum().backward()
+
+        ms_gd = _timed(gd_backward, reps=2)
+        res[f"fan64_512_{name}"] = {
+            "ms_per_step": round(ms, 4), "projections_per_s": round(64 * 1024 / (ms * 1e-3), 1),
+            "fwd_rel_l2_vs_oracle_sampled": e4, "alpha": alpha,
+            "unrolled_gd10_fwd_bwd_ms": round(ms_gd, 3)}
+        print(f"[bench] fan {name}: {ms:.3f} ms/step, unrolled GD fwd+bwd {ms_gd:.1f} ms",
+              file=sys.stderr, flush=True)
+        del x4, y4, yreq
     return res
 
 

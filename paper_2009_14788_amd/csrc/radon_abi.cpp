@@ -190,6 +190,8 @@ static int build_plan(const radon_geometry_t *g, int device, std::unique_ptr<Pla
         p->fwd_work.n_items = (int)items.size();
         p->fwd_work.tile_t = tile_t | 1;
         p->fwd_shape.variant = VARIANT_TILED;
+        const char *il = std::getenv("RADON_FWD_INTERLEAVE");
+        p->no_interleave = il && std::strcmp(il, "0") == 0;
         const char *imgs = std::getenv("RADON_FWD_IMAGES");
         p->fwd_shape.images = (imgs && std::atoi(imgs) >= 16) ? 16 : 8;
         p->fwd_shape.angles = kFwdWaves;
@@ -248,6 +250,40 @@ int get_plan(const radon_geometry_t *g, hipStream_t stream, Plan **out) {
     return RADON_OK;
 }
 
+// Forward workspace (the interleaved copy of the input batch), one per (device,
+// stream) so calls on different streams never share it.  Grown on demand outside
+// stream capture; a smaller buffer it replaces stays allocated (a captured graph may
+// still use it) until radon_release_plans.  Under capture without a large enough
+// workspace the forward stages straight from the caller's images instead.
+struct Workspace {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    std::vector<void *> retired;
+};
+static std::unordered_map<std::string, Workspace> g_workspaces;
+
+static void *forward_workspace(hipStream_t stream, size_t need, size_t *have) {
+    *have = 0;
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return nullptr;
+    std::string key(reinterpret_cast<const char *>(&device), sizeof device);
+    key.append(reinterpret_cast<const char *>(&stream), sizeof stream);
+    std::lock_guard<std::mutex> lock(g_mutex);
+    Workspace &w = g_workspaces[key];
+    if (w.bytes < need) {
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(stream, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
+            return w.ptr ? (*have = w.bytes, w.ptr) : nullptr;
+        void *p = nullptr;
+        if (hipMalloc(&p, need) != hipSuccess) return w.ptr ? (*have = w.bytes, w.ptr) : nullptr;
+        if (w.ptr) w.retired.push_back(w.ptr);
+        w.ptr = p;
+        w.bytes = need;
+    }
+    *have = w.bytes;
+    return w.ptr;
+}
+
 static int dot_scratch(hipStream_t stream, double **out) {
     int device = 0;
     if (hipGetDevice(&device) != hipSuccess) return RADON_ERR_NO_DEVICE;
@@ -270,6 +306,7 @@ static int dot_scratch(hipStream_t stream, double **out) {
 // captures) only launch.
 struct BatchTable {
     BatchJob *jobs = nullptr;
+    ImageGroup *groups = nullptr;
     WorkUnit *work = nullptr;
     int *counter = nullptr;
     BatchLaunch launch;
@@ -279,6 +316,7 @@ struct BatchTable {
     BatchTable &operator=(const BatchTable &) = delete;
     ~BatchTable() {
         if (jobs) (void)hipFree(jobs);
+        if (groups) (void)hipFree(groups);
         if (work) (void)hipFree(work);
         if (counter) (void)hipFree(counter);
     }
@@ -287,17 +325,29 @@ static std::unordered_map<std::string, std::unique_ptr<BatchTable>> g_batches;
 static std::deque<std::string> g_batch_order;
 constexpr size_t kMaxBatchTables = 32;
 
+template <typename V>
+static int upload(V **dst, const std::vector<V> &src) {
+    if (hipMalloc(dst, std::max<size_t>(src.size(), 1) * sizeof(V)) != hipSuccess) return RADON_ERR_ALLOC;
+    if (!src.empty() &&
+        hipMemcpy(*dst, src.data(), src.size() * sizeof(V), hipMemcpyHostToDevice) != hipSuccess)
+        return RADON_ERR_HIP;
+    return RADON_OK;
+}
+
+// Images of all jobs that share a plan are pooled and cut into image groups (8 for
+// the forward; for the backprojection 32 while at least 14 remain, else 8), so
+// single-image jobs of one geometry share lanes.  Units are sorted longest first.
 static int build_batch_table(const std::vector<Plan *> &plans, const radon_job_t *jobs, int n,
                              int dtype, int direction, int device, std::unique_ptr<BatchTable> &out) {
     std::unique_ptr<BatchTable> t(new (std::nothrow) BatchTable());
     if (!t) return RADON_ERR_ALLOC;
+    const size_t esize = dtype == RADON_F32 ? 4 : 2;
     const int ch = dtype == RADON_F32 ? 4 : 8;
-    std::vector<BatchJob> bj;
-    struct Unit { WorkUnit u; double cost; };
-    std::vector<Unit> units;
-    size_t lds = 16;
+    struct Img { const char *in; char *out; float scale; };
+    std::vector<Plan *> order;                       // distinct plans, first-seen order
+    std::unordered_map<Plan *, std::vector<Img>> pool;
     for (int i = 0; i < n; ++i) {
-        const Plan *p = plans[i];
+        Plan *p = plans[i];
         if (jobs[i].batch == 0) continue;
         const bool tiled = direction == 0
                                ? (p->fwd_shape.variant == VARIANT_TILED && p->fwd_work.n_items > 0)
@@ -306,6 +356,23 @@ static int build_batch_table(const std::vector<Plan *> &plans, const radon_job_t
             t->fallback.push_back(i);
             continue;
         }
+        const size_t img = (size_t)p->geom.n * p->geom.n * esize;
+        const size_t sino = (size_t)p->geom.n_angles * p->geom.det_count * esize;
+        const size_t in_stride = direction == 0 ? img : sino, out_stride = direction == 0 ? sino : img;
+        if (!pool.count(p)) order.push_back(p);
+        std::vector<Img> &v = pool[p];
+        const float sdt = (float)(jobs[i].scale * jobs[i].geometry->step);
+        for (int b = 0; b < jobs[i].batch; ++b)
+            v.push_back({static_cast<const char *>(jobs[i].input) + b * in_stride,
+                         static_cast<char *>(jobs[i].output) + b * out_stride, sdt});
+    }
+    std::vector<BatchJob> bj;
+    std::vector<ImageGroup> groups;
+    struct Unit { WorkUnit u; double cost; };
+    std::vector<Unit> units;
+    size_t lds = 16;
+    for (Plan *p : order) {
+        const std::vector<Img> &v = pool[p];
         BatchJob j{};
         j.g = p->geom;
         j.items = p->fwd_work.items;
@@ -313,39 +380,46 @@ static int build_batch_table(const std::vector<Plan *> &plans, const radon_job_t
         j.tile_t = p->fwd_work.tile_t;
         j.window = p->bp_work.window;
         j.bins = p->bp_work.bins;
-        j.batch = jobs[i].batch;
-        j.in = jobs[i].input;
-        j.out = jobs[i].output;
-        j.scale_dt = (float)(jobs[i].scale * jobs[i].geometry->step);
         const int jid = (int)bj.size();
         bj.push_back(j);
-        if (direction == 0) {
-            const int planes = kBatchFwdImages / ch;
-            lds = std::max(lds, (size_t)planes * (kSlabH + 3) * j.tile_t * sizeof(uint4));
-            for (size_t k = 0; k < p->fwd_items_host.size(); ++k) {
-                const FwdItem &it = p->fwd_items_host[k];
-                const double cost = (double)(it.nslab + 1) * it.na * it.nd;
-                for (int b0 = 0; b0 < j.batch; b0 += kBatchFwdImages)
-                    units.push_back({{jid, (int)k, b0, 0}, cost});
+        for (size_t k = 0; k < v.size();) {
+            const size_t left = v.size() - k;
+            const int cap = direction == 0 ? kBatchFwdImages
+                                           : (left >= 14 ? kBatchBpWide : kBatchBpNarrow);
+            const int cnt = (int)std::min<size_t>(left, (size_t)cap);
+            ImageGroup gr{};
+            for (int e = 0; e < kBatchBpWide; ++e) {
+                const Img &im = v[k + std::min(e, cnt - 1)];
+                gr.in[e] = im.in;
+                gr.out[e] = im.out;
+                gr.scale[e] = im.scale;
             }
-        } else {
-            const int planes = kBatchBpImages / ch;
-            const int n_img = p->geom.n;
-            const int tiles = ((n_img + kBpTile - 1) / kBpTile) * ((n_img + kBpTile - 1) / kBpTile);
-            size_t need;
-            double cost;
-            if (!p->geom.fan) {
-                need = (size_t)planes * kBpAngles * j.window * sizeof(uint4);
-                cost = (double)p->geom.n_angles * 3;
+            gr.count = cnt;
+            const int gid = (int)groups.size();
+            groups.push_back(gr);
+            k += cnt;
+            if (direction == 0) {
+                lds = std::max(lds, (size_t)(kBatchFwdImages / ch) * (kSlabH + 3) * j.tile_t * sizeof(uint4));
+                for (size_t it = 0; it < p->fwd_items_host.size(); ++it) {
+                    const FwdItem &f = p->fwd_items_host[it];
+                    units.push_back({{jid, (int)it, gid, 0}, (double)(f.nslab + 1) * f.na * f.nd});
+                }
             } else {
-                need = (size_t)planes * kBpAnglesFan * j.window * sizeof(uint4) +
-                       (size_t)kBpAnglesFan * j.window * sizeof(double4);
-                cost = (double)p->geom.n_angles * j.bins;
+                const bool wide = cap == kBatchBpWide;
+                const int planes = (wide ? kBatchBpWide : kBatchBpNarrow) / ch;
+                const int nimg = p->geom.n;
+                const int tiles = ((nimg + kBpTile - 1) / kBpTile) * ((nimg + kBpTile - 1) / kBpTile);
+                const size_t need = !p->geom.fan
+                    ? (size_t)planes * kBpAngles * j.window * sizeof(uint4)
+                    : (size_t)planes * kBpAnglesFan * j.window * sizeof(uint4) +
+                          (size_t)kBpAnglesFan * j.window * sizeof(double4);
+                lds = std::max(lds, need);
+                // instruction estimate per (pixel, angle): candidate search + 3 or NB FMAs per image
+                const int nb = p->geom.fan ? j.bins : 3;
+                const double cost = (double)p->geom.n_angles * (30.0 * nb + (wide ? 32 : 8) * nb);
+                for (int tile = 0; tile < tiles; ++tile)
+                    units.push_back({{jid, tile, gid, wide ? 1 : 0}, cost});
             }
-            lds = std::max(lds, need);
-            for (int tile = 0; tile < tiles; ++tile)
-                for (int b0 = 0; b0 < j.batch; b0 += kBatchBpImages)
-                    units.push_back({{jid, tile, b0, 0}, cost});
         }
     }
     std::stable_sort(units.begin(), units.end(),
@@ -353,20 +427,16 @@ static int build_batch_table(const std::vector<Plan *> &plans, const radon_job_t
     std::vector<WorkUnit> wu(units.size());
     for (size_t k = 0; k < units.size(); ++k) wu[k] = units[k].u;
     if (!bj.empty()) {
-        if (hipMalloc(&t->jobs, bj.size() * sizeof(BatchJob)) != hipSuccess) return RADON_ERR_ALLOC;
-        if (hipMalloc(&t->work, std::max<size_t>(wu.size(), 1) * sizeof(WorkUnit)) != hipSuccess)
-            return RADON_ERR_ALLOC;
+        int rc;
+        if ((rc = upload(&t->jobs, bj)) != RADON_OK) return rc;
+        if ((rc = upload(&t->groups, groups)) != RADON_OK) return rc;
+        if ((rc = upload(&t->work, wu)) != RADON_OK) return rc;
         if (hipMalloc(&t->counter, 64) != hipSuccess) return RADON_ERR_ALLOC;
-        if (hipMemcpy(t->jobs, bj.data(), bj.size() * sizeof(BatchJob), hipMemcpyHostToDevice) !=
-            hipSuccess)
-            return RADON_ERR_HIP;
-        if (!wu.empty() && hipMemcpy(t->work, wu.data(), wu.size() * sizeof(WorkUnit),
-                                     hipMemcpyHostToDevice) != hipSuccess)
-            return RADON_ERR_HIP;
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, device) != hipSuccess) return RADON_ERR_HIP;
         const int per_cu = batched_blocks_per_cu(direction, dtype, lds);
         t->launch.jobs = t->jobs;
+        t->launch.groups = t->groups;
         t->launch.work = t->work;
         t->launch.counter = t->counter;
         t->launch.n_work = (int)wu.size();
@@ -438,7 +508,7 @@ static int run_batched(const radon_job_t *jobs, int32_t n, int32_t dtype, int di
         const Plan *p = plans[i];
         hipError_t e = direction == 0
             ? launch_forward(p->geom, p->fwd_work, dtype, p->fwd_shape, jobs[i].input,
-                             jobs[i].output, jobs[i].batch, jobs[i].scale, s)
+                             jobs[i].output, jobs[i].batch, jobs[i].scale, nullptr, 0, s)
             : launch_backproject(p->geom, p->bp_work, dtype, p->bp_shape, jobs[i].input,
                                  jobs[i].output, jobs[i].batch, jobs[i].scale, s);
         if (e != hipSuccess) return RADON_ERR_HIP;
@@ -452,6 +522,11 @@ static int release_all() {
     g_batches.clear();
     g_batch_order.clear();
     g_plans.clear();
+    for (auto &kv : g_workspaces) {
+        if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+        for (void *r : kv.second.retired) (void)hipFree(r);
+    }
+    g_workspaces.clear();
     for (auto &kv : g_scratch)
         if (kv.second.dot_partials) (void)hipFree(kv.second.dot_partials);
     g_scratch.clear();
@@ -488,7 +563,12 @@ int radon_forward(const radon_geometry_t *geometry, const void *x, void *y, int3
     hipStream_t s = static_cast<hipStream_t>(stream);
     Plan *p = nullptr;
     if ((rc = get_plan(geometry, s, &p)) != RADON_OK) return rc;
-    hipError_t e = launch_forward(p->geom, p->fwd_work, dtype, p->fwd_shape, x, y, batch, scale, s);
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    if (p->fwd_shape.variant == VARIANT_TILED && p->fwd_work.n_items > 0 && !p->no_interleave)
+        ws = forward_workspace(s, interleaved_bytes(geometry->image_size, batch, dtype), &ws_bytes);
+    hipError_t e = launch_forward(p->geom, p->fwd_work, dtype, p->fwd_shape, x, y, batch, scale,
+                                  ws, ws_bytes, s);
     return e == hipSuccess ? RADON_OK : RADON_ERR_HIP;
 }
 

@@ -1,8 +1,10 @@
 // Uneven batches in one persistent launch (TorchRadon's batch processing, Sec. 4.1,
 // extended to jobs of different image sizes and angle sets).
 //
-// The host flattens every job into work units -- forward: (job, plan item, image
-// group); backprojection: (job, pixel tile, image group) -- sorted longest first.
+// The host groups the images of all jobs that share a geometry into image groups
+// (8 images for the forward; 8 or 32 for the backprojection) and flattens them into
+// work units -- forward: (geometry, plan item, image group); backprojection:
+// (geometry, pixel tile, image group) -- sorted longest first.
 // A grid sized to the resident capacity of the GPU pulls units from a device
 // counter (the only atomic) until the list is exhausted; each unit runs the same
 // per-item device function as the per-call kernels, so results are identical.
@@ -24,7 +26,21 @@ __device__ __forceinline__ int next_unit(int *counter, int *slot) {
 }
 
 template <typename T, int BC>
+__device__ __forceinline__ ImageSet<T, BC> group_images(const ImageGroup &grp) {
+    ImageSet<T, BC> s;
+#pragma unroll
+    for (int e = 0; e < BC; ++e) {
+        s.in[e] = (const T *)grp.in[e];
+        s.out[e] = (T *)grp.out[e];
+        s.scale[e] = grp.scale[e];
+    }
+    s.count = min(grp.count, BC);
+    return s;
+}
+
+template <typename T>
 __global__ __launch_bounds__(256) void fwd_batched(const BatchJob *__restrict__ jobs,
+                                                   const ImageGroup *__restrict__ groups,
                                                    const WorkUnit *__restrict__ work, int n_work,
                                                    int *counter) {
     extern __shared__ uint4 lds[];
@@ -35,13 +51,27 @@ __global__ __launch_bounds__(256) void fwd_batched(const BatchJob *__restrict__ 
         const WorkUnit u = work[w];
         const BatchJob &j = jobs[u.job];
         const FwdItem it = j.items[u.unit];
-        fwd_item<T, BC>(j.g, it, j.ranges, (const T *)j.in, (T *)j.out, j.batch, u.b0, j.scale_dt,
-                        j.tile_t, lds);
+        const ImageSet<T, kBatchFwdImages> imgs = group_images<T, kBatchFwdImages>(groups[u.group]);
+        const PointerSource<T, kBatchFwdImages> src{imgs.in, j.g.n};
+        fwd_item<T, kBatchFwdImages>(j.g, it, j.ranges, imgs, src, j.tile_t, lds);
     }
 }
 
 template <typename T, int BC>
+__device__ __forceinline__ void bp_unit(const BatchJob &j, const WorkUnit &u,
+                                        const ImageGroup &grp, uint4 *lds) {
+    const ImageSet<T, BC> imgs = group_images<T, BC>(grp);
+    if (!j.g.fan)
+        bp_tile_par<T, BC, 3, 3>(j.g, u.unit, imgs, j.window, lds);
+    else if (j.bins <= 4)
+        bp_tile_fan<T, BC, 4, 3>(j.g, u.unit, imgs, j.window, lds);
+    else
+        bp_tile_fan<T, BC, 6, 3>(j.g, u.unit, imgs, j.window, lds);
+}
+
+template <typename T>
 __global__ __launch_bounds__(256) void bp_batched(const BatchJob *__restrict__ jobs,
+                                                  const ImageGroup *__restrict__ groups,
                                                   const WorkUnit *__restrict__ work, int n_work,
                                                   int *counter) {
     extern __shared__ uint4 lds[];
@@ -50,15 +80,10 @@ __global__ __launch_bounds__(256) void bp_batched(const BatchJob *__restrict__ j
         const int w = next_unit(counter, &slot);
         if (w >= n_work) break;
         const WorkUnit u = work[w];
-        const BatchJob &j = jobs[u.job];
-        const T *in = (const T *)j.in;
-        T *out = (T *)j.out;
-        if (!j.g.fan)
-            bp_tile_par<T, BC, 3, 3>(j.g, u.unit, u.b0, in, out, j.batch, j.scale_dt, j.window, lds);
-        else if (j.bins <= 4)
-            bp_tile_fan<T, BC, 4, 3>(j.g, u.unit, u.b0, in, out, j.batch, j.scale_dt, j.window, lds);
+        if (u.wide)
+            bp_unit<T, kBatchBpWide>(jobs[u.job], u, groups[u.group], lds);
         else
-            bp_tile_fan<T, BC, 6, 3>(j.g, u.unit, u.b0, in, out, j.batch, j.scale_dt, j.window, lds);
+            bp_unit<T, kBatchBpNarrow>(jobs[u.job], u, groups[u.group], lds);
     }
 }
 
@@ -68,11 +93,11 @@ static hipError_t launch_batched_t(int direction, const BatchLaunch &L, hipStrea
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (direction == 0)
-        hipLaunchKernelGGL((fwd_batched<T, kBatchFwdImages>), dim3(L.grid), dim3(256), L.lds, s,
-                           L.jobs, L.work, L.n_work, L.counter);
+        hipLaunchKernelGGL((fwd_batched<T>), dim3(L.grid), dim3(256), L.lds, s, L.jobs, L.groups,
+                           L.work, L.n_work, L.counter);
     else
-        hipLaunchKernelGGL((bp_batched<T, kBatchBpImages>), dim3(L.grid), dim3(256), L.lds, s,
-                           L.jobs, L.work, L.n_work, L.counter);
+        hipLaunchKernelGGL((bp_batched<T>), dim3(L.grid), dim3(256), L.lds, s, L.jobs, L.groups,
+                           L.work, L.n_work, L.counter);
     return hipGetLastError();
 }
 
@@ -89,12 +114,12 @@ int batched_blocks_per_cu(int direction, int dtype, size_t lds) {
     int nb = 0;
     hipError_t e = hipErrorInvalidValue;
     switch (dtype * 2 + direction) {
-    case F32 * 2 + 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fwd_batched<float, kBatchFwdImages>, 256, lds); break;
-    case F32 * 2 + 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, bp_batched<float, kBatchBpImages>, 256, lds); break;
-    case F16 * 2 + 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fwd_batched<__half, kBatchFwdImages>, 256, lds); break;
-    case F16 * 2 + 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, bp_batched<__half, kBatchBpImages>, 256, lds); break;
-    case BF16 * 2 + 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fwd_batched<bf16_t, kBatchFwdImages>, 256, lds); break;
-    case BF16 * 2 + 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, bp_batched<bf16_t, kBatchBpImages>, 256, lds); break;
+    case F32 * 2 + 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fwd_batched<float>, 256, lds); break;
+    case F32 * 2 + 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, bp_batched<float>, 256, lds); break;
+    case F16 * 2 + 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fwd_batched<__half>, 256, lds); break;
+    case F16 * 2 + 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, bp_batched<__half>, 256, lds); break;
+    case BF16 * 2 + 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fwd_batched<bf16_t>, 256, lds); break;
+    case BF16 * 2 + 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, bp_batched<bf16_t>, 256, lds); break;
     default: break;
     }
     return (e == hipSuccess && nb > 0) ? nb : 1;

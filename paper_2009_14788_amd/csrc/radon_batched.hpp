@@ -8,10 +8,12 @@
 
 namespace radon {
 
-constexpr int kBatchFwdImages = 8;    // images per lane in the batched forward units
-constexpr int kBatchBpImages = 32;    // images per lane in the batched backprojection units
+constexpr int kBatchFwdImages = 8;     // images per lane in forward units
+constexpr int kBatchBpNarrow = 8;      // images per lane in small backprojection units
+constexpr int kBatchBpWide = 32;       // images per lane in large backprojection units
 
-// One job of an uneven batch as the device sees it.
+// One geometry of an uneven batch as the device sees it (shared by every job of
+// the batch that uses that geometry).
 struct BatchJob {
     Geom g;
     const FwdItem *items;     // forward plan items
@@ -19,22 +21,31 @@ struct BatchJob {
     int tile_t;               // forward LDS tile extent
     int window;               // backprojection bin window
     int bins;                 // backprojection candidate bins (fan)
-    int batch;                // images in the job
-    const void *in;
-    void *out;
-    float scale_dt;           // scale * step
+    int pad;
 };
 
-// One unit of work: forward (job, plan item, first image); backprojection
-// (job, pixel tile, first image).
+// Up to kBatchBpWide images of one geometry, possibly from different jobs: input
+// and output base pointers and the output scale (scale * step) of each.  Entries
+// past `count` repeat the last valid input.
+struct ImageGroup {
+    const void *in[kBatchBpWide];
+    void *out[kBatchBpWide];
+    float scale[kBatchBpWide];
+    int count;
+    int pad[3];
+};
+
+// One unit of work: forward (geometry, plan item, image group); backprojection
+// (geometry, pixel tile, image group); `wide` selects 32-image backprojection lanes.
 struct WorkUnit {
-    int job, unit, b0, pad;
+    int job, unit, group, wide;
 };
 
 struct BatchLaunch {
-    const BatchJob *jobs = nullptr;   // device
-    const WorkUnit *work = nullptr;   // device
-    int *counter = nullptr;           // device work counter
+    const BatchJob *jobs = nullptr;     // device
+    const ImageGroup *groups = nullptr; // device
+    const WorkUnit *work = nullptr;     // device
+    int *counter = nullptr;             // device work counter
     int n_work = 0;
     int grid = 0;
     size_t lds = 0;

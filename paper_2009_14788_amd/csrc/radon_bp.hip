@@ -103,7 +103,9 @@ __global__ __launch_bounds__(256) void bp_tiled_par(Geom g, const T *__restrict_
                                                     T *__restrict__ x, int batch, float scale_dt,
                                                     int W) {
     extern __shared__ uint4 lds[];
-    bp_tile_par<T, BC, NB, NK>(g, blockIdx.x, blockIdx.y * BC, y, x, batch, scale_dt, W, lds);
+    const ImageSet<T, BC> imgs = contiguous_images<T, BC>(
+        y, (size_t)g.n_angles * g.det_count, x, (size_t)g.n * g.n, batch, blockIdx.y * BC, scale_dt);
+    bp_tile_par<T, BC, NB, NK>(g, blockIdx.x, imgs, W, lds);
 }
 
 template <typename T, int BC, int NB, int NK>
@@ -111,7 +113,9 @@ __global__ __launch_bounds__(256) void bp_tiled_fan(Geom g, const T *__restrict_
                                                     T *__restrict__ x, int batch, float scale_dt,
                                                     int W) {
     extern __shared__ uint4 lds[];
-    bp_tile_fan<T, BC, NB, NK>(g, blockIdx.x, blockIdx.y * BC, y, x, batch, scale_dt, W, lds);
+    const ImageSet<T, BC> imgs = contiguous_images<T, BC>(
+        y, (size_t)g.n_angles * g.det_count, x, (size_t)g.n * g.n, batch, blockIdx.y * BC, scale_dt);
+    bp_tile_fan<T, BC, NB, NK>(g, blockIdx.x, imgs, W, lds);
 }
 
 template <typename T, int BC>

@@ -3,6 +3,8 @@
 // Ray-driven (each line integral is sampled along the ray with bilinear
 // interpolation and multiplied by the step length; TorchRadon Sec. 3.1.1-3.1.2,
 // batch processing Sec. 4.1, FP32 arithmetic on 16-bit storage Sec. 3.3).
+#include <algorithm>
+
 #include "radon_common.hpp"
 #include "radon_launch.hpp"
 #include "radon_tiles.hpp"
@@ -74,7 +76,58 @@ __global__ __launch_bounds__(256) void fwd_tiled(Geom g, FwdWork work, const T *
                                                  int tile_t) {
     extern __shared__ uint4 lds[];
     const FwdItem it = work.items[blockIdx.x];
-    fwd_item<T, BC>(g, it, work.ranges, x, y, batch, blockIdx.y * BC, scale_dt, tile_t, lds);
+    const ImageSet<T, BC> imgs = contiguous_images<T, BC>(
+        x, (size_t)g.n * g.n, y, (size_t)g.n_angles * g.det_count, batch, blockIdx.y * BC, scale_dt);
+    const PointerSource<T, BC> src{imgs.in, g.n};
+    fwd_item<T, BC>(g, it, work.ranges, imgs, src, tile_t, lds);
+}
+
+// Same, staging from the interleaved, zero-bordered copy xi of the batch.
+template <typename T, int BC>
+__global__ __launch_bounds__(256) void fwd_tiled_il(Geom g, FwdWork work, const uint4 *__restrict__ xi,
+                                                    T *__restrict__ y, int batch, float scale_dt,
+                                                    int tile_t) {
+    extern __shared__ uint4 lds[];
+    constexpr int CH = Chunk<T>::kImages;
+    const FwdItem it = work.items[blockIdx.x];
+    const int b0 = blockIdx.y * BC;
+    // only the output side of the image set is used with an interleaved source
+    const ImageSet<T, BC> imgs = contiguous_images<T, BC>(
+        y, 0, y, (size_t)g.n_angles * g.det_count, batch, b0, scale_dt);
+    const int plane = (g.n + 4) * (g.n + 4);
+    const InterleavedSource<T, BC> src{xi + (size_t)(b0 / CH) * plane, g.n, plane};
+    fwd_item<T, BC>(g, it, work.ranges, imgs, src, tile_t, lds);
+}
+
+// Interleave a batch x[B][N][N] into xi[ceil(B/CH)][N+4][N+4] chunks of CH images
+// with a zero border of 2 pixels (images past B are zero).
+template <typename T>
+__global__ __launch_bounds__(256) void interleave_images(const T *__restrict__ x, uint4 *__restrict__ xi,
+                                                         int n, int batch, int groups) {
+    constexpr int CH = Chunk<T>::kImages;
+    const int np = n + 4;
+    const int plane = np * np;
+    const long long total = (long long)groups * plane;
+    for (long long c = (long long)blockIdx.x * 256 + threadIdx.x; c < total;
+         c += (long long)gridDim.x * 256) {
+        const int grp = (int)(c / plane);
+        const int rem = (int)(c - (long long)grp * plane);
+        const int yy = rem / np - 2, xx = rem % np - 2;
+        const bool inside = (unsigned)xx < (unsigned)n && (unsigned)yy < (unsigned)n;
+        T v[CH];
+#pragma unroll
+        for (int e = 0; e < CH; ++e) {
+            const int b = grp * CH + e;
+            v[e] = (inside && b < batch) ? x[(size_t)b * n * n + (size_t)yy * n + xx] : Chunk<T>::zero();
+        }
+        xi[c] = Chunk<T>::pack(v);
+    }
+}
+
+size_t interleaved_bytes(int n, int batch, int dtype) {
+    const int ch = dtype == F32 ? 4 : 8;
+    const size_t groups = ((size_t)batch + 15) / 16 * 16 / ch;   // whole 16-image blocks
+    return groups * (size_t)(n + 4) * (n + 4) * sizeof(uint4);
 }
 
 template <typename T, int BC>
@@ -89,30 +142,46 @@ static hipError_t launch_fwd_direct(const Geom &g, const void *x, void *y, int b
 
 template <typename T, int BC>
 static hipError_t launch_fwd_tiled(const Geom &g, const FwdWork &work, const void *x, void *y,
-                                   int batch, float scale_dt, hipStream_t s) {
-    constexpr int PLANES = BC / Chunk<T>::kImages;
+                                   int batch, float scale_dt, void *ws, size_t ws_bytes,
+                                   hipStream_t s) {
+    constexpr int CH = Chunk<T>::kImages;
+    constexpr int PLANES = BC / CH;
     const size_t lds = (size_t)PLANES * (kSlabH + 3) * work.tile_t * sizeof(uint4);
     dim3 grid(work.n_items, (batch + BC - 1) / BC);
-    hipLaunchKernelGGL((fwd_tiled<T, BC>), grid, dim3(256), lds, s, g, work, (const T *)x, (T *)y,
-                       batch, scale_dt, work.tile_t);
+    const int dt = sizeof(T) == 4 ? F32 : F16;
+    if (ws && ws_bytes >= interleaved_bytes(g.n, batch, dt)) {
+        const int groups = (batch + BC - 1) / BC * PLANES;
+        const long long chunks = (long long)groups * (g.n + 4) * (g.n + 4);
+        const int blocks = (int)std::min<long long>((chunks + 255) / 256, 65536);
+        hipLaunchKernelGGL(interleave_images<T>, dim3(blocks), dim3(256), 0, s, (const T *)x,
+                           (uint4 *)ws, g.n, batch, groups);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((fwd_tiled_il<T, BC>), grid, dim3(256), lds, s, g, work,
+                           (const uint4 *)ws, (T *)y, batch, scale_dt, work.tile_t);
+    } else {
+        hipLaunchKernelGGL((fwd_tiled<T, BC>), grid, dim3(256), lds, s, g, work, (const T *)x,
+                           (T *)y, batch, scale_dt, work.tile_t);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_forward(const Geom &g, const FwdWork &work, int dtype, const LaunchShape &shape,
-                          const void *x, void *y, int batch, float scale, hipStream_t s) {
+                          const void *x, void *y, int batch, float scale, void *ws,
+                          size_t ws_bytes, hipStream_t s) {
     const float scale_dt = (float)(scale * g.step);
     if (shape.variant == VARIANT_TILED && work.n_items > 0) {
         const bool wide = shape.images >= 16;
         switch (dtype) {
         case F32:
-            return wide ? launch_fwd_tiled<float, 16>(g, work, x, y, batch, scale_dt, s)
-                        : launch_fwd_tiled<float, 8>(g, work, x, y, batch, scale_dt, s);
+            return wide ? launch_fwd_tiled<float, 16>(g, work, x, y, batch, scale_dt, ws, ws_bytes, s)
+                        : launch_fwd_tiled<float, 8>(g, work, x, y, batch, scale_dt, ws, ws_bytes, s);
         case F16:
-            return wide ? launch_fwd_tiled<__half, 16>(g, work, x, y, batch, scale_dt, s)
-                        : launch_fwd_tiled<__half, 8>(g, work, x, y, batch, scale_dt, s);
+            return wide ? launch_fwd_tiled<__half, 16>(g, work, x, y, batch, scale_dt, ws, ws_bytes, s)
+                        : launch_fwd_tiled<__half, 8>(g, work, x, y, batch, scale_dt, ws, ws_bytes, s);
         case BF16:
-            return wide ? launch_fwd_tiled<bf16_t, 16>(g, work, x, y, batch, scale_dt, s)
-                        : launch_fwd_tiled<bf16_t, 8>(g, work, x, y, batch, scale_dt, s);
+            return wide ? launch_fwd_tiled<bf16_t, 16>(g, work, x, y, batch, scale_dt, ws, ws_bytes, s)
+                        : launch_fwd_tiled<bf16_t, 8>(g, work, x, y, batch, scale_dt, ws, ws_bytes, s);
         default: return hipErrorInvalidValue;
         }
     }

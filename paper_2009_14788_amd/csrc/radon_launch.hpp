@@ -53,8 +53,12 @@ struct FwdWork {
 bool plan_forward_tiles(int n, int n_angles, int det_count, const std::vector<double4> &rays,
                         std::vector<FwdItem> &items, std::vector<int2> &ranges, int &tile_t);
 
+// ws: optional workspace for the interleaved copy of the input batch (used by the
+// tiled kernel when ws_bytes >= interleaved_bytes(n, batch, dtype)).
 hipError_t launch_forward(const Geom &g, const FwdWork &work, int dtype, const LaunchShape &shape,
-                          const void *x, void *y, int batch, float scale, hipStream_t s);
+                          const void *x, void *y, int batch, float scale, void *ws,
+                          size_t ws_bytes, hipStream_t s);
+size_t interleaved_bytes(int n, int batch, int dtype);
 // ------------------------------------------------------------------ tiled backprojection
 constexpr int kBpTile = 16;        // pixels per tile side (one lane per pixel)
 constexpr int kBpAngles = 8;       // angles per LDS block (parallel beam)

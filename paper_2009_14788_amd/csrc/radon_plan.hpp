@@ -35,6 +35,7 @@ struct Plan {
     FwdWork fwd_work;
     std::vector<FwdItem> fwd_items_host;   // host copy (work-unit costs of uneven batches)
     BpWork bp_work;
+    bool no_interleave = false;            // stage the forward from the caller's images
     LaunchShape fwd_shape, bp_shape;
     Plan() = default;
     Plan(const Plan &) = delete;

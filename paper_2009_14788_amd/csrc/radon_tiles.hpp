@@ -8,42 +8,116 @@
 
 namespace radon {
 
+// The BC images one block works on: input and output base pointers (entries past
+// `count` repeat a valid input so loads stay in bounds; their outputs are never
+// written) and the per-image output scale (scale * step).
+template <typename T, int BC>
+struct ImageSet {
+    const T *in[BC];
+    T *out[BC];
+    float scale[BC];
+    int count;
+};
+
+// Images b0 .. b0+BC-1 of one contiguous batch (input stride `in_stride`, output
+// stride `out_stride` elements).
+template <typename T, int BC>
+__device__ __forceinline__ ImageSet<T, BC> contiguous_images(const T *in, size_t in_stride, T *out,
+                                                             size_t out_stride, int batch, int b0,
+                                                             float scale_dt) {
+    ImageSet<T, BC> s;
+#pragma unroll
+    for (int e = 0; e < BC; ++e) {
+        const int b = min(b0 + e, batch - 1);
+        s.in[e] = in + (size_t)b * in_stride;
+        s.out[e] = out + (size_t)b * out_stride;
+        s.scale[e] = scale_dt;
+    }
+    s.count = min(BC, batch - b0);
+    return s;
+}
+
 // ------------------------------------------------------------------ forward
-// Stage a rows x cols pixel window whose element (0, 0) is image pixel (ox0, oy0)
-// into LDS as PLANES planes of 16-byte chunks (Chunk<T>::kImages images per chunk,
-// zero outside the image).  Image base pointers are uniform per plane and image,
-// so loads use 32-bit pixel offsets; the (row, col) walk is incremental.
-template <typename T, int PLANES>
-__device__ __forceinline__ void stage_window(uint4 *lds, int plane_chunks, int pitch,
-                                             const T *const *img_base, int n, int ox0, int oy0,
-                                             int rows, int cols) {
-    constexpr int CH = Chunk<T>::kImages;
-    const int total = rows * cols;
-    const int step_i = 256 / cols, step_j = 256 - step_i * cols;
-    int i0 = threadIdx.x / cols, j0 = threadIdx.x - (threadIdx.x / cols) * cols;
+// Slab staging sources.  Both fill a rows x cols pixel window whose element (0, 0) is
+// image pixel (ox0, oy0) into LDS as PLANES planes of 16-byte chunks (Chunk<T>::kImages
+// images per chunk, zero outside the image), rows `pitch` chunks apart and planes
+// `plane_chunks` apart.
+
+// From the callers' images (any layout of BC image pointers): image base pointers are
+// uniform per plane and image, loads use 32-bit pixel offsets, the (row, col) walk is
+// incremental, and pixels outside the image read a valid address and are replaced by 0.
+template <typename T, int BC>
+struct PointerSource {
+    const T *const *img;
+    int n;
+    __device__ __forceinline__ void stage(uint4 *lds, int plane_chunks, int pitch, int ox0, int oy0,
+                                          int rows, int cols) const {
+        constexpr int CH = Chunk<T>::kImages;
+        constexpr int PLANES = BC / CH;
+        const int total = rows * cols;
+        const int step_i = 256 / cols, step_j = 256 - step_i * cols;
+        const int i0 = threadIdx.x / cols, j0 = threadIdx.x - i0 * cols;
 #pragma unroll
-    for (int q = 0; q < PLANES; ++q) {
-        int i = i0, jj = j0;
-        for (int idx = threadIdx.x; idx < total; idx += 256) {
-            const int gx = ox0 + jj, gy = oy0 + i;
-            const bool inside = (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n;
-            const unsigned off = inside ? (unsigned)(gy * n + gx) : 0u;
-            T v[CH];
+        for (int q = 0; q < PLANES; ++q) {
+            int i = i0, jj = j0;
+            for (int idx = threadIdx.x; idx < total; idx += 256) {
+                const int gx = ox0 + jj, gy = oy0 + i;
+                const bool inside = (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n;
+                const unsigned off = inside ? (unsigned)(gy * n + gx) : 0u;
+                T v[CH];
 #pragma unroll
-            for (int e = 0; e < CH; ++e) {
-                const T val = img_base[q * CH + e][off];     // always a valid address
-                v[e] = inside ? val : Chunk<T>::zero();
-            }
-            lds[q * plane_chunks + i * pitch + jj] = Chunk<T>::pack(v);
-            jj += step_j;
-            i += step_i;
-            if (jj >= cols) {
-                jj -= cols;
-                ++i;
+                for (int e = 0; e < CH; ++e) {
+                    const T val = img[q * CH + e][off];     // always a valid address
+                    v[e] = inside ? val : Chunk<T>::zero();
+                }
+                lds[q * plane_chunks + i * pitch + jj] = Chunk<T>::pack(v);
+                jj += step_j;
+                i += step_i;
+                if (jj >= cols) {
+                    jj -= cols;
+                    ++i;
+                }
             }
         }
     }
-}
+};
+
+// From an interleaved copy of the batch: chunk (group, y+2, x+2) of a
+// [groups][N+4][N+4] array holds pixel (x, y) of the group's images, with a zero
+// border of 2 pixels, so a window inside [-2, N+1]^2 is copied chunk for chunk with
+// no bounds test.  Window rows/columns beyond [-2, N+1] are never tapped and are
+// not staged.
+template <typename T, int BC>
+struct InterleavedSource {
+    const uint4 *base;   // first plane of the block's images
+    int n;
+    int plane_stride;    // chunks between planes ((N+4)^2)
+    __device__ __forceinline__ void stage(uint4 *lds, int plane_chunks, int pitch, int ox0, int oy0,
+                                          int rows, int cols) const {
+        constexpr int PLANES = BC / Chunk<T>::kImages;
+        const int np = n + 4;
+        const int r_end = min(rows, n + 2 - oy0), c_end = min(cols, n + 2 - ox0);
+        if (r_end <= 0 || c_end <= 0) return;
+        const int total = r_end * c_end;
+        const int step_i = 256 / c_end, step_j = 256 - step_i * c_end;
+        const int i0 = threadIdx.x / c_end, j0 = threadIdx.x - i0 * c_end;
+        const uint4 *src0 = base + (oy0 + 2) * np + (ox0 + 2);
+#pragma unroll
+        for (int q = 0; q < PLANES; ++q) {
+            int i = i0, jj = j0;
+            const uint4 *src = src0 + q * plane_stride;
+            for (int idx = threadIdx.x; idx < total; idx += 256) {
+                lds[q * plane_chunks + i * pitch + jj] = src[i * np + jj];
+                jj += step_j;
+                i += step_i;
+                if (jj >= c_end) {
+                    jj -= c_end;
+                    ++i;
+                }
+            }
+        }
+    }
+};
 
 // One block processes one work item (up to 4 angles x 64 bins; wave w <-> angle a0+w, lane
 // l <-> bin d0+l) x BC images.  The rays march through the image in slabs of
@@ -55,10 +129,10 @@ __device__ __forceinline__ void stage_window(uint4 *lds, int plane_chunks, int p
 // FP64 boundary crossings (consistent across slabs); sample positions are FP64
 // offsets from the lane's first cell in the slab and only the bilinear fractions
 // drop to FP32, so weights are accurate to FP32 rounding anywhere in the image.
-template <typename T, int BC>
+template <typename T, int BC, class Source>
 __device__ __forceinline__ void fwd_item(const Geom &g, const FwdItem &it, const int2 *__restrict__ ranges,
-                                         const T *__restrict__ x, T *__restrict__ y, int batch,
-                                         int b0, float scale_dt, int tile_t, uint4 *lds) {
+                                         const ImageSet<T, BC> &imgs, const Source &src, int tile_t,
+                                         uint4 *lds) {
     constexpr int CH = Chunk<T>::kImages;
     constexpr int PLANES = BC / CH;
     static_assert(BC % CH == 0, "BC must be a multiple of the images per chunk");
@@ -68,10 +142,6 @@ __device__ __forceinline__ void fwd_item(const Geom &g, const FwdItem &it, const
     const bool active = wave < it.na && lane < it.nd;
     const int a = it.a0 + min(wave, it.na - 1), d = it.d0 + min(lane, it.nd - 1);
     const int n = g.n;
-    const size_t img = (size_t)n * n;
-    const T *img_base[BC];
-#pragma unroll
-    for (int e = 0; e < BC; ++e) img_base[e] = x + (size_t)min(b0 + e, batch - 1) * img;
 
     // the lane's ray, oriented so that the march coordinate grows with the sample index
     double4 r = ray_params(g, a, d);
@@ -98,37 +168,41 @@ __device__ __forceinline__ void fwd_item(const Geom &g, const FwdItem &it, const
         const int rows = it.axis ? tr.y - tr.x + 1 : kSlabH + 3;
 
         __syncthreads();                                // previous slab fully consumed
-        stage_window<T, PLANES>(lds, plane_chunks, pitch, img_base, n, ox0, oy0, rows, cols);
+        src.stage(lds, plane_chunks, pitch, ox0, oy0, rows, cols);
         __syncthreads();
 
         // samples of this ray whose march coordinate lies in [m_lo, m_lo + kSlabH)
         const int jb = max(jlo, (int)ceil(((double)m_lo - om) * inv_sm));
         const int je = min(jhi + 1, (int)ceil(((double)(m_lo + kSlabH) - om) * inv_sm));
         if (jb >= je) continue;
+        // anchor: one cell below the lowest cell over the slab's samples, so that every
+        // sample offset is >= 1 (truncation is floor even after rounding) and small
+        // (FP64; only the fraction drops to FP32)
         const double px64 = fma((double)jb, r.z, r.x) - (double)ox0;
         const double py64 = fma((double)jb, r.w, r.y) - (double)oy0;
-        const double bx = floor(px64), by = floor(py64);
+        const double lx64 = fma((double)(je - 1 - jb), r.z, px64);
+        const double ly64 = fma((double)(je - 1 - jb), r.w, py64);
+        const double bx = floor(fmin(px64, lx64)) - 1.0, by = floor(fmin(py64, ly64)) - 1.0;
         const double fxa = px64 - bx, fya = py64 - by;
-        const int base = (int)by * pitch + (int)bx;
-        const int max_addr = max((rows - 2) * pitch + (cols - 2), 0);
+        const uint4 *lane_lds = lds + ((int)by * pitch + (int)bx);
         // the slab's samples are summed separately and then added to the ray total
         // (two-level summation keeps FP32 rounding of long rays small)
         float part[BC];
 #pragma unroll
         for (int i = 0; i < BC; ++i) part[i] = 0.0f;
-        double jd = 0.0;
-        for (int j = jb; j < je; ++j, jd += 1.0) {
+        const int cnt = je - jb;
+        for (int j = 0; j < cnt; ++j) {
+            const double jd = (double)j;
             const double px = fma(jd, r.z, fxa), py = fma(jd, r.w, fya);
-            const double cx = floor(px), cy = floor(py);
-            const float fx = (float)(px - cx), fy = (float)(py - cy);
+            const int cx = (int)px, cy = (int)py;                       // px, py >= 1
+            const float fx = (float)__builtin_amdgcn_fract(px), fy = (float)__builtin_amdgcn_fract(py);
             const float gx = 1.0f - fx, gy = 1.0f - fy;
             const float w00 = __fmul_rn(gx, gy), w01 = __fmul_rn(fx, gy);
             const float w10 = __fmul_rn(gx, fy), w11 = __fmul_rn(fx, fy);
-            int addr = base + __mul24((int)cy, pitch) + (int)cx;
-            addr = min(max(addr, 0), max_addr);         // memory safety; real samples are inside
+            const uint4 *pt = lane_lds + (__mul24(cy, pitch) + cx);
 #pragma unroll
             for (int q = 0; q < PLANES; ++q) {
-                const uint4 *pl = lds + q * plane_chunks + addr;
+                const uint4 *pl = pt + q * plane_chunks;
                 const uint4 t00 = pl[0], t01 = pl[1], t10 = pl[pitch], t11 = pl[pitch + 1];
                 float *aq = part + q * CH;
                 Chunk<T>::fma(w00, t00, aq);
@@ -143,9 +217,8 @@ __device__ __forceinline__ void fwd_item(const Geom &g, const FwdItem &it, const
     if (!active) return;
 #pragma unroll
     for (int i = 0; i < BC; ++i)
-        if (b0 + i < batch)
-            Store<T>::store(y + ((size_t)(b0 + i) * g.n_angles + a) * g.det_count + d,
-                            acc[i] * scale_dt);
+        if (i < imgs.count)
+            Store<T>::store(imgs.out[i] + (size_t)a * g.det_count + d, acc[i] * imgs.scale[i]);
 }
 
 // ------------------------------------------------------------------ backprojection
@@ -160,9 +233,8 @@ __device__ __forceinline__ void fwd_item(const Geom &g, const FwdItem &it, const
 // tent weights are accurate to FP32 rounding.  The NB bin weights are then applied
 // to BC images with 16-byte LDS reads.  No atomics.
 template <typename T, int BC, int NB, int NK>
-__device__ __forceinline__ void bp_tile_par(const Geom &g, int tile, int b0, const T *__restrict__ y,
-                                            T *__restrict__ x, int batch, float scale_dt, int W,
-                                            uint4 *lds) {
+__device__ __forceinline__ void bp_tile_par(const Geom &g, int tile, const ImageSet<T, BC> &imgs,
+                                            int W, uint4 *lds) {
     __shared__ int wlo_s[kBpAngles];
     constexpr int CH = Chunk<T>::kImages;
     constexpr int PLANES = BC / CH;
@@ -173,11 +245,8 @@ __device__ __forceinline__ void bp_tile_par(const Geom &g, int tile, int b0, con
     const int c = tx0 + (threadIdx.x % kBpTile), r = ty0 + (threadIdx.x / kBpTile);
     const double qx = (double)c - g.cn, qy = (double)r - g.cn;
     const double tcx = tx0 + 0.5 * (kBpTile - 1) - g.cn, tcy = ty0 + 0.5 * (kBpTile - 1) - g.cn;
-    const size_t sino = (size_t)A * D;
     const int per_plane = kBpAngles * W;
-    const T *img_base[BC];
-#pragma unroll
-    for (int e = 0; e < BC; ++e) img_base[e] = y + (size_t)min(b0 + e, batch - 1) * sino;
+    const T *const *img_base = imgs.in;
     const float dt = (float)g.step, sp = (float)g.spacing;
 
     float acc[BC];
@@ -261,8 +330,8 @@ __device__ __forceinline__ void bp_tile_par(const Geom &g, int tile, int b0, con
     if (c >= n || r >= n) return;
 #pragma unroll
     for (int i = 0; i < BC; ++i)
-        if (b0 + i < batch)
-            Store<T>::store(x + (size_t)(b0 + i) * n * n + (size_t)r * n + c, acc[i] * scale_dt);
+        if (i < imgs.count)
+            Store<T>::store(imgs.out[i] + (size_t)r * n + c, acc[i] * imgs.scale[i]);
 }
 
 // Fan beam.  Same tiling as the parallel kernel; every bin has its own ray, so the
@@ -273,9 +342,8 @@ __device__ __forceinline__ void bp_tile_par(const Geom &g, int tile, int b0, con
 // candidate samples around the pixel's position along that ray are evaluated with
 // FP64 anchors and FP32 offsets, exactly as in the parallel kernel.
 template <typename T, int BC, int NB, int NK>
-__device__ __forceinline__ void bp_tile_fan(const Geom &g, int tile, int b0, const T *__restrict__ y,
-                                            T *__restrict__ x, int batch, float scale_dt, int W,
-                                            uint4 *lds) {
+__device__ __forceinline__ void bp_tile_fan(const Geom &g, int tile, const ImageSet<T, BC> &imgs,
+                                            int W, uint4 *lds) {
     __shared__ int wlo_s[kBpAnglesFan];
     constexpr int CH = Chunk<T>::kImages;
     constexpr int PLANES = BC / CH;
@@ -285,12 +353,9 @@ __device__ __forceinline__ void bp_tile_fan(const Geom &g, int tile, int b0, con
     const int tx0 = (tile % tiles_x) * kBpTile, ty0 = (tile / tiles_x) * kBpTile;
     const int c = tx0 + (threadIdx.x % kBpTile), r = ty0 + (threadIdx.x / kBpTile);
     const double qx = (double)c - g.cn, qy = (double)r - g.cn;
-    const size_t sino = (size_t)A * D;
     const int per_plane = kBpAnglesFan * W;
     double4 *rays_s = reinterpret_cast<double4 *>(lds + PLANES * per_plane);
-    const T *img_base[BC];
-#pragma unroll
-    for (int e = 0; e < BC; ++e) img_base[e] = y + (size_t)min(b0 + e, batch - 1) * sino;
+    const T *const *img_base = imgs.in;
     const double is2 = g.inv_step * g.inv_step;
 
     float acc[BC];
@@ -383,8 +448,8 @@ __device__ __forceinline__ void bp_tile_fan(const Geom &g, int tile, int b0, con
     if (c >= n || r >= n) return;
 #pragma unroll
     for (int i = 0; i < BC; ++i)
-        if (b0 + i < batch)
-            Store<T>::store(x + (size_t)(b0 + i) * n * n + (size_t)r * n + c, acc[i] * scale_dt);
+        if (i < imgs.count)
+            Store<T>::store(imgs.out[i] + (size_t)r * n + c, acc[i] * imgs.scale[i]);
 }
 
 }  // namespace radon
