@@ -25,6 +25,39 @@ sys.path.insert(0, ROOT)
 METRIC = "fwd+backproj projections/s & rays/s, 512², 720 angles, batch 128; HBM GB/s"
 PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak
 PEAK_HBM_GBS = 8000.0         # MI355X HBM3E
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "hbm_traffic_batch128_512.md")
+
+
+def kernel_sources_sha256():
+    """SHA-256 over the library's kernel and planner sources (name + bytes, sorted)."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2009_14788_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            h.update(name.encode())
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(direction, shape):
+    """HBM bytes per launch of one direction from the committed counter record, or
+    None when there is no record, the launch shape differs, or the kernel sources
+    changed since the counters were taken."""
+    import re
+    try:
+        text = open(TRAFFIC_RECORD).read()
+    except OSError:
+        return None
+    m = re.search(r"traffic-record sources_sha256=(\w+) (.*?)-->", text)
+    if not m or m.group(1) != kernel_sources_sha256():
+        return None
+    fields = dict(kv.split("=", 1) for kv in m.group(2).split())
+    if fields.get(f"{direction}_shape") != shape:
+        return None
+    v = fields.get(f"{direction}_bytes")
+    return int(v) if v is not None else None
 
 
 def support_samples(n, angles, det_count, spacing, step, beam="parallel", S=0.0, E=0.0):
@@ -91,7 +124,7 @@ def main():
     ap.add_argument("--quick", action="store_true",
                     help="only the headline workload (skip the other workloads and forms)")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="after the benchmark, run a plain 1 GiB device-to-device copy three times "
+                    help="after the benchmark, run a plain elementwise copy of 1 GiB three times "
                          "(reference dispatch for scaling HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -156,10 +189,17 @@ def main():
     dom = "forward" if fwd_ms >= bp_ms else "backprojection"
     dom_ms = max(fwd_ms, bp_ms)
     achieved = flop / (dom_ms * 1e-3) / 1e12
+    info = op.plan_info(torch.float32, B)[dom]
+    shape = f"{info['variant']},{info['images']},{info['angles']},{info['staging']}"
+    kernels = {("forward", 1, 1): "interleave_images + fwd_tiled_il", ("forward", 1, 0): "fwd_tiled",
+               ("backprojection", 1, 0): "bp_tiled_par"}.get(
+                   (dom, info["variant"], info["staging"]), f"{dom}_direct")
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
-            "kernel": dom, "kernel_ms": round(dom_ms, 4),
-            "work": f"8 flop per (image, ray sample); {samples:.4e} samples per launch"}
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+            "traffic": recorded_traffic(dom, shape),
+            "kernel": f"{dom}: {kernels}", "kernel_ms": round(dom_ms, 4), "shape": shape,
+            "work": f"8 flop per (image, ray sample); {samples:.4e} samples per launch",
+            "algorithmic_bytes": int(bytes_dir)}
 
     # sampled correctness of this very output against the oracle (8 rays)
     import oracle
@@ -187,10 +227,11 @@ def main():
     if not args.quick:
         out["workloads"] = variants(op, x, x_np, B, A, D)
     if args.copy_calibration:
-        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)     # 1 GiB
+        # a plain elementwise kernel that reads 1 GiB once and writes 1 GiB once
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
     if not args.no_cpu:

@@ -126,8 +126,11 @@ int radon_dot_f64(const void *a, const void *b, int64_t n, int32_t dtype, double
 int radon_release_plans(void);
 
 /* Launch shape chosen for a geometry/dtype/batch (after radon_prepare):
- * out[0..3] = forward {images per thread, angles per block, rays per block, variant},
- * out[4..7] = the same for the backprojection. */
+ * out[0..3] = forward {images per thread, angles per block, staging, variant},
+ * out[4..7] = the same for the backprojection.  variant: 0 = direct kernel, 1 = tiled
+ * kernel.  staging: 1 when the tiled forward first copies the batch into a
+ * zero-bordered, image-interleaved workspace, else 0 (always 0 for the
+ * backprojection).  Builds the plan when missing; status codes as radon_forward. */
 int radon_plan_info(const radon_geometry_t *geometry, int32_t dtype, int32_t batch,
                     int32_t *out8);
 

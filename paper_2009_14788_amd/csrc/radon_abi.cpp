@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
@@ -15,6 +16,7 @@
 #include <vector>
 
 #include "../../include/radon.h"
+#include "radon_autotune.hpp"
 #include "radon_batched.hpp"
 #include "radon_launch.hpp"
 #include "radon_plan.hpp"
@@ -245,6 +247,7 @@ int get_plan(const radon_geometry_t *g, hipStream_t stream, Plan **out) {
     std::unique_ptr<Plan> p;
     int rc = build_plan(g, device, p);
     if (rc != RADON_OK) return rc;
+    p->key_hash = PlanKeyHash()(key);
     *out = p.get();
     g_plans.emplace(std::move(key), std::move(p));
     return RADON_OK;
@@ -533,6 +536,33 @@ static int release_all() {
     return RADON_OK;
 }
 
+// Launch shapes for a call: the autotuned ones for this storage type and batch class
+// when radon_prepare has tuned them, else the plan's defaults.
+// RADON_FORCE_SHAPE="fi,fs,bi,ba" overrides both (used to test every variant).
+static void call_shapes(Plan *p, int dtype, int batch, LaunchShape &fwd, LaunchShape &bp) {
+    fwd = p->fwd_shape;
+    bp = p->bp_shape;
+    if (const char *f = std::getenv("RADON_FORCE_SHAPE")) {
+        int fi, fs, bi, ba;
+        if (std::sscanf(f, "%d,%d,%d,%d", &fi, &fs, &bi, &ba) == 4) {
+            fwd.images = fi;
+            fwd.stage = fs;
+            bp.images = bi;
+            if (!p->geom.fan) bp.angles = ba;
+            return;
+        }
+    }
+    std::lock_guard<std::mutex> lock(g_mutex);
+    auto it = p->tuned.find({dtype, batch_class(batch)});
+    if (it == p->tuned.end() || !it->second.valid) return;
+    fwd.variant = it->second.fwd_variant;
+    bp.variant = it->second.bp_variant;
+    fwd.images = it->second.fwd_images;
+    fwd.stage = it->second.fwd_stage;
+    bp.images = it->second.bp_images;
+    bp.angles = it->second.bp_angles;
+}
+
 }  // namespace radon
 
 using namespace radon;
@@ -549,6 +579,26 @@ int radon_prepare(const radon_geometry_t *geometry, int32_t dtype, int32_t batch
     Plan *p = nullptr;
     rc = get_plan(geometry, nullptr, &p);
     if (rc != RADON_OK) return rc;
+    const char *tune = std::getenv("RADON_AUTOTUNE");
+    const bool want = !(tune && std::strcmp(tune, "0") == 0);
+    if (want && batch > 0) {
+        bool have;
+        {
+            std::lock_guard<std::mutex> lock(g_mutex);
+            auto it = p->tuned.find({dtype, batch_class(batch)});
+            have = it != p->tuned.end() && it->second.valid;
+        }
+        if (!have) {
+            size_t ws_bytes = 0;
+            void *ws = forward_workspace(nullptr, interleaved_bytes(geometry->image_size, batch, dtype),
+                                         &ws_bytes);
+            TunedShapes t;
+            if (autotune(*p, dtype, batch, ws, ws_bytes, t) == 0) {
+                std::lock_guard<std::mutex> lock(g_mutex);
+                p->tuned[{dtype, batch_class(batch)}] = t;
+            }
+        }
+    }
     return hipDeviceSynchronize() == hipSuccess ? RADON_OK : RADON_ERR_HIP;
 }
 
@@ -563,12 +613,14 @@ int radon_forward(const radon_geometry_t *geometry, const void *x, void *y, int3
     hipStream_t s = static_cast<hipStream_t>(stream);
     Plan *p = nullptr;
     if ((rc = get_plan(geometry, s, &p)) != RADON_OK) return rc;
+    LaunchShape fwd, bp;
+    call_shapes(p, dtype, batch, fwd, bp);
     void *ws = nullptr;
     size_t ws_bytes = 0;
-    if (p->fwd_shape.variant == VARIANT_TILED && p->fwd_work.n_items > 0 && !p->no_interleave)
+    if (fwd.variant == VARIANT_TILED && fwd.stage && p->fwd_work.n_items > 0 && !p->no_interleave)
         ws = forward_workspace(s, interleaved_bytes(geometry->image_size, batch, dtype), &ws_bytes);
-    hipError_t e = launch_forward(p->geom, p->fwd_work, dtype, p->fwd_shape, x, y, batch, scale,
-                                  ws, ws_bytes, s);
+    hipError_t e = launch_forward(p->geom, p->fwd_work, dtype, fwd, x, y, batch, scale, ws,
+                                  ws_bytes, s);
     return e == hipSuccess ? RADON_OK : RADON_ERR_HIP;
 }
 
@@ -583,7 +635,9 @@ int radon_backproject(const radon_geometry_t *geometry, const void *y, void *x, 
     hipStream_t s = static_cast<hipStream_t>(stream);
     Plan *p = nullptr;
     if ((rc = get_plan(geometry, s, &p)) != RADON_OK) return rc;
-    hipError_t e = launch_backproject(p->geom, p->bp_work, dtype, p->bp_shape, y, x, batch, scale, s);
+    LaunchShape fwd, bp;
+    call_shapes(p, dtype, batch, fwd, bp);
+    hipError_t e = launch_backproject(p->geom, p->bp_work, dtype, bp, y, x, batch, scale, s);
     return e == hipSuccess ? RADON_OK : RADON_ERR_HIP;
 }
 
@@ -620,11 +674,15 @@ int radon_plan_info(const radon_geometry_t *geometry, int32_t dtype, int32_t bat
     if (!out8 || batch < 0) return RADON_ERR_INVALID_ARG;
     Plan *p = nullptr;
     if ((rc = get_plan(geometry, nullptr, &p)) != RADON_OK) return rc;
-    const LaunchShape *sh[2] = {&p->fwd_shape, &p->bp_shape};
+    LaunchShape fwd, bp;
+    call_shapes(p, dtype, std::max(batch, 1), fwd, bp);
+    bp.stage = 0;
+    if (fwd.variant != VARIANT_TILED || p->no_interleave) fwd.stage = 0;
+    const LaunchShape *sh[2] = {&fwd, &bp};
     for (int i = 0; i < 2; ++i) {
         out8[4 * i + 0] = sh[i]->images;
         out8[4 * i + 1] = sh[i]->angles;
-        out8[4 * i + 2] = sh[i]->rays;
+        out8[4 * i + 2] = sh[i]->stage;
         out8[4 * i + 3] = sh[i]->variant;
     }
     return RADON_OK;

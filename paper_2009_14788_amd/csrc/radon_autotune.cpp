@@ -1,0 +1,170 @@
+// Autotuner: picks the launch shape of each direction for a (plan, storage type,
+// batch size class) by timing the candidates on the device with HIP events.
+//
+// Forward candidates: images per lane {8, 4 (FP32 only), 16 (16-bit only)} x slab
+// staging {interleaved copy, caller's images}, and the direct kernel.
+// Backprojection candidates: images per lane {32, 16} x angles per LDS block {8, 4}
+// (parallel beam; the fan beam's block is fixed at 4 because its rays are staged
+// too), and the direct kernel.  The direct kernels win on tiny problems, where the
+// tiled kernels' sequential slabs and angle blocks are latency-bound.  Results live in the plan
+// and, when RADON_TUNE_CACHE names a file, in that file (one line per entry:
+// "<key> <fwd variant> <fwd images> <fwd stage> <bp variant> <bp images> <bp angles>"),
+// so later processes skip the timing.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "radon_autotune.hpp"
+
+namespace radon {
+
+int batch_class(int batch) {
+    int c = 1;
+    while (c < batch && c < (1 << 20)) c <<= 1;
+    return c;
+}
+
+static std::string tune_key(const Plan &p, int dtype, int bclass) {
+    std::ostringstream k;
+    k << "g" << std::hex << p.key_hash << std::dec << "_n" << p.geom.n << "_a" << p.geom.n_angles
+      << "_d" << p.geom.det_count << "_f" << p.geom.fan << "_t" << dtype << "_b" << bclass;
+    return k.str();
+}
+
+static bool cache_lookup(const std::string &key, TunedShapes &out) {
+    const char *path = std::getenv("RADON_TUNE_CACHE");
+    if (!path || !*path) return false;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        std::istringstream ls(line);
+        std::string k;
+        int fv, fi, fs, bv, bi, ba;
+        if (!(ls >> k >> fv >> fi >> fs >> bv >> bi >> ba) || k != key) continue;
+        out.fwd_variant = fv;
+        out.bp_variant = bv;
+        out.fwd_images = fi;
+        out.fwd_stage = fs;
+        out.bp_images = bi;
+        out.bp_angles = ba;
+        return true;
+    }
+    return false;
+}
+
+static void cache_store(const std::string &key, const TunedShapes &t) {
+    const char *path = std::getenv("RADON_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::ofstream f(path, std::ios::app);
+    f << key << " " << t.fwd_variant << " " << t.fwd_images << " " << t.fwd_stage << " "
+      << t.bp_variant << " " << t.bp_images << " " << t.bp_angles << "\n";
+}
+
+// Average milliseconds of `reps` launches after one warm-up; a negative value when
+// a launch fails.
+template <class F>
+static float time_launches(F launch, hipStream_t s, int reps = 3) {
+    if (launch() != hipSuccess) return -1.0f;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return -1.0f;
+    if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return -1.0f; }
+    float ms = -1.0f;
+    bool ok = hipEventRecord(a, s) == hipSuccess;
+    for (int i = 0; ok && i < reps; ++i) ok = launch() == hipSuccess;
+    ok = ok && hipEventRecord(b, s) == hipSuccess && hipEventSynchronize(b) == hipSuccess &&
+         hipEventElapsedTime(&ms, a, b) == hipSuccess;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return ok ? ms / reps : -1.0f;
+}
+
+int autotune(Plan &p, int dtype, int batch, void *ws, size_t ws_bytes, TunedShapes &out) {
+    const int bclass = batch_class(batch);
+    const std::string key = tune_key(p, dtype, bclass);
+    out = TunedShapes{};
+    out.fwd_images = p.fwd_shape.images;
+    out.fwd_stage = p.fwd_shape.stage;
+    out.bp_images = p.bp_shape.images;
+    out.bp_angles = p.bp_shape.angles;
+    out.fwd_variant = p.fwd_shape.variant;
+    out.bp_variant = p.bp_shape.variant;
+    if (cache_lookup(key, out)) {
+        out.valid = true;
+        return 0;
+    }
+    const size_t es = dtype == F32 ? 4 : 2;
+    const size_t xb = (size_t)batch * p.geom.n * p.geom.n * es;
+    const size_t yb = (size_t)batch * p.geom.n_angles * p.geom.det_count * es;
+    void *x = nullptr, *y = nullptr;
+    if (hipMalloc(&x, std::max<size_t>(xb, 16)) != hipSuccess) return -1;
+    if (hipMalloc(&y, std::max<size_t>(yb, 16)) != hipSuccess) { (void)hipFree(x); return -1; }
+    (void)hipMemset(x, 0, xb);
+    (void)hipMemset(y, 0, yb);
+    hipStream_t s = nullptr;
+
+    if (p.fwd_shape.variant == VARIANT_TILED) {
+        std::vector<int> imgs = dtype == F32 ? std::vector<int>{8, 4} : std::vector<int>{8, 16};
+        float best = time_launches([&] {
+            LaunchShape sh = p.fwd_shape;
+            sh.variant = VARIANT_DIRECT;
+            return launch_forward(p.geom, p.fwd_work, dtype, sh, x, y, batch, 1.0f, ws, ws_bytes, s);
+        }, s);
+        out.fwd_variant = VARIANT_DIRECT;
+        for (int im : imgs)
+            for (int st : {1, 0}) {
+                if (st == 1 && p.no_interleave) continue;
+                LaunchShape sh = p.fwd_shape;
+                sh.images = im;
+                sh.stage = st;
+                const float ms = time_launches([&] {
+                    return launch_forward(p.geom, p.fwd_work, dtype, sh, x, y, batch, 1.0f, ws,
+                                          ws_bytes, s);
+                }, s);
+                if (ms > 0.0f && (best < 0.0f || ms < best)) {
+                    best = ms;
+                    out.fwd_variant = VARIANT_TILED;
+                    out.fwd_images = im;
+                    out.fwd_stage = st;
+                }
+            }
+    }
+    if (p.bp_shape.variant == VARIANT_TILED) {
+        float best = time_launches([&] {
+            LaunchShape sh = p.bp_shape;
+            sh.variant = VARIANT_DIRECT;
+            return launch_backproject(p.geom, p.bp_work, dtype, sh, y, x, batch, 1.0f, s);
+        }, s);
+        out.bp_variant = VARIANT_DIRECT;
+        const std::vector<int> abs = p.geom.fan ? std::vector<int>{kBpAnglesFan}
+                                                : std::vector<int>{kBpAngles, 4};
+        for (int im : {32, 16})
+            for (int ab : abs) {
+                LaunchShape sh = p.bp_shape;
+                sh.images = im;
+                sh.angles = ab;
+                const float ms = time_launches([&] {
+                    return launch_backproject(p.geom, p.bp_work, dtype, sh, y, x, batch, 1.0f, s);
+                }, s);
+                if (ms > 0.0f && (best < 0.0f || ms < best)) {
+                    best = ms;
+                    out.bp_variant = VARIANT_TILED;
+                    out.bp_images = im;
+                    out.bp_angles = ab;
+                }
+            }
+    }
+    (void)hipDeviceSynchronize();
+    (void)hipFree(x);
+    (void)hipFree(y);
+    out.valid = true;
+    cache_store(key, out);
+    return 0;
+}
+
+}  // namespace radon

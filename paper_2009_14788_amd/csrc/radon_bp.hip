@@ -98,14 +98,14 @@ __global__ __launch_bounds__(256) void bp_direct(Geom g, const T *__restrict__ y
 
 // ------------------------------------------------------------------ tiled variant
 // One block = one 16x16 pixel tile x BC images (blockIdx.y selects the images).
-template <typename T, int BC, int NB, int NK>
+template <typename T, int BC, int NB, int NK, int AB>
 __global__ __launch_bounds__(256) void bp_tiled_par(Geom g, const T *__restrict__ y,
                                                     T *__restrict__ x, int batch, float scale_dt,
                                                     int W) {
     extern __shared__ uint4 lds[];
     const ImageSet<T, BC> imgs = contiguous_images<T, BC>(
         y, (size_t)g.n_angles * g.det_count, x, (size_t)g.n * g.n, batch, blockIdx.y * BC, scale_dt);
-    bp_tile_par<T, BC, NB, NK>(g, blockIdx.x, imgs, W, lds);
+    bp_tile_par<T, BC, NB, NK, AB>(g, blockIdx.x, imgs, W, lds);
 }
 
 template <typename T, int BC, int NB, int NK>
@@ -129,15 +129,21 @@ static hipError_t launch_bp_direct(const Geom &g, const void *y, void *x, int ba
 }
 
 template <typename T, int BC>
-static hipError_t launch_bp_tiled(const Geom &g, const BpWork &work, const void *y, void *x,
-                                  int batch, float scale_dt, hipStream_t s) {
+static hipError_t launch_bp_tiled(const Geom &g, const BpWork &work, int angles, const void *y,
+                                  void *x, int batch, float scale_dt, hipStream_t s) {
     constexpr int PLANES = BC / Chunk<T>::kImages;
     const int tiles = ((g.n + kBpTile - 1) / kBpTile) * ((g.n + kBpTile - 1) / kBpTile);
     dim3 grid(tiles, (batch + BC - 1) / BC);
     if (!g.fan) {
-        const size_t lds = (size_t)PLANES * kBpAngles * work.window * sizeof(uint4);
-        hipLaunchKernelGGL((bp_tiled_par<T, BC, 3, 3>), grid, dim3(256), lds, s, g, (const T *)y,
-                           (T *)x, batch, scale_dt, work.window);
+        if (angles <= 4) {
+            const size_t lds = (size_t)PLANES * 4 * work.window * sizeof(uint4);
+            hipLaunchKernelGGL((bp_tiled_par<T, BC, 3, 3, 4>), grid, dim3(256), lds, s, g,
+                               (const T *)y, (T *)x, batch, scale_dt, work.window);
+        } else {
+            const size_t lds = (size_t)PLANES * kBpAngles * work.window * sizeof(uint4);
+            hipLaunchKernelGGL((bp_tiled_par<T, BC, 3, 3, kBpAngles>), grid, dim3(256), lds, s, g,
+                               (const T *)y, (T *)x, batch, scale_dt, work.window);
+        }
     } else {
         const size_t lds = (size_t)PLANES * kBpAnglesFan * work.window * sizeof(uint4) +
                            (size_t)kBpAnglesFan * work.window * sizeof(double4);
@@ -156,10 +162,18 @@ hipError_t launch_backproject(const Geom &g, const BpWork &work, int dtype, cons
     // every matrix entry carries the step length: R = step * (sum of sample weights)
     const float scale_dt = (float)(scale * g.step);
     if (shape.variant == VARIANT_TILED && work.window > 0) {
+        const bool wide = shape.images >= 32;
+        const int ab = shape.angles;
         switch (dtype) {
-        case F32: return launch_bp_tiled<float, 32>(g, work, y, x, batch, scale_dt, s);
-        case F16: return launch_bp_tiled<__half, 32>(g, work, y, x, batch, scale_dt, s);
-        case BF16: return launch_bp_tiled<bf16_t, 32>(g, work, y, x, batch, scale_dt, s);
+        case F32:
+            return wide ? launch_bp_tiled<float, 32>(g, work, ab, y, x, batch, scale_dt, s)
+                        : launch_bp_tiled<float, 16>(g, work, ab, y, x, batch, scale_dt, s);
+        case F16:
+            return wide ? launch_bp_tiled<__half, 32>(g, work, ab, y, x, batch, scale_dt, s)
+                        : launch_bp_tiled<__half, 16>(g, work, ab, y, x, batch, scale_dt, s);
+        case BF16:
+            return wide ? launch_bp_tiled<bf16_t, 32>(g, work, ab, y, x, batch, scale_dt, s)
+                        : launch_bp_tiled<bf16_t, 16>(g, work, ab, y, x, batch, scale_dt, s);
         default: return hipErrorInvalidValue;
         }
     }

@@ -82,11 +82,12 @@ __global__ __launch_bounds__(256) void fwd_tiled(Geom g, FwdWork work, const T *
     fwd_item<T, BC>(g, it, work.ranges, imgs, src, tile_t, lds);
 }
 
-// Same, staging from the interleaved, zero-bordered copy xi of the batch.
+// Same, staging from the interleaved, zero-bordered copies of the batch: xi holds
+// the row-major copy [groups][N+4][N+4] followed by the transposed copy.
 template <typename T, int BC>
 __global__ __launch_bounds__(256) void fwd_tiled_il(Geom g, FwdWork work, const uint4 *__restrict__ xi,
                                                     T *__restrict__ y, int batch, float scale_dt,
-                                                    int tile_t) {
+                                                    int tile_t, int groups) {
     extern __shared__ uint4 lds[];
     constexpr int CH = Chunk<T>::kImages;
     const FwdItem it = work.items[blockIdx.x];
@@ -95,39 +96,53 @@ __global__ __launch_bounds__(256) void fwd_tiled_il(Geom g, FwdWork work, const 
     const ImageSet<T, BC> imgs = contiguous_images<T, BC>(
         y, 0, y, (size_t)g.n_angles * g.det_count, batch, b0, scale_dt);
     const int plane = (g.n + 4) * (g.n + 4);
-    const InterleavedSource<T, BC> src{xi + (size_t)(b0 / CH) * plane, g.n, plane};
+    const uint4 *first = xi + (size_t)(b0 / CH) * plane;
+    const InterleavedSource<T, BC> src{first, first + (size_t)groups * plane, g.n, plane};
     fwd_item<T, BC>(g, it, work.ranges, imgs, src, tile_t, lds);
 }
 
-// Interleave a batch x[B][N][N] into xi[ceil(B/CH)][N+4][N+4] chunks of CH images
-// with a zero border of 2 pixels (images past B are zero).
+// Interleave a batch x[B][N][N] into chunks of CH images with a zero border of 2
+// pixels (images past B are zero): xi[grp][y+2][x+2] (row-major copy) and
+// xi[groups + grp][x+2][y+2] (transposed copy).  One block = one 16 x 16 chunk tile
+// of one group, transposed through LDS so both stores are coalesced.
+constexpr int kIlTile = 16;
 template <typename T>
 __global__ __launch_bounds__(256) void interleave_images(const T *__restrict__ x, uint4 *__restrict__ xi,
                                                          int n, int batch, int groups) {
     constexpr int CH = Chunk<T>::kImages;
+    __shared__ uint4 tile[kIlTile][kIlTile + 1];
     const int np = n + 4;
-    const int plane = np * np;
-    const long long total = (long long)groups * plane;
-    for (long long c = (long long)blockIdx.x * 256 + threadIdx.x; c < total;
-         c += (long long)gridDim.x * 256) {
-        const int grp = (int)(c / plane);
-        const int rem = (int)(c - (long long)grp * plane);
-        const int yy = rem / np - 2, xx = rem % np - 2;
-        const bool inside = (unsigned)xx < (unsigned)n && (unsigned)yy < (unsigned)n;
+    const int tiles = (np + kIlTile - 1) / kIlTile;
+    const int grp = blockIdx.y;
+    const int ty0 = (blockIdx.x / tiles) * kIlTile, tx0 = (blockIdx.x % tiles) * kIlTile;
+    const int tx = threadIdx.x % kIlTile, ty = threadIdx.x / kIlTile;
+    const size_t plane = (size_t)np * np;
+    {   // padded row-major coordinates (xx, yy) of this thread's chunk
+        const int xx = tx0 + tx, yy = ty0 + ty;
+        const int ix = xx - 2, iy = yy - 2;
+        const bool inside = (unsigned)ix < (unsigned)n && (unsigned)iy < (unsigned)n;
         T v[CH];
 #pragma unroll
         for (int e = 0; e < CH; ++e) {
             const int b = grp * CH + e;
-            v[e] = (inside && b < batch) ? x[(size_t)b * n * n + (size_t)yy * n + xx] : Chunk<T>::zero();
+            v[e] = (inside && b < batch) ? x[(size_t)b * n * n + (size_t)iy * n + ix] : Chunk<T>::zero();
         }
-        xi[c] = Chunk<T>::pack(v);
+        const uint4 c = Chunk<T>::pack(v);
+        tile[ty][tx] = c;
+        if (xx < np && yy < np) xi[(size_t)grp * plane + (size_t)yy * np + xx] = c;
+    }
+    __syncthreads();
+    {   // transposed copy: row = padded x, column = padded y
+        const int row = tx0 + ty, col = ty0 + tx;
+        if (row < np && col < np)
+            xi[(size_t)(groups + grp) * plane + (size_t)row * np + col] = tile[tx][ty];
     }
 }
 
 size_t interleaved_bytes(int n, int batch, int dtype) {
     const int ch = dtype == F32 ? 4 : 8;
     const size_t groups = ((size_t)batch + 15) / 16 * 16 / ch;   // whole 16-image blocks
-    return groups * (size_t)(n + 4) * (n + 4) * sizeof(uint4);
+    return 2 * groups * (size_t)(n + 4) * (n + 4) * sizeof(uint4);
 }
 
 template <typename T, int BC>
@@ -142,23 +157,23 @@ static hipError_t launch_fwd_direct(const Geom &g, const void *x, void *y, int b
 
 template <typename T, int BC>
 static hipError_t launch_fwd_tiled(const Geom &g, const FwdWork &work, const void *x, void *y,
-                                   int batch, float scale_dt, void *ws, size_t ws_bytes,
+                                   int batch, float scale_dt, int stage, void *ws, size_t ws_bytes,
                                    hipStream_t s) {
     constexpr int CH = Chunk<T>::kImages;
     constexpr int PLANES = BC / CH;
     const size_t lds = (size_t)PLANES * (kSlabH + 3) * work.tile_t * sizeof(uint4);
     dim3 grid(work.n_items, (batch + BC - 1) / BC);
     const int dt = sizeof(T) == 4 ? F32 : F16;
-    if (ws && ws_bytes >= interleaved_bytes(g.n, batch, dt)) {
+    if (ws && stage && ws_bytes >= interleaved_bytes(g.n, batch, dt)) {
+        // groups of the launch: whole BC-image blocks (<= the groups interleaved_bytes counts)
         const int groups = (batch + BC - 1) / BC * PLANES;
-        const long long chunks = (long long)groups * (g.n + 4) * (g.n + 4);
-        const int blocks = (int)std::min<long long>((chunks + 255) / 256, 65536);
-        hipLaunchKernelGGL(interleave_images<T>, dim3(blocks), dim3(256), 0, s, (const T *)x,
-                           (uint4 *)ws, g.n, batch, groups);
+        const int tiles = (g.n + 4 + kIlTile - 1) / kIlTile;
+        hipLaunchKernelGGL(interleave_images<T>, dim3(tiles * tiles, groups), dim3(256), 0, s,
+                           (const T *)x, (uint4 *)ws, g.n, batch, groups);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((fwd_tiled_il<T, BC>), grid, dim3(256), lds, s, g, work,
-                           (const uint4 *)ws, (T *)y, batch, scale_dt, work.tile_t);
+                           (const uint4 *)ws, (T *)y, batch, scale_dt, work.tile_t, groups);
     } else {
         hipLaunchKernelGGL((fwd_tiled<T, BC>), grid, dim3(256), lds, s, g, work, (const T *)x,
                            (T *)y, batch, scale_dt, work.tile_t);
@@ -171,17 +186,20 @@ hipError_t launch_forward(const Geom &g, const FwdWork &work, int dtype, const L
                           size_t ws_bytes, hipStream_t s) {
     const float scale_dt = (float)(scale * g.step);
     if (shape.variant == VARIANT_TILED && work.n_items > 0) {
-        const bool wide = shape.images >= 16;
+        const int st = shape.stage;
         switch (dtype) {
         case F32:
-            return wide ? launch_fwd_tiled<float, 16>(g, work, x, y, batch, scale_dt, ws, ws_bytes, s)
-                        : launch_fwd_tiled<float, 8>(g, work, x, y, batch, scale_dt, ws, ws_bytes, s);
+            if (shape.images <= 4)
+                return launch_fwd_tiled<float, 4>(g, work, x, y, batch, scale_dt, st, ws, ws_bytes, s);
+            return launch_fwd_tiled<float, 8>(g, work, x, y, batch, scale_dt, st, ws, ws_bytes, s);
         case F16:
-            return wide ? launch_fwd_tiled<__half, 16>(g, work, x, y, batch, scale_dt, ws, ws_bytes, s)
-                        : launch_fwd_tiled<__half, 8>(g, work, x, y, batch, scale_dt, ws, ws_bytes, s);
+            if (shape.images >= 16)
+                return launch_fwd_tiled<__half, 16>(g, work, x, y, batch, scale_dt, st, ws, ws_bytes, s);
+            return launch_fwd_tiled<__half, 8>(g, work, x, y, batch, scale_dt, st, ws, ws_bytes, s);
         case BF16:
-            return wide ? launch_fwd_tiled<bf16_t, 16>(g, work, x, y, batch, scale_dt, ws, ws_bytes, s)
-                        : launch_fwd_tiled<bf16_t, 8>(g, work, x, y, batch, scale_dt, ws, ws_bytes, s);
+            if (shape.images >= 16)
+                return launch_fwd_tiled<bf16_t, 16>(g, work, x, y, batch, scale_dt, st, ws, ws_bytes, s);
+            return launch_fwd_tiled<bf16_t, 8>(g, work, x, y, batch, scale_dt, st, ws, ws_bytes, s);
         default: return hipErrorInvalidValue;
         }
     }

@@ -18,6 +18,7 @@ struct LaunchShape {
     int images = 4;       // images per thread (accumulators per lane)
     int angles = 1;       // angles per block (forward: waves; backprojection: LDS angle block)
     int rays = 256;       // forward: bins per block; backprojection: pixels per block
+    int stage = 1;        // forward tiled staging: 1 = interleaved copy, 0 = caller's images
 };
 
 // ------------------------------------------------------------------ tiled forward work

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <utility>
 #include <vector>
 
 #include "../../include/radon.h"
@@ -25,6 +27,14 @@ struct PlanKeyHash {
     size_t operator()(const PlanKey &k) const;
 };
 
+// Launch shapes chosen by the autotuner for one (storage type, batch class).
+struct TunedShapes {
+    bool valid = false;
+    int fwd_variant = VARIANT_TILED, bp_variant = VARIANT_TILED;
+    int fwd_images = 8, fwd_stage = 1;
+    int bp_images = 32, bp_angles = 8;
+};
+
 struct Plan {
     int device = 0;
     Geom geom{};
@@ -36,7 +46,9 @@ struct Plan {
     std::vector<FwdItem> fwd_items_host;   // host copy (work-unit costs of uneven batches)
     BpWork bp_work;
     bool no_interleave = false;            // stage the forward from the caller's images
-    LaunchShape fwd_shape, bp_shape;
+    LaunchShape fwd_shape, bp_shape;       // defaults
+    size_t key_hash = 0;
+    std::map<std::pair<int, int>, TunedShapes> tuned;   // (dtype, batch class) -> shapes
     Plan() = default;
     Plan(const Plan &) = delete;
     Plan &operator=(const Plan &) = delete;

@@ -56,7 +56,13 @@ bool plan_item(int n, int det_count, const std::vector<double4> &rays, int a0, i
         // each side absorbs FP32 rounding of boundary samples
         lo = std::max(lo, -2);
         hi = std::min(hi, n + 1);
-        if (lo == hi) lo = hi - 1;          // keep every staged window at least 2 wide
+        // keep every staged window at least 2 wide and inside [-2, N+1]
+        if (lo == hi) {
+            if (hi < n + 1)
+                ++hi;
+            else
+                --lo;
+        }
         local[s] = make_int2(lo, hi);
         if (lo <= hi) {
             if (first < 0) first = s;

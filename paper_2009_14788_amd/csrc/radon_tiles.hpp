@@ -38,20 +38,24 @@ __device__ __forceinline__ ImageSet<T, BC> contiguous_images(const T *in, size_t
 }
 
 // ------------------------------------------------------------------ forward
-// Slab staging sources.  Both fill a rows x cols pixel window whose element (0, 0) is
-// image pixel (ox0, oy0) into LDS as PLANES planes of 16-byte chunks (Chunk<T>::kImages
-// images per chunk, zero outside the image), rows `pitch` chunks apart and planes
-// `plane_chunks` apart.
+// Slab staging sources.  Both fill a rows x cols pixel window of the staging frame
+// whose element (0, 0) is frame pixel (ox0, oy0) into LDS as PLANES planes of 16-byte
+// chunks (Chunk<T>::kImages images per chunk, zero outside the image), rows `pitch`
+// chunks apart and planes `plane_chunks` apart.  A source with kMarchFrame stages in
+// the march frame: for items that march along x (axis 1) the frame is the transposed
+// image, so every slab is a band of rows; otherwise the frame is the image.
 
-// From the callers' images (any layout of BC image pointers): image base pointers are
-// uniform per plane and image, loads use 32-bit pixel offsets, the (row, col) walk is
-// incremental, and pixels outside the image read a valid address and are replaced by 0.
+// From the callers' images (any layout of BC image pointers), in the image frame:
+// image base pointers are uniform per plane and image, loads use 32-bit pixel
+// offsets, the (row, col) walk is incremental, and pixels outside the image read a
+// valid address and are replaced by 0.
 template <typename T, int BC>
 struct PointerSource {
+    static constexpr bool kMarchFrame = false;
     const T *const *img;
     int n;
     __device__ __forceinline__ void stage(uint4 *lds, int plane_chunks, int pitch, int ox0, int oy0,
-                                          int rows, int cols) const {
+                                          int rows, int cols, int /*axis*/) const {
         constexpr int CH = Chunk<T>::kImages;
         constexpr int PLANES = BC / CH;
         const int total = rows * cols;
@@ -82,42 +86,95 @@ struct PointerSource {
     }
 };
 
-// From an interleaved copy of the batch: chunk (group, y+2, x+2) of a
-// [groups][N+4][N+4] array holds pixel (x, y) of the group's images, with a zero
-// border of 2 pixels, so a window inside [-2, N+1]^2 is copied chunk for chunk with
-// no bounds test.  Window rows/columns beyond [-2, N+1] are never tapped and are
-// not staged.
+// From the interleaved copies of the batch, in the march frame: chunk (group, y+2,
+// x+2) of the row-major copy [groups][N+4][N+4] holds pixel (x, y) of the group's
+// images, and chunk (group, x+2, y+2) of the transposed copy holds the same pixel,
+// both with a zero border of 2 pixels, so a window inside [-2, N+1]^2 is copied chunk
+// for chunk with no bounds test.  Window rows/columns beyond [-2, N+1] are never
+// tapped and are not staged.  Wave w copies window rows w, w+4, w+8 (a slab has
+// kSlabH + 3 = 11 rows) with its lanes along the row (at most kTileTMax = 3 x 64
+// chunks), from wave-uniform row addresses.
 template <typename T, int BC>
 struct InterleavedSource {
-    const uint4 *base;   // first plane of the block's images
+    static constexpr bool kMarchFrame = true;
+    const uint4 *base;   // row-major copy: first plane of the block's images
+    const uint4 *tbase;  // transposed copy: first plane of the block's images
     int n;
     int plane_stride;    // chunks between planes ((N+4)^2)
     __device__ __forceinline__ void stage(uint4 *lds, int plane_chunks, int pitch, int ox0, int oy0,
-                                          int rows, int cols) const {
+                                          int rows, int cols, int axis) const {
+        static_assert(kTileTMax <= 3 * 64 && kSlabH + 3 <= 3 * 4, "staging loop bounds");
         constexpr int PLANES = BC / Chunk<T>::kImages;
         const int np = n + 4;
         const int r_end = min(rows, n + 2 - oy0), c_end = min(cols, n + 2 - ox0);
         if (r_end <= 0 || c_end <= 0) return;
-        const int total = r_end * c_end;
-        const int step_i = 256 / c_end, step_j = 256 - step_i * c_end;
-        const int i0 = threadIdx.x / c_end, j0 = threadIdx.x - i0 * c_end;
-        const uint4 *src0 = base + (oy0 + 2) * np + (ox0 + 2);
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const int lane = threadIdx.x & 63;
+        const uint4 *src0 = (axis ? tbase : base) + (oy0 + 2) * np + (ox0 + 2);
+        // per window row: the row's loads are issued before its LDS stores; the row and
+        // column-block tests are wave-uniform, the last partial block clamps its column
+        // (a valid address) and masks the store
 #pragma unroll
         for (int q = 0; q < PLANES; ++q) {
-            int i = i0, jj = j0;
             const uint4 *src = src0 + q * plane_stride;
-            for (int idx = threadIdx.x; idx < total; idx += 256) {
-                lds[q * plane_chunks + i * pitch + jj] = src[i * np + jj];
-                jj += step_j;
-                i += step_i;
-                if (jj >= c_end) {
-                    jj -= c_end;
-                    ++i;
+            uint4 *dst = lds + q * plane_chunks;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const int row = wave + 4 * i;
+                if (row >= r_end) break;
+                const uint4 *srow = src + row * np;
+                uint4 *drow = dst + row * pitch;
+                const uint4 v0 = srow[min(lane, c_end - 1)];
+                if (c_end > 64) {
+                    const uint4 v1 = srow[min(lane + 64, c_end - 1)];
+                    if (c_end > 128) {
+                        const uint4 v2 = srow[min(lane + 128, c_end - 1)];
+                        if (lane + 128 < c_end) drow[lane + 128] = v2;
+                    }
+                    if (lane + 64 < c_end) drow[lane + 64] = v1;
                 }
+                if (lane < c_end) drow[lane] = v0;
             }
         }
     }
 };
+
+// The samples of one lane's ray inside one slab: `cnt` samples at frame offsets
+// (fxa + j sx, fya + j sy) >= 1 from the lane's anchor chunk.  SWAP: the frame is the
+// transposed image; the two middle taps are then taken in the image frame's order,
+// so both frames give bitwise identical sums.
+template <typename T, int BC, bool SWAP>
+__device__ __forceinline__ void slab_samples(const uint4 *lane_lds, int pitch, int plane_chunks,
+                                             double fxa, double fya, double sx, double sy, int cnt,
+                                             float *part) {
+    constexpr int CH = Chunk<T>::kImages;
+    constexpr int PLANES = BC / CH;
+    for (int j = 0; j < cnt; ++j) {
+        const double jd = (double)j;
+        const double px = fma(jd, sx, fxa), py = fma(jd, sy, fya);
+        const int cx = (int)px, cy = (int)py;                       // px, py >= 1
+        const float fx = (float)__builtin_amdgcn_fract(px), fy = (float)__builtin_amdgcn_fract(py);
+        const float gx = 1.0f - fx, gy = 1.0f - fy;
+        const float w00 = __fmul_rn(gx, gy), w01 = __fmul_rn(fx, gy);
+        const float w10 = __fmul_rn(gx, fy), w11 = __fmul_rn(fx, fy);
+        const uint4 *pt = lane_lds + (__mul24(cy, pitch) + cx);
+#pragma unroll
+        for (int q = 0; q < PLANES; ++q) {
+            const uint4 *pl = pt + q * plane_chunks;
+            const uint4 t00 = pl[0], t01 = pl[1], t10 = pl[pitch], t11 = pl[pitch + 1];
+            float *aq = part + q * CH;
+            Chunk<T>::fma(w00, t00, aq);
+            if (SWAP) {
+                Chunk<T>::fma(w10, t10, aq);
+                Chunk<T>::fma(w01, t01, aq);
+            } else {
+                Chunk<T>::fma(w01, t01, aq);
+                Chunk<T>::fma(w10, t10, aq);
+            }
+            Chunk<T>::fma(w11, t11, aq);
+        }
+    }
+}
 
 // One block processes one work item (up to 4 angles x 64 bins; wave w <-> angle a0+w, lane
 // l <-> bin d0+l) x BC images.  The rays march through the image in slabs of
@@ -133,9 +190,6 @@ template <typename T, int BC, class Source>
 __device__ __forceinline__ void fwd_item(const Geom &g, const FwdItem &it, const int2 *__restrict__ ranges,
                                          const ImageSet<T, BC> &imgs, const Source &src, int tile_t,
                                          uint4 *lds) {
-    constexpr int CH = Chunk<T>::kImages;
-    constexpr int PLANES = BC / CH;
-    static_assert(BC % CH == 0, "BC must be a multiple of the images per chunk");
     const int plane_chunks = (kSlabH + 3) * tile_t;
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -147,11 +201,15 @@ __device__ __forceinline__ void fwd_item(const Geom &g, const FwdItem &it, const
     double4 r = ray_params(g, a, d);
     const double sm_raw = it.axis ? r.z : r.w;
     if (sm_raw < 0.0) { r.z = -r.z; r.w = -r.w; }
-    const double om = it.axis ? r.x : r.y;
     const double inv_sm = 1.0 / fabs(sm_raw);
     int jlo, jhi;
     support_range(r, n, jlo, jhi);
-    const int pitch = it.axis ? (kSlabH + 3) : tile_t;
+    // staging frame: the march frame swaps x and y for items marching along x
+    const bool swap = Source::kMarchFrame && it.axis;
+    if (swap) r = make_double4(r.y, r.x, r.w, r.z);
+    const int faxis = Source::kMarchFrame ? 0 : it.axis;
+    const double om = faxis ? r.x : r.y;
+    const int pitch = faxis ? (kSlabH + 3) : tile_t;
 
     float acc[BC];
 #pragma unroll
@@ -161,14 +219,14 @@ __device__ __forceinline__ void fwd_item(const Geom &g, const FwdItem &it, const
         const int2 tr = ranges[it.range + si];
         if (tr.x > tr.y) continue;                      // uniform over the block
         const int m_lo = -1 + (it.slab0 + si) * kSlabH;
-        // tile element (0, 0) sits at image (ox0, oy0); tile is rows x cols pixels
-        const int ox0 = it.axis ? m_lo - 1 : tr.x;
-        const int oy0 = it.axis ? tr.x : m_lo - 1;
-        const int cols = it.axis ? kSlabH + 3 : tr.y - tr.x + 1;
-        const int rows = it.axis ? tr.y - tr.x + 1 : kSlabH + 3;
+        // tile element (0, 0) sits at frame pixel (ox0, oy0); tile is rows x cols pixels
+        const int ox0 = faxis ? m_lo - 1 : tr.x;
+        const int oy0 = faxis ? tr.x : m_lo - 1;
+        const int cols = faxis ? kSlabH + 3 : tr.y - tr.x + 1;
+        const int rows = faxis ? tr.y - tr.x + 1 : kSlabH + 3;
 
         __syncthreads();                                // previous slab fully consumed
-        src.stage(lds, plane_chunks, pitch, ox0, oy0, rows, cols);
+        src.stage(lds, plane_chunks, pitch, ox0, oy0, rows, cols, it.axis);
         __syncthreads();
 
         // samples of this ray whose march coordinate lies in [m_lo, m_lo + kSlabH)
@@ -183,34 +241,18 @@ __device__ __forceinline__ void fwd_item(const Geom &g, const FwdItem &it, const
         const double lx64 = fma((double)(je - 1 - jb), r.z, px64);
         const double ly64 = fma((double)(je - 1 - jb), r.w, py64);
         const double bx = floor(fmin(px64, lx64)) - 1.0, by = floor(fmin(py64, ly64)) - 1.0;
-        const double fxa = px64 - bx, fya = py64 - by;
         const uint4 *lane_lds = lds + ((int)by * pitch + (int)bx);
         // the slab's samples are summed separately and then added to the ray total
         // (two-level summation keeps FP32 rounding of long rays small)
         float part[BC];
 #pragma unroll
         for (int i = 0; i < BC; ++i) part[i] = 0.0f;
-        const int cnt = je - jb;
-        for (int j = 0; j < cnt; ++j) {
-            const double jd = (double)j;
-            const double px = fma(jd, r.z, fxa), py = fma(jd, r.w, fya);
-            const int cx = (int)px, cy = (int)py;                       // px, py >= 1
-            const float fx = (float)__builtin_amdgcn_fract(px), fy = (float)__builtin_amdgcn_fract(py);
-            const float gx = 1.0f - fx, gy = 1.0f - fy;
-            const float w00 = __fmul_rn(gx, gy), w01 = __fmul_rn(fx, gy);
-            const float w10 = __fmul_rn(gx, fy), w11 = __fmul_rn(fx, fy);
-            const uint4 *pt = lane_lds + (__mul24(cy, pitch) + cx);
-#pragma unroll
-            for (int q = 0; q < PLANES; ++q) {
-                const uint4 *pl = pt + q * plane_chunks;
-                const uint4 t00 = pl[0], t01 = pl[1], t10 = pl[pitch], t11 = pl[pitch + 1];
-                float *aq = part + q * CH;
-                Chunk<T>::fma(w00, t00, aq);
-                Chunk<T>::fma(w01, t01, aq);
-                Chunk<T>::fma(w10, t10, aq);
-                Chunk<T>::fma(w11, t11, aq);
-            }
-        }
+        if (swap)
+            slab_samples<T, BC, Source::kMarchFrame>(lane_lds, pitch, plane_chunks, px64 - bx,
+                                                     py64 - by, r.z, r.w, je - jb, part);
+        else
+            slab_samples<T, BC, false>(lane_lds, pitch, plane_chunks, px64 - bx, py64 - by, r.z,
+                                       r.w, je - jb, part);
 #pragma unroll
         for (int i = 0; i < BC; ++i) acc[i] += part[i];
     }
@@ -223,7 +265,7 @@ __device__ __forceinline__ void fwd_item(const Geom &g, const FwdItem &it, const
 
 // ------------------------------------------------------------------ backprojection
 // Parallel beam.  One block = a 16x16 pixel tile (lane <-> pixel) x BC images.
-// Angles are processed in blocks of kBpAngles: for each, the block stages into LDS
+// Angles are processed in blocks of AB: for each, the block stages into LDS
 // the window of W bins its tile can touch, as 16-byte chunks of Chunk<T>::kImages
 // images ("planes").  Each pixel then finds, per angle, the lattice samples
 // (bin d, step k) whose bilinear footprint covers it: the pixel's continuous
@@ -232,10 +274,10 @@ __device__ __forceinline__ void fwd_item(const Geom &g, const FwdItem &it, const
 // the footprint, and their offsets from the pixel are small FP32 numbers, so the
 // tent weights are accurate to FP32 rounding.  The NB bin weights are then applied
 // to BC images with 16-byte LDS reads.  No atomics.
-template <typename T, int BC, int NB, int NK>
+template <typename T, int BC, int NB, int NK, int AB = kBpAngles>
 __device__ __forceinline__ void bp_tile_par(const Geom &g, int tile, const ImageSet<T, BC> &imgs,
                                             int W, uint4 *lds) {
-    __shared__ int wlo_s[kBpAngles];
+    __shared__ int wlo_s[AB];
     constexpr int CH = Chunk<T>::kImages;
     constexpr int PLANES = BC / CH;
     static_assert(BC % CH == 0, "BC must be a multiple of the images per chunk");
@@ -245,7 +287,7 @@ __device__ __forceinline__ void bp_tile_par(const Geom &g, int tile, const Image
     const int c = tx0 + (threadIdx.x % kBpTile), r = ty0 + (threadIdx.x / kBpTile);
     const double qx = (double)c - g.cn, qy = (double)r - g.cn;
     const double tcx = tx0 + 0.5 * (kBpTile - 1) - g.cn, tcy = ty0 + 0.5 * (kBpTile - 1) - g.cn;
-    const int per_plane = kBpAngles * W;
+    const int per_plane = AB * W;
     const T *const *img_base = imgs.in;
     const float dt = (float)g.step, sp = (float)g.spacing;
 
@@ -253,8 +295,8 @@ __device__ __forceinline__ void bp_tile_par(const Geom &g, int tile, const Image
 #pragma unroll
     for (int i = 0; i < BC; ++i) acc[i] = 0.0f;
 
-    for (int a0 = 0; a0 < A; a0 += kBpAngles) {
-        const int na = min(kBpAngles, A - a0);
+    for (int a0 = 0; a0 < A; a0 += AB) {
+        const int na = min(AB, A - a0);
         __syncthreads();                                // previous block consumed
         if (threadIdx.x < na) {
             const double2 cs = g.trig[a0 + threadIdx.x];

@@ -125,7 +125,7 @@ class _Base:
         out = (ctypes.c_int32 * 8)()
         _lib.check("radon_plan_info", _lib.lib.radon_plan_info(
             ctypes.byref(self._geom), dtype_code(dtype), int(batch), out))
-        keys = ("images", "angles", "rays", "variant")
+        keys = ("images", "angles", "staging", "variant")
         return {"forward": dict(zip(keys, out[0:4])), "backprojection": dict(zip(keys, out[4:8]))}
 
 

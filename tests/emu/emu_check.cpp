@@ -1,0 +1,191 @@
+// CPU check of the library's kernels, built against the host emulation of HIP with
+// AddressSanitizer.  For every geometry of a list it runs the per-call forward and
+// backprojection (tiled kernels where the planner accepts the geometry), the direct
+// kernels, and the FP64 oracle on the same inputs, and reports the relative L2
+// differences; with "batched" it also runs the whole list as one uneven batch in each
+// direction and compares it with the per-call results bitwise.
+//
+// Line format: beam n D spacing S E step batch dtype A angle_0 ... angle_{A-1}
+// Output: one "geometry ..." line per geometry, then "batched ..." and "summary ...".
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <random>
+#include <vector>
+
+#include "radon.h"
+
+extern "C" {
+int oracle_forward(int beam, int n, int n_angles, const double *angles, int det_count,
+                   double det_spacing, double source_distance, double det_distance, double step,
+                   const double *x, int batch, double scale, double *y);
+int oracle_backproject(int beam, int n, int n_angles, const double *angles, int det_count,
+                       double det_spacing, double source_distance, double det_distance,
+                       double step, const double *y, int batch, double scale, double *x);
+}
+
+namespace {
+
+struct Geo {
+    int beam, n, D, batch, dt, A;
+    double sp, S, E, step;
+    std::vector<double> angles;
+    radon_geometry_t g;
+    size_t nx, ny;
+    std::vector<unsigned char> x, y;           // inputs (storage type)
+    void *fx = nullptr, *bx = nullptr;         // per-call outputs
+};
+
+size_t esize(int dt) { return dt == RADON_F32 ? 4 : 2; }
+
+double to_double(const void *p, size_t i, int dt) {
+    if (dt == RADON_F32) return ((const float *)p)[i];
+    const unsigned short h = ((const unsigned short *)p)[i];
+    if (dt == RADON_BF16) {
+        const unsigned u = (unsigned)h << 16;
+        float f;
+        std::memcpy(&f, &u, 4);
+        return f;
+    }
+    _Float16 f;
+    std::memcpy(&f, &h, 2);
+    return (float)f;
+}
+
+void from_float(void *p, size_t i, float v, int dt) {
+    if (dt == RADON_F32) { ((float *)p)[i] = v; return; }
+    if (dt == RADON_BF16) {      // round to nearest even
+        unsigned u;
+        std::memcpy(&u, &v, 4);
+        u += 0x7fffu + ((u >> 16) & 1u);
+        ((unsigned short *)p)[i] = (unsigned short)(u >> 16);
+        return;
+    }
+    const _Float16 h = (_Float16)v;
+    std::memcpy((unsigned short *)p + i, &h, 2);
+}
+
+double rel_l2(const void *a, int dt, const double *ref, size_t n) {
+    double num = 0.0, den = 0.0;
+    for (size_t i = 0; i < n; ++i) {
+        const double d = to_double(a, i, dt) - ref[i];
+        num += d * d;
+        den += ref[i] * ref[i];
+    }
+    return den > 0.0 ? std::sqrt(num / den) : std::sqrt(num);
+}
+
+void *dev_alloc(size_t bytes) {
+    void *p = nullptr;
+    if (posix_memalign(&p, 256, bytes ? bytes : 1) != 0) return nullptr;
+    return p;
+}
+
+}  // namespace
+
+int main(int argc, char **argv) {
+    if (argc < 2) return 2;
+    const bool batched = argc > 2 && std::strcmp(argv[2], "batched") == 0;
+    FILE *f = std::fopen(argv[1], "r");
+    if (!f) return 2;
+    std::vector<Geo> geos;
+    for (;;) {
+        Geo g;
+        if (std::fscanf(f, "%d %d %d %lf %lf %lf %lf %d %d %d", &g.beam, &g.n, &g.D, &g.sp, &g.S,
+                        &g.E, &g.step, &g.batch, &g.dt, &g.A) != 10)
+            break;
+        g.angles.resize(g.A);
+        for (double &a : g.angles)
+            if (std::fscanf(f, "%lf", &a) != 1) return 2;
+        geos.push_back(std::move(g));
+    }
+    std::fclose(f);
+    std::mt19937 rng(7);
+    std::normal_distribution<float> normal;
+    int fails = 0;
+    for (size_t k = 0; k < geos.size(); ++k) {
+        Geo &g = geos[k];
+        g.g = radon_geometry_t{g.beam, g.n, g.A, g.D, g.angles.data(), g.sp, g.S, g.E, g.step};
+        g.nx = (size_t)g.batch * g.n * g.n;
+        g.ny = (size_t)g.batch * g.A * g.D;
+        const size_t es = esize(g.dt);
+        g.x.resize(g.nx * es);
+        g.y.resize(g.ny * es);
+        for (size_t i = 0; i < g.nx; ++i) from_float(g.x.data(), i, normal(rng), g.dt);
+        for (size_t i = 0; i < g.ny; ++i) from_float(g.y.data(), i, normal(rng), g.dt);
+        std::fprintf(stderr, "[emu] geometry %zu: beam %d N %d A %d D %d batch %d dtype %d\n", k,
+                     g.beam, g.n, g.A, g.D, g.batch, g.dt);
+        void *xin = dev_alloc(g.nx * es), *yin = dev_alloc(g.ny * es);
+        std::memcpy(xin, g.x.data(), g.nx * es);
+        std::memcpy(yin, g.y.data(), g.ny * es);
+        g.fx = dev_alloc(g.ny * es);
+        g.bx = dev_alloc(g.nx * es);
+        void *fd = dev_alloc(g.ny * es), *bd = dev_alloc(g.nx * es);
+        int rc = radon_forward(&g.g, xin, g.fx, g.batch, g.dt, 1.0f, nullptr);
+        if (!rc) rc = radon_backproject(&g.g, yin, g.bx, g.batch, g.dt, 1.0f, nullptr);
+        int info[8] = {0};
+        if (!rc) rc = radon_plan_info(&g.g, g.dt, g.batch, info);
+        // direct kernels: plans rebuilt with the tiled planners switched off
+        if (!rc) {
+            radon_release_plans();
+            setenv("RADON_VARIANT", "direct", 1);
+            rc = radon_forward(&g.g, xin, fd, g.batch, g.dt, 1.0f, nullptr);
+            if (!rc) rc = radon_backproject(&g.g, yin, bd, g.batch, g.dt, 1.0f, nullptr);
+            unsetenv("RADON_VARIANT");
+            radon_release_plans();
+        }
+        if (rc) {
+            std::printf("geometry %zu status %d\n", k, rc);
+            ++fails;
+            continue;
+        }
+        // oracle on the same (already rounded) inputs
+        std::vector<double> xd(g.nx), yd(g.ny), of(g.ny), ob(g.nx);
+        for (size_t i = 0; i < g.nx; ++i) xd[i] = to_double(g.x.data(), i, g.dt);
+        for (size_t i = 0; i < g.ny; ++i) yd[i] = to_double(g.y.data(), i, g.dt);
+        oracle_forward(g.beam, g.n, g.A, g.angles.data(), g.D, g.sp, g.S, g.E, g.step, xd.data(),
+                       g.batch, 1.0, of.data());
+        oracle_backproject(g.beam, g.n, g.A, g.angles.data(), g.D, g.sp, g.S, g.E, g.step,
+                           yd.data(), g.batch, 1.0, ob.data());
+        const double ef = rel_l2(g.fx, g.dt, of.data(), g.ny), eb = rel_l2(g.bx, g.dt, ob.data(), g.nx);
+        const double df = rel_l2(fd, g.dt, of.data(), g.ny), db = rel_l2(bd, g.dt, ob.data(), g.nx);
+        std::printf("geometry %zu fwd_variant %d bp_variant %d forward %.3e backprojection %.3e "
+                    "direct_forward %.3e direct_backprojection %.3e\n",
+                    k, info[3], info[7], ef, eb, df, db);
+        std::free(xin);
+        std::free(yin);
+        std::free(fd);
+        std::free(bd);
+    }
+    if (batched) {
+        std::vector<radon_job_t> jf, jb;
+        std::vector<void *> of, ob, ins;
+        for (Geo &g : geos) {
+            const size_t es = esize(g.dt);
+            void *xin = dev_alloc(g.nx * es), *yin = dev_alloc(g.ny * es);
+            std::memcpy(xin, g.x.data(), g.nx * es);
+            std::memcpy(yin, g.y.data(), g.ny * es);
+            of.push_back(dev_alloc(g.ny * es));
+            ob.push_back(dev_alloc(g.nx * es));
+            ins.push_back(xin);
+            ins.push_back(yin);
+            jf.push_back(radon_job_t{&g.g, xin, of.back(), g.batch, 1.0f});
+            jb.push_back(radon_job_t{&g.g, yin, ob.back(), g.batch, 1.0f});
+        }
+        const int dt = geos.empty() ? RADON_F32 : geos[0].dt;
+        std::fprintf(stderr, "[emu] batched forward and backprojection of %zu jobs\n", geos.size());
+        int rc = radon_forward_batched(jf.data(), (int)jf.size(), dt, nullptr);
+        if (!rc) rc = radon_backproject_batched(jb.data(), (int)jb.size(), dt, nullptr);
+        int same = 0;
+        for (size_t k = 0; !rc && k < geos.size(); ++k) {
+            const size_t es = esize(geos[k].dt);
+            same += std::memcmp(of[k], geos[k].fx, geos[k].ny * es) == 0 &&
+                    std::memcmp(ob[k], geos[k].bx, geos[k].nx * es) == 0;
+        }
+        std::printf("batched status %d identical %d of %zu\n", rc, same, geos.size());
+        if (rc || same != (int)geos.size()) ++fails;
+    }
+    std::printf("summary geometries %zu failures %d\n", geos.size(), fails);
+    return fails ? 1 : 0;
+}
