@@ -190,7 +190,9 @@ static int build_plan(const radon_geometry_t *g, int device, std::unique_ptr<Pla
         p->fwd_work.items = p->fwd_items;
         p->fwd_work.ranges = p->fwd_ranges;
         p->fwd_work.n_items = (int)items.size();
-        p->fwd_work.tile_t = tile_t | 1;
+        // LDS row pitch: a multiple of 16 chunks, so lanes whose samples sit in
+        // neighbouring rows of the staged window keep their bank offsets
+        p->fwd_work.tile_t = (tile_t + 15) / 16 * 16;
         p->fwd_shape.variant = VARIANT_TILED;
         const char *il = std::getenv("RADON_FWD_INTERLEAVE");
         p->no_interleave = il && std::strcmp(il, "0") == 0;

@@ -45,7 +45,7 @@ struct FwdWork {
     const FwdItem *items = nullptr;   // device
     const int2 *ranges = nullptr;     // device
     int n_items = 0;
-    int tile_t = 0;                   // transverse extent to allocate (odd, <= kTileTMax+1)
+    int tile_t = 0;                   // LDS row pitch in chunks (multiple of 16, <= kTileTMax)
 };
 
 // Host planning of the tiled forward projector from FP64 ray parameters

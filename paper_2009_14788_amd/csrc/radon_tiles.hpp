@@ -149,19 +149,26 @@ __device__ __forceinline__ void slab_samples(const uint4 *lane_lds, int pitch, i
                                              float *part) {
     constexpr int CH = Chunk<T>::kImages;
     constexpr int PLANES = BC / CH;
-    for (int j = 0; j < cnt; ++j) {
-        const double jd = (double)j;
+    // byte addressing: one multiply-add and one shift-add per sample, the tap
+    // offsets (+16 bytes, +pitch, +plane) are loop invariants
+    const char *base = reinterpret_cast<const char *>(lane_lds);
+    const unsigned row_bytes = (unsigned)pitch * 16u, plane_bytes = (unsigned)plane_chunks * 16u;
+    const double end = (double)cnt;
+    for (double jd = 0.0; jd < end; jd += 1.0) {
         const double px = fma(jd, sx, fxa), py = fma(jd, sy, fya);
         const int cx = (int)px, cy = (int)py;                       // px, py >= 1
         const float fx = (float)__builtin_amdgcn_fract(px), fy = (float)__builtin_amdgcn_fract(py);
         const float gx = 1.0f - fx, gy = 1.0f - fy;
         const float w00 = __fmul_rn(gx, gy), w01 = __fmul_rn(fx, gy);
         const float w10 = __fmul_rn(gx, fy), w11 = __fmul_rn(fx, fy);
-        const uint4 *pt = lane_lds + (__mul24(cy, pitch) + cx);
+        const char *p0 = base + ((unsigned)__mul24(cy, pitch) + (unsigned)cx) * 16u;
 #pragma unroll
         for (int q = 0; q < PLANES; ++q) {
-            const uint4 *pl = pt + q * plane_chunks;
-            const uint4 t00 = pl[0], t01 = pl[1], t10 = pl[pitch], t11 = pl[pitch + 1];
+            const char *pq = p0 + q * plane_bytes;
+            const uint4 t00 = *reinterpret_cast<const uint4 *>(pq);
+            const uint4 t01 = *reinterpret_cast<const uint4 *>(pq + 16);
+            const uint4 t10 = *reinterpret_cast<const uint4 *>(pq + row_bytes);
+            const uint4 t11 = *reinterpret_cast<const uint4 *>(pq + row_bytes + 16);
             float *aq = part + q * CH;
             Chunk<T>::fma(w00, t00, aq);
             if (SWAP) {
