@@ -39,7 +39,7 @@ __device__ __forceinline__ ImageSet<T, BC> group_images(const ImageGroup &grp) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void fwd_batched(const BatchJob *__restrict__ jobs,
+__global__ __launch_bounds__(kFwdThreads) void fwd_batched(const BatchJob *__restrict__ jobs,
                                                    const ImageGroup *__restrict__ groups,
                                                    const WorkUnit *__restrict__ work, int n_work,
                                                    int *counter) {
@@ -93,7 +93,7 @@ static hipError_t launch_batched_t(int direction, const BatchLaunch &L, hipStrea
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (direction == 0)
-        hipLaunchKernelGGL((fwd_batched<T>), dim3(L.grid), dim3(256), L.lds, s, L.jobs, L.groups,
+        hipLaunchKernelGGL((fwd_batched<T>), dim3(L.grid), dim3(kFwdThreads), L.lds, s, L.jobs, L.groups,
                            L.work, L.n_work, L.counter);
     else
         hipLaunchKernelGGL((bp_batched<T>), dim3(L.grid), dim3(256), L.lds, s, L.jobs, L.groups,
@@ -114,11 +114,11 @@ int batched_blocks_per_cu(int direction, int dtype, size_t lds) {
     int nb = 0;
     hipError_t e = hipErrorInvalidValue;
     switch (dtype * 2 + direction) {
-    case F32 * 2 + 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fwd_batched<float>, 256, lds); break;
+    case F32 * 2 + 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fwd_batched<float>, kFwdThreads, lds); break;
     case F32 * 2 + 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, bp_batched<float>, 256, lds); break;
-    case F16 * 2 + 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fwd_batched<__half>, 256, lds); break;
+    case F16 * 2 + 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fwd_batched<__half>, kFwdThreads, lds); break;
     case F16 * 2 + 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, bp_batched<__half>, 256, lds); break;
-    case BF16 * 2 + 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fwd_batched<bf16_t>, 256, lds); break;
+    case BF16 * 2 + 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fwd_batched<bf16_t>, kFwdThreads, lds); break;
     case BF16 * 2 + 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, bp_batched<bf16_t>, 256, lds); break;
     default: break;
     }

@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256) void fwd_direct(Geom g, const T *__restrict__ 
 // ------------------------------------------------------------------ tiled variant
 // One block = one work item of the plan x BC images (blockIdx.y selects the images).
 template <typename T, int BC>
-__global__ __launch_bounds__(256) void fwd_tiled(Geom g, FwdWork work, const T *__restrict__ x,
+__global__ __launch_bounds__(kFwdThreads) void fwd_tiled(Geom g, FwdWork work, const T *__restrict__ x,
                                                  T *__restrict__ y, int batch, float scale_dt,
                                                  int tile_t) {
     extern __shared__ uint4 lds[];
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void fwd_tiled(Geom g, FwdWork work, const T *
 // Same, staging from the interleaved, zero-bordered copies of the batch: xi holds
 // the row-major copy [groups][N+4][N+4] followed by the transposed copy.
 template <typename T, int BC>
-__global__ __launch_bounds__(256) void fwd_tiled_il(Geom g, FwdWork work, const uint4 *__restrict__ xi,
+__global__ __launch_bounds__(kFwdThreads) void fwd_tiled_il(Geom g, FwdWork work, const uint4 *__restrict__ xi,
                                                     T *__restrict__ y, int batch, float scale_dt,
                                                     int tile_t, int groups) {
     extern __shared__ uint4 lds[];
@@ -172,10 +172,10 @@ static hipError_t launch_fwd_tiled(const Geom &g, const FwdWork &work, const voi
                            (const T *)x, (uint4 *)ws, g.n, batch, groups);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((fwd_tiled_il<T, BC>), grid, dim3(256), lds, s, g, work,
+        hipLaunchKernelGGL((fwd_tiled_il<T, BC>), grid, dim3(kFwdThreads), lds, s, g, work,
                            (const uint4 *)ws, (T *)y, batch, scale_dt, work.tile_t, groups);
     } else {
-        hipLaunchKernelGGL((fwd_tiled<T, BC>), grid, dim3(256), lds, s, g, work, (const T *)x,
+        hipLaunchKernelGGL((fwd_tiled<T, BC>), grid, dim3(kFwdThreads), lds, s, g, work, (const T *)x,
                            (T *)y, batch, scale_dt, work.tile_t);
     }
     return hipGetLastError();

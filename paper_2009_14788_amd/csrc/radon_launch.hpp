@@ -36,8 +36,15 @@ struct FwdItem {
     int range;
 };
 
-constexpr int kSlabH = 8;          // pixel rows (columns) per slab
-constexpr int kFwdWaves = 4;       // angles per forward item
+#ifndef RADON_SLAB_H
+#define RADON_SLAB_H 12
+#endif
+constexpr int kSlabH = RADON_SLAB_H;   // pixel rows (columns) per slab
+#ifndef RADON_FWD_WAVES
+#define RADON_FWD_WAVES 8
+#endif
+constexpr int kFwdWaves = RADON_FWD_WAVES;   // angles (waves) per forward work item
+constexpr int kFwdThreads = 64 * kFwdWaves;  // threads per forward block
 constexpr int kFwdLanes = 64;      // bins per forward item
 constexpr int kTileTMax = 192;     // largest transverse extent of a staged slab
 
@@ -45,7 +52,7 @@ struct FwdWork {
     const FwdItem *items = nullptr;   // device
     const int2 *ranges = nullptr;     // device
     int n_items = 0;
-    int tile_t = 0;                   // LDS row pitch in chunks (multiple of 16, <= kTileTMax)
+    int tile_t = 0;                   // LDS row pitch in chunks (16k + 8, <= kTileTMax + 8)
 };
 
 // Host planning of the tiled forward projector from FP64 ray parameters

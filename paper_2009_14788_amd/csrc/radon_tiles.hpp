@@ -1,6 +1,7 @@
 // Per-work-item device functions of the tiled projectors, shared by the per-call
 // kernels and the persistent uneven-batch kernels.  Every function is called by all
-// 256 threads of a block with block-uniform arguments (they contain barriers).
+// threads of a block (kFwdThreads for the forward, 256 for the backprojection) with
+// block-uniform arguments (they contain barriers).
 #pragma once
 
 #include "radon_common.hpp"
@@ -59,12 +60,12 @@ struct PointerSource {
         constexpr int CH = Chunk<T>::kImages;
         constexpr int PLANES = BC / CH;
         const int total = rows * cols;
-        const int step_i = 256 / cols, step_j = 256 - step_i * cols;
+        const int step_i = kFwdThreads / cols, step_j = kFwdThreads - step_i * cols;
         const int i0 = threadIdx.x / cols, j0 = threadIdx.x - i0 * cols;
 #pragma unroll
         for (int q = 0; q < PLANES; ++q) {
             int i = i0, jj = j0;
-            for (int idx = threadIdx.x; idx < total; idx += 256) {
+            for (int idx = threadIdx.x; idx < total; idx += kFwdThreads) {
                 const int gx = ox0 + jj, gy = oy0 + i;
                 const bool inside = (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n;
                 const unsigned off = inside ? (unsigned)(gy * n + gx) : 0u;
@@ -91,8 +92,8 @@ struct PointerSource {
 // images, and chunk (group, x+2, y+2) of the transposed copy holds the same pixel,
 // both with a zero border of 2 pixels, so a window inside [-2, N+1]^2 is copied chunk
 // for chunk with no bounds test.  Window rows/columns beyond [-2, N+1] are never
-// tapped and are not staged.  Wave w copies window rows w, w+4, w+8 (a slab has
-// kSlabH + 3 = 11 rows) with its lanes along the row (at most kTileTMax = 3 x 64
+// tapped and are not staged.  Wave w copies window rows w, w+W, w+2W, ... (W waves; a slab has
+// kSlabH + 3 rows) with its lanes along the row (at most kTileTMax = 3 x 64
 // chunks), from wave-uniform row addresses.
 template <typename T, int BC>
 struct InterleavedSource {
@@ -103,7 +104,8 @@ struct InterleavedSource {
     int plane_stride;    // chunks between planes ((N+4)^2)
     __device__ __forceinline__ void stage(uint4 *lds, int plane_chunks, int pitch, int ox0, int oy0,
                                           int rows, int cols, int axis) const {
-        static_assert(kTileTMax <= 3 * 64 && kSlabH + 3 <= 3 * 4, "staging loop bounds");
+        static_assert(kTileTMax <= 3 * 64, "staging loop bounds");
+        constexpr int kRowsPerWave = (kSlabH + 3 + kFwdWaves - 1) / kFwdWaves;
         constexpr int PLANES = BC / Chunk<T>::kImages;
         const int np = n + 4;
         const int r_end = min(rows, n + 2 - oy0), c_end = min(cols, n + 2 - ox0);
@@ -119,8 +121,8 @@ struct InterleavedSource {
             const uint4 *src = src0 + q * plane_stride;
             uint4 *dst = lds + q * plane_chunks;
 #pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                const int row = wave + 4 * i;
+            for (int i = 0; i < kRowsPerWave; ++i) {
+                const int row = wave + kFwdWaves * i;
                 if (row >= r_end) break;
                 const uint4 *srow = src + row * np;
                 uint4 *drow = dst + row * pitch;
@@ -183,8 +185,7 @@ __device__ __forceinline__ void slab_samples(const uint4 *lane_lds, int pitch, i
     }
 }
 
-// One block processes one work item (up to 4 angles x 64 bins; wave w <-> angle a0+w, lane
-// l <-> bin d0+l) x BC images.  The rays march through the image in slabs of
+// One block processes one work item (up to kFwdWaves angles x 64 bins) x BC images.  The rays march through the image in slabs of
 // kSlabH rows (or columns); per slab the block stages the slab's pixel window
 // into LDS as 16-byte chunks holding Chunk<T>::kImages images each ("planes"),
 // then every lane walks its ray's samples inside the slab.  A sample costs one
@@ -199,9 +200,15 @@ __device__ __forceinline__ void fwd_item(const Geom &g, const FwdItem &it, const
                                          uint4 *lds) {
     const int plane_chunks = (kSlabH + 3) * tile_t;
 
+    // rays of the item -> lanes: a wave takes 4 angles x 16 bins, and each 16-lane
+    // quarter of it 4 neighbouring bins x 4 neighbouring angles, so the quarter's taps
+    // fall on nearby columns (distinct LDS banks) and its rays have similar lengths
+    static_assert(kFwdWaves % 4 == 0, "waves come in groups of four");
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const bool active = wave < it.na && lane < it.nd;
-    const int a = it.a0 + min(wave, it.na - 1), d = it.d0 + min(lane, it.nd - 1);
+    const int ai = 4 * (wave >> 2) + ((lane >> 2) & 3);
+    const int di = 16 * (wave & 3) + 4 * (lane >> 4) + (lane & 3);
+    const bool active = ai < it.na && di < it.nd;
+    const int a = it.a0 + min(ai, it.na - 1), d = it.d0 + min(di, it.nd - 1);
     const int n = g.n;
 
     // the lane's ray, oriented so that the march coordinate grows with the sample index
