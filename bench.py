@@ -192,6 +192,7 @@ def main():
     info = op.plan_info(torch.float32, B)[dom]
     shape = f"{info['variant']},{info['images']},{info['angles']},{info['staging']}"
     kernels = {("forward", 1, 1): "interleave_images + fwd_tiled_il", ("forward", 1, 0): "fwd_tiled",
+               ("backprojection", 1, 1): "interleave_sinograms + bp_tiled_par_il",
                ("backprojection", 1, 0): "bp_tiled_par"}.get(
                    (dom, info["variant"], info["staging"]), f"{dom}_direct")
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,

@@ -102,6 +102,7 @@ bool PlanKey::operator==(const PlanKey &o) const {
 Plan::~Plan() {
     if (trig) (void)hipFree(trig);
     if (rays) (void)hipFree(rays);
+    if (bpa) (void)hipFree(bpa);
     if (fwd_items) (void)hipFree(fwd_items);
     if (fwd_ranges) (void)hipFree(fwd_ranges);
 }
@@ -161,6 +162,30 @@ static int build_plan(const radon_geometry_t *g, int device, std::unique_ptr<Pla
     if (hipMemcpy(p->trig, trig.data(), trig.size() * sizeof(double2), hipMemcpyHostToDevice) !=
         hipSuccess)
         return RADON_ERR_HIP;
+    if (g->beam != RADON_FANBEAM) {
+        // per-angle constants of the parallel backprojection
+        std::vector<BpAngle> bpa(g->n_angles);
+        for (int a = 0; a < g->n_angles; ++a) {
+            const double c = trig[a].x, sn = trig[a].y, h = std::fabs(c) + std::fabs(sn);
+            BpAngle &b = bpa[a];
+            b.cu = c / g->det_spacing;
+            b.su = sn / g->det_spacing;
+            b.cv = c / g->step;
+            b.sv = sn / g->step;
+            b.hu = h / g->det_spacing;
+            b.hv = h / g->step;
+            b.cf = (float)c;
+            b.sf = (float)sn;
+            b.ux = (float)(g->det_spacing * c);
+            b.uy = (float)(g->det_spacing * sn);
+            b.vx = (float)(-g->step * sn);
+            b.vy = (float)(g->step * c);
+        }
+        if (hipMalloc(&p->bpa, bpa.size() * sizeof(BpAngle)) != hipSuccess) return RADON_ERR_ALLOC;
+        if (hipMemcpy(p->bpa, bpa.data(), bpa.size() * sizeof(BpAngle), hipMemcpyHostToDevice) !=
+            hipSuccess)
+            return RADON_ERR_HIP;
+    }
     if (g->beam == RADON_FANBEAM) {
         if (hipMalloc(&p->rays, rays.size() * sizeof(double4)) != hipSuccess) return RADON_ERR_ALLOC;
         if (hipMemcpy(p->rays, rays.data(), rays.size() * sizeof(double4),
@@ -227,6 +252,7 @@ static int build_plan(const radon_geometry_t *g, int device, std::unique_ptr<Pla
     G.sde = g->source_distance + g->det_distance;
     G.trig = p->trig;
     G.rays = p->rays;
+    G.bpa = p->bpa;
     p->device = device;
     out = std::move(p);
     return RADON_OK;
@@ -255,8 +281,9 @@ int get_plan(const radon_geometry_t *g, hipStream_t stream, Plan **out) {
     return RADON_OK;
 }
 
-// Forward workspace (the interleaved copy of the input batch), one per (device,
-// stream) so calls on different streams never share it.  Grown on demand outside
+// Workspace for the interleaved copy of a call's input batch (images for the
+// forward, sinograms for the backprojection), one per (device, stream) so calls on
+// different streams never share it; calls on one stream use it in stream order.  Grown on demand outside
 // stream capture; a smaller buffer it replaces stays allocated (a captured graph may
 // still use it) until radon_release_plans.  Under capture without a large enough
 // workspace the forward stages straight from the caller's images instead.
@@ -267,7 +294,7 @@ struct Workspace {
 };
 static std::unordered_map<std::string, Workspace> g_workspaces;
 
-static void *forward_workspace(hipStream_t stream, size_t need, size_t *have) {
+static void *stream_workspace(hipStream_t stream, size_t need, size_t *have) {
     *have = 0;
     int device = 0;
     if (hipGetDevice(&device) != hipSuccess) return nullptr;
@@ -515,7 +542,7 @@ static int run_batched(const radon_job_t *jobs, int32_t n, int32_t dtype, int di
             ? launch_forward(p->geom, p->fwd_work, dtype, p->fwd_shape, jobs[i].input,
                              jobs[i].output, jobs[i].batch, jobs[i].scale, nullptr, 0, s)
             : launch_backproject(p->geom, p->bp_work, dtype, p->bp_shape, jobs[i].input,
-                                 jobs[i].output, jobs[i].batch, jobs[i].scale, s);
+                                 jobs[i].output, jobs[i].batch, jobs[i].scale, nullptr, 0, s);
         if (e != hipSuccess) return RADON_ERR_HIP;
     }
     return RADON_OK;
@@ -544,13 +571,16 @@ static int release_all() {
 static void call_shapes(Plan *p, int dtype, int batch, LaunchShape &fwd, LaunchShape &bp) {
     fwd = p->fwd_shape;
     bp = p->bp_shape;
+    // test hook: "fwd images, fwd staging, bp images, bp angles[, bp staging]"
     if (const char *f = std::getenv("RADON_FORCE_SHAPE")) {
-        int fi, fs, bi, ba;
-        if (std::sscanf(f, "%d,%d,%d,%d", &fi, &fs, &bi, &ba) == 4) {
+        int fi, fs, bi, ba, bs = 1;
+        const int k = std::sscanf(f, "%d,%d,%d,%d,%d", &fi, &fs, &bi, &ba, &bs);
+        if (k >= 4) {
             fwd.images = fi;
             fwd.stage = fs;
             bp.images = bi;
             if (!p->geom.fan) bp.angles = ba;
+            bp.stage = bs;
             return;
         }
     }
@@ -563,6 +593,7 @@ static void call_shapes(Plan *p, int dtype, int batch, LaunchShape &fwd, LaunchS
     fwd.stage = it->second.fwd_stage;
     bp.images = it->second.bp_images;
     bp.angles = it->second.bp_angles;
+    bp.stage = it->second.bp_stage;
 }
 
 }  // namespace radon
@@ -592,8 +623,10 @@ int radon_prepare(const radon_geometry_t *geometry, int32_t dtype, int32_t batch
         }
         if (!have) {
             size_t ws_bytes = 0;
-            void *ws = forward_workspace(nullptr, interleaved_bytes(geometry->image_size, batch, dtype),
-                                         &ws_bytes);
+            const size_t need = std::max(
+                interleaved_bytes(geometry->image_size, batch, dtype),
+                interleaved_sino_bytes(p->geom.n_angles, p->geom.det_count, p->bp_work.window, batch, dtype));
+            void *ws = stream_workspace(nullptr, need, &ws_bytes);
             TunedShapes t;
             if (autotune(*p, dtype, batch, ws, ws_bytes, t) == 0) {
                 std::lock_guard<std::mutex> lock(g_mutex);
@@ -620,7 +653,7 @@ int radon_forward(const radon_geometry_t *geometry, const void *x, void *y, int3
     void *ws = nullptr;
     size_t ws_bytes = 0;
     if (fwd.variant == VARIANT_TILED && fwd.stage && p->fwd_work.n_items > 0 && !p->no_interleave)
-        ws = forward_workspace(s, interleaved_bytes(geometry->image_size, batch, dtype), &ws_bytes);
+        ws = stream_workspace(s, interleaved_bytes(geometry->image_size, batch, dtype), &ws_bytes);
     hipError_t e = launch_forward(p->geom, p->fwd_work, dtype, fwd, x, y, batch, scale, ws,
                                   ws_bytes, s);
     return e == hipSuccess ? RADON_OK : RADON_ERR_HIP;
@@ -639,7 +672,14 @@ int radon_backproject(const radon_geometry_t *geometry, const void *y, void *x, 
     if ((rc = get_plan(geometry, s, &p)) != RADON_OK) return rc;
     LaunchShape fwd, bp;
     call_shapes(p, dtype, batch, fwd, bp);
-    hipError_t e = launch_backproject(p->geom, p->bp_work, dtype, bp, y, x, batch, scale, s);
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    if (bp.variant == VARIANT_TILED && bp.stage && p->bp_work.window > 0)
+        ws = stream_workspace(s, interleaved_sino_bytes(p->geom.n_angles, p->geom.det_count,
+                                                        p->bp_work.window, batch, dtype),
+                              &ws_bytes);
+    hipError_t e = launch_backproject(p->geom, p->bp_work, dtype, bp, y, x, batch, scale, ws,
+                                      ws_bytes, s);
     return e == hipSuccess ? RADON_OK : RADON_ERR_HIP;
 }
 
@@ -678,7 +718,7 @@ int radon_plan_info(const radon_geometry_t *geometry, int32_t dtype, int32_t bat
     if ((rc = get_plan(geometry, nullptr, &p)) != RADON_OK) return rc;
     LaunchShape fwd, bp;
     call_shapes(p, dtype, std::max(batch, 1), fwd, bp);
-    bp.stage = 0;
+    if (bp.variant != VARIANT_TILED) bp.stage = 0;
     if (fwd.variant != VARIANT_TILED || p->no_interleave) fwd.stage = 0;
     const LaunchShape *sh[2] = {&fwd, &bp};
     for (int i = 0; i < 2; ++i) {

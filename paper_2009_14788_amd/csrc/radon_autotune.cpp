@@ -5,10 +5,11 @@
 // staging {interleaved copy, caller's images}, and the direct kernel.
 // Backprojection candidates: images per lane {32, 16} x angles per LDS block {8, 4}
 // (parallel beam; the fan beam's block is fixed at 4 because its rays are staged
-// too), and the direct kernel.  The direct kernels win on tiny problems, where the
+// too) x sinogram staging {interleaved copy, caller's sinograms}, and the direct kernel.  The direct kernels win on tiny problems, where the
 // tiled kernels' sequential slabs and angle blocks are latency-bound.  Results live in the plan
 // and, when RADON_TUNE_CACHE names a file, in that file (one line per entry:
-// "<key> <fwd variant> <fwd images> <fwd stage> <bp variant> <bp images> <bp angles>"),
+// "<key> <fwd variant> <fwd images> <fwd stage> <bp variant> <bp images> <bp angles>
+// <bp stage>"),
 // so later processes skip the timing.
 #include <hip/hip_runtime.h>
 
@@ -45,14 +46,15 @@ static bool cache_lookup(const std::string &key, TunedShapes &out) {
     while (std::getline(f, line)) {
         std::istringstream ls(line);
         std::string k;
-        int fv, fi, fs, bv, bi, ba;
-        if (!(ls >> k >> fv >> fi >> fs >> bv >> bi >> ba) || k != key) continue;
+        int fv, fi, fs, bv, bi, ba, bs;
+        if (!(ls >> k >> fv >> fi >> fs >> bv >> bi >> ba >> bs) || k != key) continue;
         out.fwd_variant = fv;
         out.bp_variant = bv;
         out.fwd_images = fi;
         out.fwd_stage = fs;
         out.bp_images = bi;
         out.bp_angles = ba;
+        out.bp_stage = bs;
         return true;
     }
     return false;
@@ -63,7 +65,7 @@ static void cache_store(const std::string &key, const TunedShapes &t) {
     if (!path || !*path) return;
     std::ofstream f(path, std::ios::app);
     f << key << " " << t.fwd_variant << " " << t.fwd_images << " " << t.fwd_stage << " "
-      << t.bp_variant << " " << t.bp_images << " " << t.bp_angles << "\n";
+      << t.bp_variant << " " << t.bp_images << " " << t.bp_angles << " " << t.bp_stage << "\n";
 }
 
 // Average milliseconds of `reps` launches after one warm-up; a negative value when
@@ -92,6 +94,7 @@ int autotune(Plan &p, int dtype, int batch, void *ws, size_t ws_bytes, TunedShap
     out.fwd_stage = p.fwd_shape.stage;
     out.bp_images = p.bp_shape.images;
     out.bp_angles = p.bp_shape.angles;
+    out.bp_stage = p.bp_shape.stage;
     out.fwd_variant = p.fwd_shape.variant;
     out.bp_variant = p.bp_shape.variant;
     if (cache_lookup(key, out)) {
@@ -138,26 +141,30 @@ int autotune(Plan &p, int dtype, int batch, void *ws, size_t ws_bytes, TunedShap
         float best = time_launches([&] {
             LaunchShape sh = p.bp_shape;
             sh.variant = VARIANT_DIRECT;
-            return launch_backproject(p.geom, p.bp_work, dtype, sh, y, x, batch, 1.0f, s);
+            return launch_backproject(p.geom, p.bp_work, dtype, sh, y, x, batch, 1.0f, ws, ws_bytes, s);
         }, s);
         out.bp_variant = VARIANT_DIRECT;
         const std::vector<int> abs = p.geom.fan ? std::vector<int>{kBpAnglesFan}
                                                 : std::vector<int>{kBpAngles, 4};
         for (int im : {32, 16})
-            for (int ab : abs) {
-                LaunchShape sh = p.bp_shape;
-                sh.images = im;
-                sh.angles = ab;
-                const float ms = time_launches([&] {
-                    return launch_backproject(p.geom, p.bp_work, dtype, sh, y, x, batch, 1.0f, s);
-                }, s);
-                if (ms > 0.0f && (best < 0.0f || ms < best)) {
-                    best = ms;
-                    out.bp_variant = VARIANT_TILED;
-                    out.bp_images = im;
-                    out.bp_angles = ab;
+            for (int ab : abs)
+                for (int st : {1, 0}) {
+                    LaunchShape sh = p.bp_shape;
+                    sh.images = im;
+                    sh.angles = ab;
+                    sh.stage = st;
+                    const float ms = time_launches([&] {
+                        return launch_backproject(p.geom, p.bp_work, dtype, sh, y, x, batch, 1.0f, ws,
+                                                  ws_bytes, s);
+                    }, s);
+                    if (ms > 0.0f && (best < 0.0f || ms < best)) {
+                        best = ms;
+                        out.bp_variant = VARIANT_TILED;
+                        out.bp_images = im;
+                        out.bp_angles = ab;
+                        out.bp_stage = st;
+                    }
                 }
-            }
     }
     (void)hipDeviceSynchronize();
     (void)hipFree(x);

@@ -61,12 +61,13 @@ template <typename T, int BC>
 __device__ __forceinline__ void bp_unit(const BatchJob &j, const WorkUnit &u,
                                         const ImageGroup &grp, uint4 *lds) {
     const ImageSet<T, BC> imgs = group_images<T, BC>(grp);
+    const SinoPointerSource<T, BC> src{imgs.in, j.g.det_count};
     if (!j.g.fan)
-        bp_tile_par<T, BC, 3, 3>(j.g, u.unit, imgs, j.window, lds);
+        bp_tile_par<T, BC, 3, 3, kBpAngles>(j.g, u.unit, imgs, src, j.window, lds);
     else if (j.bins <= 4)
-        bp_tile_fan<T, BC, 4, 3>(j.g, u.unit, imgs, j.window, lds);
+        bp_tile_fan<T, BC, 4, 3>(j.g, u.unit, imgs, src, j.window, lds);
     else
-        bp_tile_fan<T, BC, 6, 3>(j.g, u.unit, imgs, j.window, lds);
+        bp_tile_fan<T, BC, 6, 3>(j.g, u.unit, imgs, src, j.window, lds);
 }
 
 template <typename T>

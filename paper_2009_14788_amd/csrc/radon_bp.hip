@@ -105,7 +105,28 @@ __global__ __launch_bounds__(256) void bp_tiled_par(Geom g, const T *__restrict_
     extern __shared__ uint4 lds[];
     const ImageSet<T, BC> imgs = contiguous_images<T, BC>(
         y, (size_t)g.n_angles * g.det_count, x, (size_t)g.n * g.n, batch, blockIdx.y * BC, scale_dt);
-    bp_tile_par<T, BC, NB, NK, AB>(g, blockIdx.x, imgs, W, lds);
+    const SinoPointerSource<T, BC> src{imgs.in, g.det_count};
+    bp_tile_par<T, BC, NB, NK, AB>(g, blockIdx.x, imgs, src, W, lds);
+}
+
+// Same, staging from the interleaved, zero-padded copy yi of the batch's sinograms.
+template <typename T, int BC, int NB, int NK, int AB>
+__global__ __launch_bounds__(256) void bp_tiled_par_il(Geom g, const uint4 *__restrict__ yi,
+                                                       T *__restrict__ x, int batch, float scale_dt,
+                                                       int W) {
+    extern __shared__ uint4 lds[];
+    constexpr int CH = Chunk<T>::kImages;
+    const int b0 = blockIdx.y * BC;
+    // only the output side of the image set is used with an interleaved source
+    const ImageSet<T, BC> imgs = contiguous_images<T, BC>(x, 0, x, (size_t)g.n * g.n, batch, b0, scale_dt);
+    const int Dp = g.det_count + 2 * W;
+    SinoInterleavedSource<T, BC> src;
+    src.plane_stride = g.n_angles * Dp;
+    src.base = yi + (size_t)(b0 / CH) * src.plane_stride;
+    src.D = g.det_count;
+    src.Dp = Dp;
+    src.setup(W, AB * W);
+    bp_tile_par<T, BC, NB, NK, AB>(g, blockIdx.x, imgs, src, W, lds);
 }
 
 template <typename T, int BC, int NB, int NK>
@@ -115,7 +136,53 @@ __global__ __launch_bounds__(256) void bp_tiled_fan(Geom g, const T *__restrict_
     extern __shared__ uint4 lds[];
     const ImageSet<T, BC> imgs = contiguous_images<T, BC>(
         y, (size_t)g.n_angles * g.det_count, x, (size_t)g.n * g.n, batch, blockIdx.y * BC, scale_dt);
-    bp_tile_fan<T, BC, NB, NK>(g, blockIdx.x, imgs, W, lds);
+    const SinoPointerSource<T, BC> src{imgs.in, g.det_count};
+    bp_tile_fan<T, BC, NB, NK>(g, blockIdx.x, imgs, src, W, lds);
+}
+
+template <typename T, int BC, int NB, int NK>
+__global__ __launch_bounds__(256) void bp_tiled_fan_il(Geom g, const uint4 *__restrict__ yi,
+                                                       T *__restrict__ x, int batch, float scale_dt,
+                                                       int W) {
+    extern __shared__ uint4 lds[];
+    constexpr int CH = Chunk<T>::kImages;
+    const int b0 = blockIdx.y * BC;
+    const ImageSet<T, BC> imgs = contiguous_images<T, BC>(x, 0, x, (size_t)g.n * g.n, batch, b0, scale_dt);
+    const int Dp = g.det_count + 2 * W;
+    SinoInterleavedSource<T, BC> src;
+    src.plane_stride = g.n_angles * Dp;
+    src.base = yi + (size_t)(b0 / CH) * src.plane_stride;
+    src.D = g.det_count;
+    src.Dp = Dp;
+    src.setup(W, kBpAnglesFan * W);
+    bp_tile_fan<T, BC, NB, NK>(g, blockIdx.x, imgs, src, W, lds);
+}
+
+// Interleave sinograms y[B][A][D] into yi[groups][A][D + 2W] chunks of CH images with
+// W zero bins on either side (images past B are zero).  Grid: (bins, A, groups).
+template <typename T>
+__global__ __launch_bounds__(256) void interleave_sinograms(const T *__restrict__ y, uint4 *__restrict__ yi,
+                                                            int A, int D, int W, int batch) {
+    constexpr int CH = Chunk<T>::kImages;
+    const int Dp = D + 2 * W;
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= Dp) return;
+    const int a = blockIdx.y, grp = blockIdx.z;
+    const int d = p - W;
+    const bool inside = (unsigned)d < (unsigned)D;
+    T v[CH];
+#pragma unroll
+    for (int e = 0; e < CH; ++e) {
+        const int b = grp * CH + e;
+        v[e] = (inside && b < batch) ? y[((size_t)b * A + a) * D + d] : Chunk<T>::zero();
+    }
+    yi[((size_t)grp * A + a) * Dp + p] = Chunk<T>::pack(v);
+}
+
+size_t interleaved_sino_bytes(int n_angles, int det_count, int window, int batch, int dtype) {
+    const int ch = dtype == F32 ? 4 : 8;
+    const size_t groups = ((size_t)batch + 31) / 32 * 32 / ch;   // whole 32-image blocks
+    return groups * (size_t)n_angles * (size_t)(det_count + 2 * window) * sizeof(uint4);
 }
 
 template <typename T, int BC>
@@ -129,51 +196,86 @@ static hipError_t launch_bp_direct(const Geom &g, const void *y, void *x, int ba
 }
 
 template <typename T, int BC>
-static hipError_t launch_bp_tiled(const Geom &g, const BpWork &work, int angles, const void *y,
-                                  void *x, int batch, float scale_dt, hipStream_t s) {
-    constexpr int PLANES = BC / Chunk<T>::kImages;
+static hipError_t launch_bp_tiled(const Geom &g, const BpWork &work, const LaunchShape &shape,
+                                  const void *y, void *x, int batch, float scale_dt, void *ws,
+                                  size_t ws_bytes, hipStream_t s) {
+    constexpr int CH = Chunk<T>::kImages;
+    constexpr int PLANES = BC / CH;
+    const int W = work.window;
     const int tiles = ((g.n + kBpTile - 1) / kBpTile) * ((g.n + kBpTile - 1) / kBpTile);
     dim3 grid(tiles, (batch + BC - 1) / BC);
+    const int dt = sizeof(T) == 4 ? F32 : F16;
+    const int groups = (batch + BC - 1) / BC * PLANES;
+    // the interleaved copy: room in the workspace, slots for the window, 32-bit offsets
+    const bool il = shape.stage && ws &&
+                    ws_bytes >= interleaved_sino_bytes(g.n_angles, g.det_count, W, batch, dt) &&
+                    PLANES * W <= 256 * SinoInterleavedSource<T, BC>::kSlots &&
+                    (double)PLANES * g.n_angles * (g.det_count + 2.0 * W) < 2.0e9;
+    if (il) {
+        dim3 ig((g.det_count + 2 * W + 255) / 256, g.n_angles, groups);
+        hipLaunchKernelGGL(interleave_sinograms<T>, ig, dim3(256), 0, s, (const T *)y, (uint4 *)ws,
+                           g.n_angles, g.det_count, W, batch);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const uint4 *yi = (const uint4 *)ws;
     if (!g.fan) {
-        if (angles <= 4) {
-            const size_t lds = (size_t)PLANES * 4 * work.window * sizeof(uint4);
-            hipLaunchKernelGGL((bp_tiled_par<T, BC, 3, 3, 4>), grid, dim3(256), lds, s, g,
-                               (const T *)y, (T *)x, batch, scale_dt, work.window);
+        if (shape.angles <= 4) {
+            const size_t lds = (size_t)PLANES * 4 * W * sizeof(uint4);
+            if (il)
+                hipLaunchKernelGGL((bp_tiled_par_il<T, BC, 3, 3, 4>), grid, dim3(256), lds, s, g, yi,
+                                   (T *)x, batch, scale_dt, W);
+            else
+                hipLaunchKernelGGL((bp_tiled_par<T, BC, 3, 3, 4>), grid, dim3(256), lds, s, g,
+                                   (const T *)y, (T *)x, batch, scale_dt, W);
         } else {
-            const size_t lds = (size_t)PLANES * kBpAngles * work.window * sizeof(uint4);
-            hipLaunchKernelGGL((bp_tiled_par<T, BC, 3, 3, kBpAngles>), grid, dim3(256), lds, s, g,
-                               (const T *)y, (T *)x, batch, scale_dt, work.window);
+            const size_t lds = (size_t)PLANES * kBpAngles * W * sizeof(uint4);
+            if (il)
+                hipLaunchKernelGGL((bp_tiled_par_il<T, BC, 3, 3, kBpAngles>), grid, dim3(256), lds, s,
+                                   g, yi, (T *)x, batch, scale_dt, W);
+            else
+                hipLaunchKernelGGL((bp_tiled_par<T, BC, 3, 3, kBpAngles>), grid, dim3(256), lds, s, g,
+                                   (const T *)y, (T *)x, batch, scale_dt, W);
         }
     } else {
-        const size_t lds = (size_t)PLANES * kBpAnglesFan * work.window * sizeof(uint4) +
-                           (size_t)kBpAnglesFan * work.window * sizeof(double4);
-        if (work.bins <= 4)
-            hipLaunchKernelGGL((bp_tiled_fan<T, BC, 4, 3>), grid, dim3(256), lds, s, g,
-                               (const T *)y, (T *)x, batch, scale_dt, work.window);
-        else
-            hipLaunchKernelGGL((bp_tiled_fan<T, BC, 6, 3>), grid, dim3(256), lds, s, g,
-                               (const T *)y, (T *)x, batch, scale_dt, work.window);
+        const size_t lds = (size_t)PLANES * kBpAnglesFan * W * sizeof(uint4) +
+                           (size_t)kBpAnglesFan * W * sizeof(double4);
+        if (work.bins <= 4) {
+            if (il)
+                hipLaunchKernelGGL((bp_tiled_fan_il<T, BC, 4, 3>), grid, dim3(256), lds, s, g, yi,
+                                   (T *)x, batch, scale_dt, W);
+            else
+                hipLaunchKernelGGL((bp_tiled_fan<T, BC, 4, 3>), grid, dim3(256), lds, s, g,
+                                   (const T *)y, (T *)x, batch, scale_dt, W);
+        } else {
+            if (il)
+                hipLaunchKernelGGL((bp_tiled_fan_il<T, BC, 6, 3>), grid, dim3(256), lds, s, g, yi,
+                                   (T *)x, batch, scale_dt, W);
+            else
+                hipLaunchKernelGGL((bp_tiled_fan<T, BC, 6, 3>), grid, dim3(256), lds, s, g,
+                                   (const T *)y, (T *)x, batch, scale_dt, W);
+        }
     }
     return hipGetLastError();
 }
 
 hipError_t launch_backproject(const Geom &g, const BpWork &work, int dtype, const LaunchShape &shape,
-                              const void *y, void *x, int batch, float scale, hipStream_t s) {
+                              const void *y, void *x, int batch, float scale, void *ws,
+                              size_t ws_bytes, hipStream_t s) {
     // every matrix entry carries the step length: R = step * (sum of sample weights)
     const float scale_dt = (float)(scale * g.step);
     if (shape.variant == VARIANT_TILED && work.window > 0) {
         const bool wide = shape.images >= 32;
-        const int ab = shape.angles;
         switch (dtype) {
         case F32:
-            return wide ? launch_bp_tiled<float, 32>(g, work, ab, y, x, batch, scale_dt, s)
-                        : launch_bp_tiled<float, 16>(g, work, ab, y, x, batch, scale_dt, s);
+            return wide ? launch_bp_tiled<float, 32>(g, work, shape, y, x, batch, scale_dt, ws, ws_bytes, s)
+                        : launch_bp_tiled<float, 16>(g, work, shape, y, x, batch, scale_dt, ws, ws_bytes, s);
         case F16:
-            return wide ? launch_bp_tiled<__half, 32>(g, work, ab, y, x, batch, scale_dt, s)
-                        : launch_bp_tiled<__half, 16>(g, work, ab, y, x, batch, scale_dt, s);
+            return wide ? launch_bp_tiled<__half, 32>(g, work, shape, y, x, batch, scale_dt, ws, ws_bytes, s)
+                        : launch_bp_tiled<__half, 16>(g, work, shape, y, x, batch, scale_dt, ws, ws_bytes, s);
         case BF16:
-            return wide ? launch_bp_tiled<bf16_t, 32>(g, work, ab, y, x, batch, scale_dt, s)
-                        : launch_bp_tiled<bf16_t, 16>(g, work, ab, y, x, batch, scale_dt, s);
+            return wide ? launch_bp_tiled<bf16_t, 32>(g, work, shape, y, x, batch, scale_dt, ws, ws_bytes, s)
+                        : launch_bp_tiled<bf16_t, 16>(g, work, shape, y, x, batch, scale_dt, ws, ws_bytes, s);
         default: return hipErrorInvalidValue;
         }
     }

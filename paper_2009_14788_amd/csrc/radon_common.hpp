@@ -137,6 +137,19 @@ struct Geom {
     double sde;          // fan: S + E
     const double2 *trig; // [A] (cos, sin) of each angle
     const double4 *rays; // fan: [A*D] (ox, oy, sx, sy)
+    const struct BpAngle *bpa;  // parallel: [A] per-angle backprojection constants
+};
+
+// Per-angle constants of the parallel-beam backprojection, formed on the host in FP64
+// once per geometry: the pixel at centred coordinates (qx, qy) has bin coordinate
+// u = qx*cu + qy*su + (D-1)/2 and step coordinate v = qy*cv - qx*sv.
+struct BpAngle {
+    double cu, su;   // cos / spacing, sin / spacing
+    double cv, sv;   // cos / step, sin / step
+    double hu, hv;   // (|cos| + |sin|) / spacing, (|cos| + |sin|) / step
+    float cf, sf;    // cos, sin
+    float ux, uy;    // one bin along the detector: spacing * (cos, sin)
+    float vx, vy;    // one step along the ray: step * (-sin, cos)
 };
 
 // Ray parameters of (angle a, bin d), FP64: foot point in index coordinates and

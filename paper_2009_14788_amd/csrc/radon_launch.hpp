@@ -84,8 +84,14 @@ struct BpWork {
 BpWork plan_backproject(int beam, int n, const std::vector<double2> &trig, double spacing,
                         double step, double source_distance, double det_distance);
 
+// Backprojection of a batch (tiled kernels when the shape asks for them and work
+// applies).  With shape.stage, a workspace ws of at least
+// interleaved_sino_bytes(A, D, window, batch, dtype) bytes receives an interleaved,
+// zero-padded copy of the sinograms first and the tiled kernel stages from it.
 hipError_t launch_backproject(const Geom &g, const BpWork &work, int dtype, const LaunchShape &shape,
-                              const void *y, void *x, int batch, float scale, hipStream_t s);
+                              const void *y, void *x, int batch, float scale, void *ws,
+                              size_t ws_bytes, hipStream_t s);
+size_t interleaved_sino_bytes(int n_angles, int det_count, int window, int batch, int dtype);
 hipError_t launch_dot_f64(const void *a, const void *b, long long n, int dtype, double *out,
                           double *partials, int n_partials, hipStream_t s);
 

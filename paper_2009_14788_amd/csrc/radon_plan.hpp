@@ -32,7 +32,7 @@ struct TunedShapes {
     bool valid = false;
     int fwd_variant = VARIANT_TILED, bp_variant = VARIANT_TILED;
     int fwd_images = 8, fwd_stage = 1;
-    int bp_images = 32, bp_angles = 8;
+    int bp_images = 32, bp_angles = 8, bp_stage = 1;
 };
 
 struct Plan {
@@ -40,6 +40,7 @@ struct Plan {
     Geom geom{};
     double2 *trig = nullptr;  // device [A]
     double4 *rays = nullptr;  // device [A*D], fan beam only
+    BpAngle *bpa = nullptr;   // device [A], parallel beam only
     FwdItem *fwd_items = nullptr;  // device, tiled forward work items
     int2 *fwd_ranges = nullptr;    // device, per item and slab transverse ranges
     FwdWork fwd_work;

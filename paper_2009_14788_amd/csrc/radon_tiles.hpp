@@ -278,47 +278,21 @@ __device__ __forceinline__ void fwd_item(const Geom &g, const FwdItem &it, const
 }
 
 // ------------------------------------------------------------------ backprojection
-// Parallel beam.  One block = a 16x16 pixel tile (lane <-> pixel) x BC images.
-// Angles are processed in blocks of AB: for each, the block stages into LDS
-// the window of W bins its tile can touch, as 16-byte chunks of Chunk<T>::kImages
-// images ("planes").  Each pixel then finds, per angle, the lattice samples
-// (bin d, step k) whose bilinear footprint covers it: the pixel's continuous
-// lattice coordinates (u*, v*) are formed in FP64, the NB x NK candidates
-// d = floor(u* - hu) + 1 + i, k = floor(v* - hv) + 1 + j cover every sample within
-// the footprint, and their offsets from the pixel are small FP32 numbers, so the
-// tent weights are accurate to FP32 rounding.  The NB bin weights are then applied
-// to BC images with 16-byte LDS reads.  No atomics.
-template <typename T, int BC, int NB, int NK, int AB = kBpAngles>
-__device__ __forceinline__ void bp_tile_par(const Geom &g, int tile, const ImageSet<T, BC> &imgs,
-                                            int W, uint4 *lds) {
-    __shared__ int wlo_s[AB];
-    constexpr int CH = Chunk<T>::kImages;
-    constexpr int PLANES = BC / CH;
-    static_assert(BC % CH == 0, "BC must be a multiple of the images per chunk");
-    const int n = g.n, A = g.n_angles, D = g.det_count;
-    const int tiles_x = (n + kBpTile - 1) / kBpTile;
-    const int tx0 = (tile % tiles_x) * kBpTile, ty0 = (tile / tiles_x) * kBpTile;
-    const int c = tx0 + (threadIdx.x % kBpTile), r = ty0 + (threadIdx.x / kBpTile);
-    const double qx = (double)c - g.cn, qy = (double)r - g.cn;
-    const double tcx = tx0 + 0.5 * (kBpTile - 1) - g.cn, tcy = ty0 + 0.5 * (kBpTile - 1) - g.cn;
-    const int per_plane = AB * W;
-    const T *const *img_base = imgs.in;
-    const float dt = (float)g.step, sp = (float)g.spacing;
+// Sinogram staging sources.  For angles a0 .. a0+na-1 of a block, both fill the
+// window of W bins starting at bin wlo_s[al] of angle a0+al (zero outside the
+// detector) into LDS chunk planes: chunk (plane q, angle al, bin j) at
+// q * per_plane + al * W + j.
 
-    float acc[BC];
-#pragma unroll
-    for (int i = 0; i < BC; ++i) acc[i] = 0.0f;
-
-    for (int a0 = 0; a0 < A; a0 += AB) {
-        const int na = min(AB, A - a0);
-        __syncthreads();                                // previous block consumed
-        if (threadIdx.x < na) {
-            const double2 cs = g.trig[a0 + threadIdx.x];
-            const double h = fabs(cs.x) + fabs(cs.y);
-            const double uc = fma(fma(tcx, cs.x, tcy * cs.y), g.inv_spacing, g.half_d);
-            wlo_s[threadIdx.x] = (int)floor(uc - (0.5 * (kBpTile - 1) + 1.0) * h * g.inv_spacing) - 1;
-        }
-        __syncthreads();
+// From the callers' sinograms (BC per-image pointers): one (angle, bin) pair per
+// thread, one scalar load per image.
+template <typename T, int BC>
+struct SinoPointerSource {
+    const T *const *img;
+    int D;
+    __device__ __forceinline__ void stage(uint4 *lds, int a0, int na, int W, const int *wlo_s,
+                                          int per_plane) const {
+        constexpr int CH = Chunk<T>::kImages;
+        constexpr int PLANES = BC / CH;
         for (int p = threadIdx.x; p < na * W; p += 256) {
             const int al = p / W, j = p - al * W;
             const int d = wlo_s[al] + j;
@@ -329,12 +303,94 @@ __device__ __forceinline__ void bp_tile_par(const Geom &g, int tile, const Image
                 T v[CH];
 #pragma unroll
                 for (int e = 0; e < CH; ++e) {
-                    const T val = img_base[q * CH + e][off];   // always a valid address
+                    const T val = img[q * CH + e][off];   // always a valid address
                     v[e] = inside ? val : Chunk<T>::zero();
                 }
                 lds[q * per_plane + al * W + j] = Chunk<T>::pack(v);
             }
         }
+    }
+};
+
+// From the interleaved copy of the batch's sinograms, [groups][A][D + 2W] chunks of
+// Chunk<T>::kImages images with W zero bins on either side: one 16-byte copy per
+// chunk.  A window starting below -W or above D lies wholly in the zero region and is
+// read from the nearest padded position instead.  Each thread owns up to kSlots
+// fixed (plane, bin) slots of the window, set up once per block.
+template <typename T, int BC>
+struct SinoInterleavedSource {
+    static constexpr int kSlots = 4;
+    const uint4 *base;     // first plane of the block's images
+    int plane_stride;      // chunks between planes (A * (D + 2W))
+    int D, Dp;             // detector bins, padded row length D + 2W
+    int src_off[kSlots], lds_off[kSlots], slots;
+
+    // slot k of this thread: element f = threadIdx + 256 k of the (plane, bin) window
+    __device__ __forceinline__ void setup(int W, int per_plane) {
+        constexpr int PLANES = BC / Chunk<T>::kImages;
+        slots = 0;
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k) {
+            const int f = (int)threadIdx.x + 256 * k;
+            const int q = f / W, j = f - q * W;
+            src_off[k] = q * plane_stride + W + j;
+            lds_off[k] = q * per_plane + j;
+            if (f < PLANES * W) slots = k + 1;
+        }
+    }
+    __device__ __forceinline__ void stage(uint4 *lds, int a0, int na, int W, const int *wlo_s,
+                                          int /*per_plane*/) const {
+        for (int al = 0; al < na; ++al) {
+            const int w0 = min(max(wlo_s[al], -W), D);
+            const uint4 *row = base + (size_t)(a0 + al) * Dp + w0;
+            uint4 *drow = lds + al * W;
+#pragma unroll
+            for (int k = 0; k < kSlots; ++k)
+                if (k < slots) drow[lds_off[k]] = row[src_off[k]];
+        }
+    }
+};
+
+// Parallel beam.  One block = a 16x16 pixel tile (lane <-> pixel) x BC images.
+// Angles are processed in blocks of AB: for each, the block stages into LDS
+// the window of W bins its tile can touch, as 16-byte chunks of Chunk<T>::kImages
+// images ("planes").  Each pixel then finds, per angle, the lattice samples
+// (bin d, step k) whose bilinear footprint covers it: the pixel's continuous
+// lattice coordinates (u*, v*) are formed in FP64 from per-angle constants, the
+// NB x NK candidates d = floor(u* - hu) + 1 + i, k = floor(v* - hv) + 1 + j cover
+// every sample within the footprint, and their offsets from the pixel are small FP32
+// numbers, so the tent weights are accurate to FP32 rounding.  The NB bin weights are
+// then applied to BC images with 16-byte LDS reads.  No atomics.
+template <typename T, int BC, int NB, int NK, int AB, class Source>
+__device__ __forceinline__ void bp_tile_par(const Geom &g, int tile, const ImageSet<T, BC> &imgs,
+                                            const Source &src, int W, uint4 *lds) {
+    __shared__ int wlo_s[AB];
+    constexpr int CH = Chunk<T>::kImages;
+    constexpr int PLANES = BC / CH;
+    static_assert(BC % CH == 0, "BC must be a multiple of the images per chunk");
+    const int n = g.n, A = g.n_angles;
+    const int tiles_x = (n + kBpTile - 1) / kBpTile;
+    const int tx0 = (tile % tiles_x) * kBpTile, ty0 = (tile / tiles_x) * kBpTile;
+    const int c = tx0 + (threadIdx.x % kBpTile), r = ty0 + (threadIdx.x / kBpTile);
+    const double qx = (double)c - g.cn, qy = (double)r - g.cn;
+    const double tcx = tx0 + 0.5 * (kBpTile - 1) - g.cn, tcy = ty0 + 0.5 * (kBpTile - 1) - g.cn;
+    const int per_plane = AB * W;
+    const float dt = (float)g.step, sp = (float)g.spacing;
+
+    float acc[BC];
+#pragma unroll
+    for (int i = 0; i < BC; ++i) acc[i] = 0.0f;
+
+    for (int a0 = 0; a0 < A; a0 += AB) {
+        const int na = min(AB, A - a0);
+        __syncthreads();                                // previous block consumed
+        if (threadIdx.x < na) {
+            const BpAngle ba = g.bpa[a0 + threadIdx.x];
+            const double uc = fma(tcx, ba.cu, fma(tcy, ba.su, g.half_d));
+            wlo_s[threadIdx.x] = (int)floor(uc - (0.5 * (kBpTile - 1) + 1.0) * ba.hu) - 1;
+        }
+        __syncthreads();
+        src.stage(lds, a0, na, W, wlo_s, per_plane);
         __syncthreads();
 
         // the angle block's contributions are summed separately, then added to the
@@ -343,18 +399,14 @@ __device__ __forceinline__ void bp_tile_par(const Geom &g, int tile, const Image
 #pragma unroll
         for (int i = 0; i < BC; ++i) part[i] = 0.0f;
         for (int al = 0; al < na; ++al) {
-            const double2 cs = g.trig[a0 + al];
-            const double h = fabs(cs.x) + fabs(cs.y);
+            const BpAngle ba = g.bpa[a0 + al];
             // continuous bin (u) and step (v) coordinates of the pixel centre
-            const double u = fma(fma(qx, cs.x, qy * cs.y), g.inv_spacing, g.half_d);
-            const double v = fma(qy, cs.x, -qx * cs.y) * g.inv_step;
-            const double db = floor(u - h * g.inv_spacing), kb = floor(v - h * g.inv_step);
+            const double u = fma(qx, ba.cu, fma(qy, ba.su, g.half_d));
+            const double v = fma(qy, ba.cv, -qx * ba.sv);
+            const double db = floor(u - ba.hu), kb = floor(v - ba.hv);
             // offset of candidate (d = db+1+i, k = kb+1+j) from the pixel, along u and v
             const float e0 = (float)(db + 1.0 - u) * sp, t0 = (float)(kb + 1.0 - v) * dt;
-            const float cf = (float)cs.x, sf = (float)cs.y;
-            const float ux = sp * cf, uy = sp * sf;      // one bin along u
-            const float vx = -dt * sf, vy = dt * cf;     // one step along v
-            float dx_i = fmaf(e0, cf, -t0 * sf), dy_i = fmaf(e0, sf, t0 * cf);
+            float dx_i = fmaf(e0, ba.cf, -t0 * ba.sf), dy_i = fmaf(e0, ba.sf, t0 * ba.cf);
             float wgt[NB];
 #pragma unroll
             for (int i = 0; i < NB; ++i) {
@@ -364,12 +416,12 @@ __device__ __forceinline__ void bp_tile_par(const Geom &g, int tile, const Image
                     const float tx = __builtin_amdgcn_fmed3f(1.0f - fabsf(dx), 0.0f, 1.0f);
                     const float ty = __builtin_amdgcn_fmed3f(1.0f - fabsf(dy), 0.0f, 1.0f);
                     w = fmaf(tx, ty, w);
-                    dx += vx;
-                    dy += vy;
+                    dx += ba.vx;
+                    dy += ba.vy;
                 }
                 wgt[i] = w;
-                dx_i += ux;
-                dy_i += uy;
+                dx_i += ba.ux;
+                dy_i += ba.uy;
             }
             int lb = (int)db + 1 - wlo_s[al];
             lb = min(max(lb, 0), W - NB);               // memory safety; real pixels are inside
@@ -397,9 +449,9 @@ __device__ __forceinline__ void bp_tile_par(const Geom &g, int tile, const Image
 // plus a margin far larger than the footprint's curvature); per bin, the NK
 // candidate samples around the pixel's position along that ray are evaluated with
 // FP64 anchors and FP32 offsets, exactly as in the parallel kernel.
-template <typename T, int BC, int NB, int NK>
+template <typename T, int BC, int NB, int NK, class Source>
 __device__ __forceinline__ void bp_tile_fan(const Geom &g, int tile, const ImageSet<T, BC> &imgs,
-                                            int W, uint4 *lds) {
+                                            const Source &src, int W, uint4 *lds) {
     __shared__ int wlo_s[kBpAnglesFan];
     constexpr int CH = Chunk<T>::kImages;
     constexpr int PLANES = BC / CH;
@@ -411,7 +463,6 @@ __device__ __forceinline__ void bp_tile_fan(const Geom &g, int tile, const Image
     const double qx = (double)c - g.cn, qy = (double)r - g.cn;
     const int per_plane = kBpAnglesFan * W;
     double4 *rays_s = reinterpret_cast<double4 *>(lds + PLANES * per_plane);
-    const T *const *img_base = imgs.in;
     const double is2 = g.inv_step * g.inv_step;
 
     float acc[BC];
@@ -435,23 +486,14 @@ __device__ __forceinline__ void bp_tile_fan(const Geom &g, int tile, const Image
             wlo_s[threadIdx.x] = (int)floor(lo) - 1;
         }
         __syncthreads();
+        src.stage(lds, a0, na, W, wlo_s, per_plane);
         for (int p = threadIdx.x; p < na * W; p += 256) {
             const int al = p / W, j = p - al * W;
             const int d = wlo_s[al] + j;
             const bool inside = (unsigned)d < (unsigned)D;
-            const unsigned off = (unsigned)((a0 + al) * D + (inside ? d : 0));
-#pragma unroll
-            for (int q = 0; q < PLANES; ++q) {
-                T v[CH];
-#pragma unroll
-                for (int e = 0; e < CH; ++e) {
-                    const T val = img_base[q * CH + e][off];
-                    v[e] = inside ? val : Chunk<T>::zero();
-                }
-                lds[q * per_plane + al * W + j] = Chunk<T>::pack(v);
-            }
             // a bin outside the detector gets a ray far from every pixel (weight 0)
-            rays_s[al * W + j] = inside ? g.rays[off] : make_double4(-1e9, -1e9, 0.0, 0.0);
+            rays_s[al * W + j] = inside ? g.rays[(size_t)(a0 + al) * D + d]
+                                        : make_double4(-1e9, -1e9, 0.0, 0.0);
         }
         __syncthreads();
 

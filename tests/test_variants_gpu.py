@@ -53,8 +53,9 @@ def _run(tmp_path, tag, env_extra):
 
 def test_all_variants_agree(tmp_path):
     base = _run(tmp_path, "default", {})
-    for fi, fs, bi, ba in [(8, 0, 16, 4), (4, 1, 32, 4), (4, 0, 16, 8), (16, 1, 32, 8), (8, 1, 16, 8)]:
-        got = _run(tmp_path, f"v{fi}{fs}{bi}{ba}", {"RADON_FORCE_SHAPE": f"{fi},{fs},{bi},{ba}"})
+    for fi, fs, bi, ba, bs in [(8, 0, 16, 4, 0), (4, 1, 32, 4, 1), (4, 0, 16, 8, 1), (16, 1, 32, 8, 0),
+                               (8, 1, 16, 8, 1)]:
+        got = _run(tmp_path, f"v{fi}{fs}{bi}{ba}{bs}", {"RADON_FORCE_SHAPE": f"{fi},{fs},{bi},{ba},{bs}"})
         for k in base:
             yb, bb = base[k]
             yg, bg = got[k]
@@ -85,7 +86,7 @@ np.save(sys.argv[2], op.forward_raw(x).cpu().numpy())
     assert r.returncode == 0, r.stderr[-2000:]
     print(r.stdout)
     lines = cache.read_text().strip().splitlines()
-    assert len(lines) == 1 and len(lines[0].split()) == 7
+    assert len(lines) == 1 and len(lines[0].split()) == 8
     y = np.load(tmp_path / "y.npy")
     og = oracle.Geometry(128, inputs.uniform_angles(90), 182, 1.0)
     ref = oracle.forward(og, inputs.phantom_batch(9, 12, 128)[:2].astype(np.float64))
