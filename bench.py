@@ -304,6 +304,7 @@ def variants(op, x, x_np, B, A, D):
     y32 = op.forward_raw(x)
     for name, dt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
         xh = x.to(dt)
+        op.prepare(dt, B)
         ms = _timed(lambda: op.backprojection_raw(op.forward_raw(xh)))
         yh = op.forward_raw(xh)
         res[f"batch128_512_{name}"] = {
@@ -338,7 +339,7 @@ def variants(op, x, x_np, B, A, D):
     op0 = Radon(64, w0.angles(), 91)
     x0_np = inputs.phantom(64, 10, [0, 0])[0][None]
     x0 = torch.from_numpy(x0_np).cuda()
-    y0 = torch.empty((1, 64, 91), device="cuda")
+    op0.prepare(torch.float32, 1)
     eager = _timed(lambda: op0.backprojection_raw(op0.forward_raw(x0)), reps=50, warm=5)
     graph = _graph_ms(lambda: op0.backprojection_raw(op0.forward_raw(x0)), reps=100)
     og0 = oracle.Geometry(64, w0.angles(), 91, 1.0)
@@ -352,6 +353,7 @@ def variants(op, x, x_np, B, A, D):
     op1 = Radon(256, w1.angles(), 363)
     x1_np = inputs.phantom_batch(1, 16, 256)
     x1 = torch.from_numpy(x1_np).cuda()
+    op1.prepare(torch.float32, 16)
     ms = _timed(lambda: op1.backprojection_raw(op1.forward_raw(x1)), reps=20)
     res["batch16_256"] = {"ms_per_step": round(ms, 4), "projections_per_s": round(16 * 256 / (ms * 1e-3), 1),
                           "fwd_rel_l2_vs_oracle_sampled": _sampled_err(oracle.Geometry(256, w1.angles(), 363, 1.0), x1_np, op1.forward_raw(x1), seed=2)}
@@ -398,6 +400,7 @@ def variants(op, x, x_np, B, A, D):
     alpha = 1.0 / lam
     for name, dt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
         x4 = torch.from_numpy(x4_np).cuda().to(dt)
+        op4.prepare(dt, 64)
         ms = _timed(lambda: op4.backprojection_raw(op4.forward_raw(x4), scale=alpha), reps=5)
         y4 = op4.forward_raw(x4)
         e4 = _sampled_err(og4, x4_np, y4, seed=7)

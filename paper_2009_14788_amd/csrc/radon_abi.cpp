@@ -217,7 +217,7 @@ static int build_plan(const radon_geometry_t *g, int device, std::unique_ptr<Pla
         p->fwd_work.n_items = (int)items.size();
         // LDS row pitch: 8 more than a multiple of 16 chunks, so the taps of lanes
         // whose samples sit in neighbouring rows land half a bank cycle apart
-        p->fwd_work.tile_t = (tile_t + 7) / 16 * 16 + 8;
+        p->fwd_work.tile_t = (tile_t + 15 - kFwdPitchMod) / 16 * 16 + kFwdPitchMod;
         p->fwd_shape.variant = VARIANT_TILED;
         const char *il = std::getenv("RADON_FWD_INTERLEAVE");
         p->no_interleave = il && std::strcmp(il, "0") == 0;

@@ -45,6 +45,15 @@ constexpr int kSlabH = RADON_SLAB_H;   // pixel rows (columns) per slab
 #endif
 constexpr int kFwdWaves = RADON_FWD_WAVES;   // angles (waves) per forward work item
 constexpr int kFwdThreads = 64 * kFwdWaves;  // threads per forward block
+#ifndef RADON_FWD_QBINS
+#define RADON_FWD_QBINS 2
+#endif
+constexpr int kFwdQBins = RADON_FWD_QBINS;        // bins per 16-lane quarter wave
+constexpr int kFwdQAngles = 16 / kFwdQBins;       // angles per quarter wave
+#ifndef RADON_FWD_PITCH_MOD
+#define RADON_FWD_PITCH_MOD 8
+#endif
+constexpr int kFwdPitchMod = RADON_FWD_PITCH_MOD; // LDS row pitch = 16k + this (chunks)
 constexpr int kFwdLanes = 64;      // bins per forward item
 constexpr int kTileTMax = 192;     // largest transverse extent of a staged slab
 

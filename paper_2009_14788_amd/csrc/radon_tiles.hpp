@@ -200,13 +200,16 @@ __device__ __forceinline__ void fwd_item(const Geom &g, const FwdItem &it, const
                                          uint4 *lds) {
     const int plane_chunks = (kSlabH + 3) * tile_t;
 
-    // rays of the item -> lanes: a wave takes 4 angles x 16 bins, and each 16-lane
-    // quarter of it 4 neighbouring bins x 4 neighbouring angles, so the quarter's taps
-    // fall on nearby columns (distinct LDS banks) and its rays have similar lengths
-    static_assert(kFwdWaves % 4 == 0, "waves come in groups of four");
+    // rays of the item -> lanes: each 16-lane quarter of a wave takes kFwdQBins
+    // neighbouring bins x kFwdQAngles neighbouring angles (4 x 4), so the quarter's taps
+    // fall on nearby columns (distinct LDS banks) and its rays have similar lengths; a
+    // wave is 4 quarters along the bins, 64 / (4 kFwdQBins) waves cover the 64 bins
+    static_assert(kFwdQBins * kFwdQAngles == 16 && kFwdWaves % kFwdQAngles == 0, "lane mapping");
+    constexpr int kWavesPerGroup = 16 / kFwdQBins;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int ai = 4 * (wave >> 2) + ((lane >> 2) & 3);
-    const int di = 16 * (wave & 3) + 4 * (lane >> 4) + (lane & 3);
+    const int q16 = lane & 15;
+    const int ai = kFwdQAngles * (wave / kWavesPerGroup) + q16 / kFwdQBins;
+    const int di = 4 * kFwdQBins * (wave % kWavesPerGroup) + kFwdQBins * (lane >> 4) + q16 % kFwdQBins;
     const bool active = ai < it.na && di < it.nd;
     const int a = it.a0 + min(ai, it.na - 1), d = it.d0 + min(di, it.nd - 1);
     const int n = g.n;
