@@ -181,7 +181,7 @@ __global__ __launch_bounds__(256) void interleave_sinograms(const T *__restrict_
 
 size_t interleaved_sino_bytes(int n_angles, int det_count, int window, int batch, int dtype) {
     const int ch = dtype == F32 ? 4 : 8;
-    const size_t groups = ((size_t)batch + 31) / 32 * 32 / ch;   // whole 32-image blocks
+    const size_t groups = ((size_t)batch + 63) / 64 * 64 / ch;   // whole 64-image blocks
     return groups * (size_t)n_angles * (size_t)(det_count + 2 * window) * sizeof(uint4);
 }
 
@@ -265,19 +265,21 @@ hipError_t launch_backproject(const Geom &g, const BpWork &work, int dtype, cons
     // every matrix entry carries the step length: R = step * (sum of sample weights)
     const float scale_dt = (float)(scale * g.step);
     if (shape.variant == VARIANT_TILED && work.window > 0) {
-        const bool wide = shape.images >= 32;
+        const int im = shape.images;
+#define RADON_BP_TILED(T, BC) launch_bp_tiled<T, BC>(g, work, shape, y, x, batch, scale_dt, ws, ws_bytes, s)
         switch (dtype) {
         case F32:
-            return wide ? launch_bp_tiled<float, 32>(g, work, shape, y, x, batch, scale_dt, ws, ws_bytes, s)
-                        : launch_bp_tiled<float, 16>(g, work, shape, y, x, batch, scale_dt, ws, ws_bytes, s);
+            return im >= 64 && !g.fan ? RADON_BP_TILED(float, 64)
+                 : im >= 32           ? RADON_BP_TILED(float, 32) : RADON_BP_TILED(float, 16);
         case F16:
-            return wide ? launch_bp_tiled<__half, 32>(g, work, shape, y, x, batch, scale_dt, ws, ws_bytes, s)
-                        : launch_bp_tiled<__half, 16>(g, work, shape, y, x, batch, scale_dt, ws, ws_bytes, s);
+            return im >= 64 && !g.fan ? RADON_BP_TILED(__half, 64)
+                 : im >= 32           ? RADON_BP_TILED(__half, 32) : RADON_BP_TILED(__half, 16);
         case BF16:
-            return wide ? launch_bp_tiled<bf16_t, 32>(g, work, shape, y, x, batch, scale_dt, ws, ws_bytes, s)
-                        : launch_bp_tiled<bf16_t, 16>(g, work, shape, y, x, batch, scale_dt, ws, ws_bytes, s);
+            return im >= 64 && !g.fan ? RADON_BP_TILED(bf16_t, 64)
+                 : im >= 32           ? RADON_BP_TILED(bf16_t, 32) : RADON_BP_TILED(bf16_t, 16);
         default: return hipErrorInvalidValue;
         }
+#undef RADON_BP_TILED
     }
     switch (dtype) {
     case F32: return launch_bp_direct<float, 4>(g, y, x, batch, scale_dt, s);

@@ -397,10 +397,16 @@ __device__ __forceinline__ void bp_tile_par(const Geom &g, int tile, const Image
         __syncthreads();
 
         // the angle block's contributions are summed separately, then added to the
-        // pixel total (two-level summation keeps FP32 rounding small)
-        float part[BC];
+        // pixel total (two-level summation keeps FP32 rounding small); with 64 images
+        // per lane the partial sums would halve the occupancy, so they go straight to
+        // the totals
+        constexpr bool kTwoLevel = BC <= 32;
+        float part_buf[kTwoLevel ? BC : 1];
+        float *part = kTwoLevel ? part_buf : acc;
+        if (kTwoLevel) {
 #pragma unroll
-        for (int i = 0; i < BC; ++i) part[i] = 0.0f;
+            for (int i = 0; i < BC; ++i) part[i] = 0.0f;
+        }
         for (int al = 0; al < na; ++al) {
             const BpAngle ba = g.bpa[a0 + al];
             // continuous bin (u) and step (v) coordinates of the pixel centre
@@ -435,8 +441,10 @@ __device__ __forceinline__ void bp_tile_par(const Geom &g, int tile, const Image
                 for (int i = 0; i < NB; ++i) Chunk<T>::fma(wgt[i], row[qq * per_plane + i], part + qq * CH);
             }
         }
+        if (kTwoLevel) {
 #pragma unroll
-        for (int i = 0; i < BC; ++i) acc[i] += part[i];
+            for (int i = 0; i < BC; ++i) acc[i] += part[i];
+        }
     }
     if (c >= n || r >= n) return;
 #pragma unroll

@@ -54,7 +54,7 @@ def _run(tmp_path, tag, env_extra):
 def test_all_variants_agree(tmp_path):
     base = _run(tmp_path, "default", {})
     for fi, fs, bi, ba, bs in [(8, 0, 16, 4, 0), (4, 1, 32, 4, 1), (4, 0, 16, 8, 1), (16, 1, 32, 8, 0),
-                               (8, 1, 16, 8, 1)]:
+                               (8, 1, 16, 8, 1), (4, 1, 64, 4, 1), (8, 0, 64, 8, 0)]:
         got = _run(tmp_path, f"v{fi}{fs}{bi}{ba}{bs}", {"RADON_FORCE_SHAPE": f"{fi},{fs},{bi},{ba},{bs}"})
         for k in base:
             yb, bb = base[k]
