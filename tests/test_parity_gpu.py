@@ -120,8 +120,12 @@ def test_batch16_256_parallel():
 
 # ------------------------------------------------------------------ headline size, sampled
 def _sampled_check(name, case, x, dt, tol, n_rays=256, n_pix=32, seed=7):
+    """Sampled outputs at full size, in the launch shapes the autotuner picks for this
+    batch (the configuration the benchmark times)."""
     op, og = case.library(), case.oracle()
     B = x.shape[0]
+    op.prepare(TDT[dt], B)
+    shapes = op.plan_info(TDT[dt], B)
     _announce(name + ":forward", case, dt, B)
     y_gpu = op.forward(_dev(x, dt))
     rng = np.random.default_rng(seed)
@@ -137,7 +141,7 @@ def _sampled_check(name, case, x, dt, tol, n_rays=256, n_pix=32, seed=7):
     del xb
     e_bp = rel_l2(xg, oracle.backproject_pixels(og, ys.astype(np.float64), pidx))
     report(name, dtype=dt, fwd_rel_l2_sampled=e_fwd, bp_rel_l2_sampled=e_bp,
-           rays=n_rays, pixels=n_pix)
+           rays=n_rays, pixels=n_pix, shapes=shapes)
     assert e_fwd <= tol and e_bp <= tol, (e_fwd, e_bp)
 
 
