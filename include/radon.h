@@ -27,8 +27,10 @@
  * frees, keeps or reallocates them.  Calls are asynchronous on `stream` (a
  * hipStream_t passed as void*, NULL = the null stream); buffers must stay alive
  * until the stream's work has completed.  The library owns only its per-geometry
- * plans (angle/ray tables, launch shapes), created on first use or by
- * radon_prepare() and kept until radon_release_plans().
+ * plans (angle/ray tables, work items, launch shapes), one workspace per (device,
+ * stream) for the interleaved copy of a call's input (grown on demand, never under
+ * stream capture), and the tables of uneven batches; all are created on first use
+ * (or by radon_prepare()) and kept until radon_release_plans().
  *
  * Errors.  Every entry point returns RADON_OK (0) or a negative status; no C++
  * exception crosses the ABI.  A launch error is reported from the call; a fault
@@ -69,7 +71,7 @@ typedef struct radon_geometry {
     int32_t det_count;         /* D >= 1 */
     const double *angles;      /* host array [A] of angles in radians; read during the call */
     double det_spacing;        /* > 0 */
-    double source_distance;    /* fan only: S > (N/2+1)*sqrt(2), source outside the image */
+    double source_distance;    /* fan only: S > (N+1)/2*sqrt(2), source outside the image */
     double det_distance;       /* fan only: E >= 0 */
     double step;               /* sample spacing along each ray, > 0 (usual value 1) */
 } radon_geometry_t;
@@ -79,10 +81,12 @@ typedef struct radon_geometry {
 int radon_validate(const radon_geometry_t *geometry);
 
 /* Build (or find) the plan of a geometry on the current device for `dtype` and a
- * batch size: angle and ray tables, and launch shapes chosen by timing candidates
- * when autotuning is on (RADON_AUTOTUNE=1, the default; results cached in memory and
- * in the JSON file named by RADON_TUNE_CACHE if set).  Synchronises the device.
- * Call before capturing a stream that will use the geometry. */
+ * batch size: angle and ray tables, work items, the null stream's workspace, and
+ * launch shapes chosen by timing the candidates on the device (unless the environment
+ * sets RADON_AUTOTUNE=0; the choice is kept per storage type and power-of-two batch
+ * class, in memory and, if RADON_TUNE_CACHE names a file, one text line per choice in
+ * that file).  Synchronises the device.  Call before capturing a stream that will use
+ * the geometry. */
 int radon_prepare(const radon_geometry_t *geometry, int32_t dtype, int32_t batch);
 
 /* Forward projection (Sec. 3.1, Sec. 4.1): y[b] = scale * R x[b] for b < batch.
@@ -128,9 +132,9 @@ int radon_release_plans(void);
 /* Launch shape chosen for a geometry/dtype/batch (after radon_prepare):
  * out[0..3] = forward {images per thread, angles per block, staging, variant},
  * out[4..7] = the same for the backprojection.  variant: 0 = direct kernel, 1 = tiled
- * kernel.  staging: 1 when the tiled forward first copies the batch into a
- * zero-bordered, image-interleaved workspace, else 0 (always 0 for the
- * backprojection).  Builds the plan when missing; status codes as radon_forward. */
+ * kernel.  staging: 1 when the tiled kernel first copies the call's input (images,
+ * or sinograms for the backprojection) into a zero-bordered, image-interleaved
+ * workspace, else 0.  Builds the plan when missing; status codes as radon_forward. */
 int radon_plan_info(const radon_geometry_t *geometry, int32_t dtype, int32_t batch,
                     int32_t *out8);
 

@@ -550,7 +550,8 @@ static int run_batched(const radon_job_t *jobs, int32_t n, int32_t dtype, int di
 
 static int release_all() {
     std::lock_guard<std::mutex> lock(g_mutex);
-    if (!g_plans.empty() || !g_scratch.empty() || !g_batches.empty()) (void)hipDeviceSynchronize();
+    if (!g_plans.empty() || !g_scratch.empty() || !g_batches.empty() || !g_workspaces.empty())
+        (void)hipDeviceSynchronize();
     g_batches.clear();
     g_batch_order.clear();
     g_plans.clear();
@@ -567,7 +568,7 @@ static int release_all() {
 
 // Launch shapes for a call: the autotuned ones for this storage type and batch class
 // when radon_prepare has tuned them, else the plan's defaults.
-// RADON_FORCE_SHAPE="fi,fs,bi,ba" overrides both (used to test every variant).
+// RADON_FORCE_SHAPE="fi,fs,bi,ba[,bs]" overrides both (used to test every variant).
 static void call_shapes(Plan *p, int dtype, int batch, LaunchShape &fwd, LaunchShape &bp) {
     fwd = p->fwd_shape;
     bp = p->bp_shape;

@@ -18,12 +18,12 @@ struct LaunchShape {
     int images = 4;       // images per thread (accumulators per lane)
     int angles = 1;       // angles per block (forward: waves; backprojection: LDS angle block)
     int rays = 256;       // forward: bins per block; backprojection: pixels per block
-    int stage = 1;        // forward tiled staging: 1 = interleaved copy, 0 = caller's images
+    int stage = 1;        // tiled staging: 1 = interleaved workspace copy, 0 = caller's buffers
 };
 
 // ------------------------------------------------------------------ tiled forward work
-// One work item of the tiled forward projector: up to 4 angles (one wave each) x up
-// to 64 consecutive bins (one lane each), marched through the image in slabs of
+// One work item of the tiled forward projector: up to kFwdWaves angles x up to 64
+// consecutive bins (one lane per ray), marched through the image in slabs of
 // kSlabH pixel rows (axis 0) or columns (axis 1).  For every slab the item stages
 // into LDS the pixel rows/columns [m_lo-1, m_lo+kSlabH+1] along the march axis and
 // the transverse index range ranges[range + s - slab0] (inclusive, clamped to
@@ -39,7 +39,8 @@ struct FwdItem {
 #ifndef RADON_SLAB_H
 #define RADON_SLAB_H 12
 #endif
-constexpr int kSlabH = RADON_SLAB_H;   // pixel rows (columns) per slab
+constexpr int kSlabH = RADON_SLAB_H;   // pixel rows (columns) per slab (a sweep on the
+                                       // MI355X: 12 beat 8, 10 and 16)
 #ifndef RADON_FWD_WAVES
 #define RADON_FWD_WAVES 8
 #endif

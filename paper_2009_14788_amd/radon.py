@@ -122,6 +122,9 @@ class _Base:
                 ctypes.byref(self._geom), dtype_code(dtype), int(batch)))
 
     def plan_info(self, dtype=torch.float32, batch: int = 1):
+        """Launch shapes used for this storage type and batch size, per direction:
+        images per lane, angles per block, staging (1 = interleaved workspace copy),
+        variant (1 = tiled kernel, 0 = direct kernel)."""
         out = (ctypes.c_int32 * 8)()
         _lib.check("radon_plan_info", _lib.lib.radon_plan_info(
             ctypes.byref(self._geom), dtype_code(dtype), int(batch), out))
