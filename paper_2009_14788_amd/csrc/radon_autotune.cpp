@@ -3,7 +3,7 @@
 //
 // Forward candidates: images per lane {8, 4 (FP32 only), 16 (16-bit only)} x slab
 // staging {interleaved copy, caller's images}, and the direct kernel.
-// Backprojection candidates: images per lane {64 (parallel beam), 32, 16} x angles per LDS block {8, 4}
+// Backprojection candidates: images per lane {64, 32, 16} x angles per LDS block {8, 4}
 // (parallel beam; the fan beam's block is fixed at 4 because its rays are staged
 // too) x sinogram staging {interleaved copy, caller's sinograms}, and the direct kernel.  The direct kernels win on tiny problems, where the
 // tiled kernels' sequential slabs and angle blocks are latency-bound.  Results live in the plan
@@ -146,7 +146,7 @@ int autotune(Plan &p, int dtype, int batch, void *ws, size_t ws_bytes, TunedShap
         out.bp_variant = VARIANT_DIRECT;
         const std::vector<int> abs = p.geom.fan ? std::vector<int>{kBpAnglesFan}
                                                 : std::vector<int>{kBpAngles, 4};
-        const std::vector<int> ims = p.geom.fan ? std::vector<int>{32, 16} : std::vector<int>{64, 32, 16};
+        const std::vector<int> ims{64, 32, 16};
         for (int im : ims)
             for (int ab : abs)
                 for (int st : {1, 0}) {

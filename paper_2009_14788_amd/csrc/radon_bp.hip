@@ -269,13 +269,13 @@ hipError_t launch_backproject(const Geom &g, const BpWork &work, int dtype, cons
 #define RADON_BP_TILED(T, BC) launch_bp_tiled<T, BC>(g, work, shape, y, x, batch, scale_dt, ws, ws_bytes, s)
         switch (dtype) {
         case F32:
-            return im >= 64 && !g.fan ? RADON_BP_TILED(float, 64)
+            return im >= 64 ? RADON_BP_TILED(float, 64)
                  : im >= 32           ? RADON_BP_TILED(float, 32) : RADON_BP_TILED(float, 16);
         case F16:
-            return im >= 64 && !g.fan ? RADON_BP_TILED(__half, 64)
+            return im >= 64 ? RADON_BP_TILED(__half, 64)
                  : im >= 32           ? RADON_BP_TILED(__half, 32) : RADON_BP_TILED(__half, 16);
         case BF16:
-            return im >= 64 && !g.fan ? RADON_BP_TILED(bf16_t, 64)
+            return im >= 64 ? RADON_BP_TILED(bf16_t, 64)
                  : im >= 32           ? RADON_BP_TILED(bf16_t, 32) : RADON_BP_TILED(bf16_t, 16);
         default: return hipErrorInvalidValue;
         }

@@ -508,9 +508,14 @@ __device__ __forceinline__ void bp_tile_fan(const Geom &g, int tile, const Image
         }
         __syncthreads();
 
-        float part[BC];
+        // two-level summation as in the parallel kernel (single level at 64 images)
+        constexpr bool kTwoLevel = BC <= 32;
+        float part_buf[kTwoLevel ? BC : 1];
+        float *part = kTwoLevel ? part_buf : acc;
+        if (kTwoLevel) {
 #pragma unroll
-        for (int i = 0; i < BC; ++i) part[i] = 0.0f;
+            for (int i = 0; i < BC; ++i) part[i] = 0.0f;
+        }
         for (int al = 0; al < na; ++al) {
             const double2 cs = g.trig[a0 + al];
             // detector coordinate of the pixel centre and its gradient (bins per pixel)
@@ -551,8 +556,10 @@ __device__ __forceinline__ void bp_tile_fan(const Geom &g, int tile, const Image
                 for (int i = 0; i < NB; ++i) Chunk<T>::fma(wgt[i], row[qq * per_plane + i], part + qq * CH);
             }
         }
+        if (kTwoLevel) {
 #pragma unroll
-        for (int i = 0; i < BC; ++i) acc[i] += part[i];
+            for (int i = 0; i < BC; ++i) acc[i] += part[i];
+        }
     }
     if (c >= n || r >= n) return;
 #pragma unroll
