@@ -120,6 +120,26 @@ int radon_forward_batched(const radon_job_t *jobs, int32_t n_jobs, int32_t dtype
 int radon_backproject_batched(const radon_job_t *jobs, int32_t n_jobs, int32_t dtype,
                               void *stream);
 
+/* Filters of filtered backprojection (Sec. 3.1.3). */
+enum { RADON_FILTER_RAMLAK = 0, RADON_FILTER_SHEPP_LOGAN = 1, RADON_FILTER_COSINE = 2,
+       RADON_FILTER_HAMMING = 3, RADON_FILTER_HANN = 4 };
+
+/* Sinogram filter of filtered backprojection (Sec. 3.1.3): every projection row of
+ * y[batch][A][D] is filtered in the frequency domain by the band-limited ramp whose
+ * Fourier filter is built as Kak & Slaney (ch. 3, eq. 61) prescribe -- the transform
+ * of the sampled impulse response h(0) = 1/4, h(n) = -1/(pi^2 n^2) for odd n, 0 for
+ * even n, over a zero-padded length L = the smallest power of two >= max(64, 2D) --
+ * times the window of `filter` at the normalised frequency f in [-1/2, 1/2)
+ * (Shepp-Logan sin(pi f)/(pi f), cosine cos(pi f), Hamming 0.54 + 0.46 cos(2 pi f),
+ * Hann 0.5 + 0.5 cos(2 pi f), Ram-Lak 1), and scaled by pi / (A * det_spacing), so
+ * that radon_backproject of the result reconstructs the image when the A angles
+ * cover [0, pi) uniformly.  out may equal y (in place).  FP32 arithmetic for every
+ * storage type.  Parallel beam only (RADON_ERR_UNSUPPORTED for the fan beam, and for
+ * D > 4096).  Builds its FP32 filter table on first use (RADON_ERR_NOT_PREPARED if
+ * that first use is under stream capture). */
+int radon_filter_sinogram(const radon_geometry_t *geometry, const void *y, void *out,
+                          int32_t batch, int32_t filter, int32_t dtype, void *stream);
+
 /* FP64 inner product sum_i a[i]*b[i] over n elements of `dtype` (device pointers),
  * written to out (device, one double).  Used for the adjoint (dot-product) test and
  * for losses; deterministic (fixed reduction tree). */

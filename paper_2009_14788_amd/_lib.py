@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(_HERE, "libradon.so")
 RADON_PARALLEL = 0
 RADON_FANBEAM = 1
 RADON_F32, RADON_F16, RADON_BF16 = 0, 1, 2
+FILTERS = {"ram-lak": 0, "shepp-logan": 1, "cosine": 2, "hamming": 3, "hann": 4}
 
 STATUS = {
     0: "RADON_OK", -1: "RADON_ERR_INVALID_ARG", -2: "RADON_ERR_ALIGN",
@@ -70,6 +71,7 @@ def _load():
         "radon_backproject": ([G, vp, vp, i32, i32, f32, vp], ctypes.c_int),
         "radon_forward_batched": ([ctypes.POINTER(Job), i32, i32, vp], ctypes.c_int),
         "radon_backproject_batched": ([ctypes.POINTER(Job), i32, i32, vp], ctypes.c_int),
+        "radon_filter_sinogram": ([G, vp, vp, i32, i32, i32, vp], ctypes.c_int),
         "radon_dot_f64": ([vp, vp, ctypes.c_int64, i32, vp, vp], ctypes.c_int),
         "radon_release_plans": ([], ctypes.c_int),
         "radon_plan_info": ([G, i32, i32, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),

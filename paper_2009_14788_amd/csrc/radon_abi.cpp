@@ -8,7 +8,9 @@
 #include <cstring>
 #include <algorithm>
 #include <deque>
+#include <map>
 #include <memory>
+#include <tuple>
 #include <string>
 #include <mutex>
 #include <new>
@@ -18,6 +20,7 @@
 #include "../../include/radon.h"
 #include "radon_autotune.hpp"
 #include "radon_batched.hpp"
+#include "radon_filter.hpp"
 #include "radon_launch.hpp"
 #include "radon_plan.hpp"
 
@@ -332,6 +335,47 @@ static int dot_scratch(hipStream_t stream, double **out) {
     return RADON_OK;
 }
 
+// ---------------------------------------------------------------- FBP filter tables
+// Frequency response and twiddles of one (device, padded length, filter), built once.
+struct FilterTable {
+    float *H = nullptr;
+    float2 *tw = nullptr;
+    ~FilterTable() {
+        if (H) (void)hipFree(H);
+        if (tw) (void)hipFree(tw);
+    }
+};
+static std::map<std::tuple<int, int, int>, std::unique_ptr<FilterTable>> g_filters;
+
+static int filter_table(hipStream_t stream, int log2L, int filter, FilterTable **out) {
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return RADON_ERR_NO_DEVICE;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    auto key = std::make_tuple(device, log2L, filter);
+    auto it = g_filters.find(key);
+    if (it != g_filters.end()) {
+        *out = it->second.get();
+        return RADON_OK;
+    }
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cap) != hipSuccess) return RADON_ERR_HIP;
+    if (cap != hipStreamCaptureStatusNone) return RADON_ERR_NOT_PREPARED;
+    std::vector<float> H;
+    std::vector<float2> tw;
+    filter_response(filter, log2L, H);
+    filter_twiddles(log2L, tw);
+    std::unique_ptr<FilterTable> t(new (std::nothrow) FilterTable());
+    if (!t) return RADON_ERR_ALLOC;
+    if (hipMalloc(&t->H, H.size() * sizeof(float)) != hipSuccess) return RADON_ERR_ALLOC;
+    if (hipMalloc(&t->tw, tw.size() * sizeof(float2)) != hipSuccess) return RADON_ERR_ALLOC;
+    if (hipMemcpy(t->H, H.data(), H.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(t->tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess)
+        return RADON_ERR_HIP;
+    *out = t.get();
+    g_filters.emplace(key, std::move(t));
+    return RADON_OK;
+}
+
 // ---------------------------------------------------------------- uneven batches
 // Device job/work tables of one uneven batch, built once per job list (by content:
 // plans, buffers, batch sizes, scales) and reused, so later calls (and graph
@@ -550,11 +594,13 @@ static int run_batched(const radon_job_t *jobs, int32_t n, int32_t dtype, int di
 
 static int release_all() {
     std::lock_guard<std::mutex> lock(g_mutex);
-    if (!g_plans.empty() || !g_scratch.empty() || !g_batches.empty() || !g_workspaces.empty())
+    if (!g_plans.empty() || !g_scratch.empty() || !g_batches.empty() || !g_workspaces.empty() ||
+        !g_filters.empty())
         (void)hipDeviceSynchronize();
     g_batches.clear();
     g_batch_order.clear();
     g_plans.clear();
+    g_filters.clear();
     for (auto &kv : g_workspaces) {
         if (kv.second.ptr) (void)hipFree(kv.second.ptr);
         for (void *r : kv.second.retired) (void)hipFree(r);
@@ -691,6 +737,28 @@ int radon_forward_batched(const radon_job_t *jobs, int32_t n_jobs, int32_t dtype
 int radon_backproject_batched(const radon_job_t *jobs, int32_t n_jobs, int32_t dtype,
                               void *stream) {
     return run_batched(jobs, n_jobs, dtype, 1, stream);
+}
+
+int radon_filter_sinogram(const radon_geometry_t *geometry, const void *y, void *out,
+                          int32_t batch, int32_t filter, int32_t dtype, void *stream) {
+    int rc = validate(geometry);
+    if (rc != RADON_OK) return rc;
+    if ((rc = check_dtype(dtype)) != RADON_OK) return rc;
+    if (filter < FILTER_RAMLAK || filter > FILTER_HANN || batch < 0) return RADON_ERR_INVALID_ARG;
+    if (geometry->beam != RADON_PARALLEL) return RADON_ERR_UNSUPPORTED;
+    const int log2L = filter_log2_length(geometry->det_count);
+    if (log2L > kFilterMaxLog2) return RADON_ERR_UNSUPPORTED;
+    if (batch == 0) return RADON_OK;
+    if ((rc = check_ptr(y)) != RADON_OK || (rc = check_ptr(out)) != RADON_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    FilterTable *t = nullptr;
+    if ((rc = filter_table(s, log2L, filter, &t)) != RADON_OK) return rc;
+    const double pi = 3.14159265358979323846;
+    const float scale = (float)(pi / ((double)geometry->n_angles * geometry->det_spacing));
+    const long long rows = (long long)batch * geometry->n_angles;
+    hipError_t e = launch_filter(dtype, y, out, rows, geometry->det_count, log2L, t->H, t->tw,
+                                 scale, s);
+    return e == hipSuccess ? RADON_OK : RADON_ERR_HIP;
 }
 
 int radon_dot_f64(const void *a, const void *b, int64_t n, int32_t dtype, double *out,

@@ -114,6 +114,40 @@ class _Base:
     # the paper's ADMM example calls the backprojection `backward` (Sec. 4.3)
     backward = backprojection
 
+    def filter_sinogram_raw(self, y: torch.Tensor, filter_name: str = "ram-lak") -> torch.Tensor:
+        """The FBP filter without autograd (see filter_sinogram)."""
+        _check_tensor(y, "input")
+        if self.beam != _lib.RADON_PARALLEL:
+            raise NotImplementedError("filter_sinogram: parallel beam only")
+        if tuple(y.shape[-2:]) != tuple(self.sinogram_shape):
+            raise ValueError(f"expected trailing shape {tuple(self.sinogram_shape)}, got {tuple(y.shape)}")
+        if filter_name not in _lib.FILTERS:
+            raise ValueError(f"unknown filter {filter_name!r}; one of {tuple(_lib.FILTERS)}")
+        lead = y.shape[:-2]
+        batch = int(np.prod(lead)) if len(lead) else 1
+        src = y.contiguous()
+        if src.data_ptr() % 16:
+            src = src.clone()
+        out = torch.empty_like(src)
+        if batch == 0:
+            return out
+        with torch.cuda.device(y.device):
+            rc = _lib.lib.radon_filter_sinogram(ctypes.byref(self._geom), src.data_ptr(), out.data_ptr(),
+                                                batch, _lib.FILTERS[filter_name], dtype_code(y.dtype),
+                                                _stream_ptr(y.device))
+        _lib.check("radon_filter_sinogram", rc)
+        return out
+
+    def filter_sinogram(self, y: torch.Tensor, filter_name: str = "ram-lak") -> torch.Tensor:
+        """Filter of filtered backprojection (TorchRadon Sec. 3.1.3): each projection is
+        filtered in the frequency domain by the Kak & Slaney band-limited ramp (ch. 3
+        eq. 61) times the window of `filter_name` ("ram-lak", "shepp-logan", "cosine",
+        "hamming", "hann") and scaled by pi / (A * det_spacing), so that
+        ``backprojection(filter_sinogram(y))`` reconstructs the image when the angles
+        cover [0, pi) uniformly.  Parallel beam.  Differentiable: the filter is
+        symmetric, so its gradient is the same filter."""
+        return RadonFilter.apply(y, self, filter_name)
+
     def prepare(self, dtype=torch.float32, batch: int = 1, device=None) -> None:
         """Build the plan (tables, launch shapes) before stream capture."""
         dev = torch.device("cuda") if device is None else torch.device(device)
@@ -191,6 +225,21 @@ class RadonBackprojection(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         return ctx.op.forward_raw(g.contiguous(), ctx.scale), None, None
+
+
+class RadonFilter(torch.autograd.Function):
+    """FBP filter; its matrix is symmetric (the kernel is even), so backward filters
+    the gradient with the same kernel."""
+
+    @staticmethod
+    def forward(ctx, y, op, name):
+        ctx.op = op
+        ctx.name = name
+        return op.filter_sinogram_raw(y, name)
+
+    @staticmethod
+    def backward(ctx, g):
+        return ctx.op.filter_sinogram_raw(g.contiguous(), ctx.name), None, None
 
 
 def dot_f64(a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:

@@ -84,9 +84,43 @@ void *dev_alloc(size_t bytes) {
 
 }  // namespace
 
+// "filter" mode: for every geometry, radon_filter_sinogram with each of the five
+// filters on the geometry's random sinograms; writes, per geometry, the input and the
+// five outputs (as FP64) to the file named by argv[3].
+static int filter_mode(std::vector<Geo> &geos, const char *path) {
+    FILE *out = std::fopen(path, "wb");
+    if (!out) return 2;
+    int fails = 0;
+    for (size_t k = 0; k < geos.size(); ++k) {
+        Geo &g = geos[k];
+        const size_t es = esize(g.dt);
+        void *yin = dev_alloc(g.ny * es), *yo = dev_alloc(g.ny * es);
+        std::memcpy(yin, g.y.data(), g.ny * es);
+        std::vector<double> buf(g.ny);
+        for (size_t i = 0; i < g.ny; ++i) buf[i] = to_double(g.y.data(), i, g.dt);
+        std::fwrite(buf.data(), sizeof(double), g.ny, out);
+        for (int f = 0; f < 5; ++f) {
+            std::fprintf(stderr, "[emu] filter %d geometry %zu\n", f, k);
+            const int rc = radon_filter_sinogram(&g.g, yin, yo, g.batch, f, g.dt, nullptr);
+            if (rc) {
+                std::printf("geometry %zu filter %d status %d\n", k, f, rc);
+                ++fails;
+            }
+            for (size_t i = 0; i < g.ny; ++i) buf[i] = rc ? 0.0 : to_double(yo, i, g.dt);
+            std::fwrite(buf.data(), sizeof(double), g.ny, out);
+        }
+        std::free(yin);
+        std::free(yo);
+    }
+    std::fclose(out);
+    std::printf("summary geometries %zu failures %d\n", geos.size(), fails);
+    return fails ? 1 : 0;
+}
+
 int main(int argc, char **argv) {
     if (argc < 2) return 2;
     const bool batched = argc > 2 && std::strcmp(argv[2], "batched") == 0;
+    const bool filtering = argc > 3 && std::strcmp(argv[2], "filter") == 0;
     FILE *f = std::fopen(argv[1], "r");
     if (!f) return 2;
     std::vector<Geo> geos;
@@ -106,6 +140,14 @@ int main(int argc, char **argv) {
     int fails = 0;
     for (size_t k = 0; k < geos.size(); ++k) {
         Geo &g = geos[k];
+        if (filtering) {
+            g.g = radon_geometry_t{g.beam, g.n, g.A, g.D, g.angles.data(), g.sp, g.S, g.E, g.step};
+            g.nx = (size_t)g.batch * g.n * g.n;
+            g.ny = (size_t)g.batch * g.A * g.D;
+            g.y.resize(g.ny * esize(g.dt));
+            for (size_t i = 0; i < g.ny; ++i) from_float(g.y.data(), i, normal(rng), g.dt);
+            continue;
+        }
         g.g = radon_geometry_t{g.beam, g.n, g.A, g.D, g.angles.data(), g.sp, g.S, g.E, g.step};
         g.nx = (size_t)g.batch * g.n * g.n;
         g.ny = (size_t)g.batch * g.A * g.D;
@@ -158,6 +200,7 @@ int main(int argc, char **argv) {
         std::free(fd);
         std::free(bd);
     }
+    if (filtering) return filter_mode(geos, argv[3]);
     if (batched) {
         std::vector<radon_job_t> jf, jb;
         std::vector<void *> of, ob, ins;

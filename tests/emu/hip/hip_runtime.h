@@ -34,6 +34,13 @@ struct uint4 { unsigned x, y, z, w; };
 struct int2 { int x, y; };
 struct double2 { double x, y; };
 struct double4 { double x, y, z, w; };
+struct float2 { float x, y; };
+inline float2 make_float2(float a, float b) { return {a, b}; }
+inline unsigned __brev(unsigned v) {
+    unsigned r = 0;
+    for (int i = 0; i < 32; ++i) r |= ((v >> i) & 1u) << (31 - i);
+    return r;
+}
 inline uint4 make_uint4(unsigned a, unsigned b, unsigned c, unsigned d) { return {a, b, c, d}; }
 inline int2 make_int2(int a, int b) { return {a, b}; }
 inline double2 make_double2(double a, double b) { return {a, b}; }

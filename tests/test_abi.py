@@ -113,3 +113,21 @@ def test_python_facade_defaults():
     assert f.det_distance == 512 and f.det_count == 512 and f.det_spacing == 2.0
     with pytest.raises(_lib.RadonError):
         Radon(16, [0.0], det_spacing=-1.0)
+
+
+def test_filter_argument_errors_before_device_use():
+    """radon_filter_sinogram validates everything before touching the device."""
+    g = _geom()
+    flt = _lib.lib.radon_filter_sinogram
+    assert flt(ctypes.byref(g), None, None, 0, 0, 0, None) == 0          # batch 0: no-op
+    assert flt(ctypes.byref(g), 0x1000, 0x2000, 1, 5, 0, None) == -1     # unknown filter
+    assert flt(ctypes.byref(g), 0x1000, 0x2000, 1, -1, 0, None) == -1
+    assert flt(ctypes.byref(g), 0x1000, 0x2000, 1, 0, 9, None) == -1     # bad dtype
+    assert flt(ctypes.byref(g), 0x1000, 0x2000, -1, 0, 0, None) == -1    # negative batch
+    assert flt(ctypes.byref(g), None, 0x2000, 1, 0, 0, None) == -1
+    assert flt(ctypes.byref(g), 0x1008, 0x2000, 1, 0, 0, None) == -2     # misaligned
+    fan = _geom(beam=1, S=40.0, E=20.0)
+    assert flt(ctypes.byref(fan), 0x1000, 0x2000, 1, 0, 0, None) == -3   # parallel beam only
+    wide = _geom(D=4097)
+    assert flt(ctypes.byref(wide), 0x1000, 0x2000, 1, 0, 0, None) == -3  # padded length > 8192
+    assert _lib.FILTERS == {"ram-lak": 0, "shepp-logan": 1, "cosine": 2, "hamming": 3, "hann": 4}

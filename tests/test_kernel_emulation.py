@@ -36,7 +36,7 @@ def emu_bin(tmp_path_factory):
         text = open(os.path.join(CSRC, name)).read()
         text = text.replace('"../../include/radon.h"', '"radon.h"')
         # dynamic LDS becomes the emulated block's buffer
-        text = text.replace("extern __shared__ uint4 lds[];", "uint4 *lds = (uint4 *)emu::dyn_lds();")
+        text = re.sub(r"extern __shared__ (\w+) (\w+)\[\];", r"\1 *\2 = (\1 *)emu::dyn_lds();", text)
         (src / name).write_text(text)
     inc = ["-I" + EMU, "-I" + os.path.join(ROOT, "include"), "-I" + str(src)]
     jobs = [[CLANG, *FLAGS, *inc, "-x", "c++", "-c", str(src / n), "-o", str(d / (n + ".o"))]
@@ -136,3 +136,35 @@ def test_emulated_uneven_batch_groups(emu_bin, tmp_path):
     rows, out = _run(emu_bin, tmp_path, lines, mode="batched")
     _check_bars(rows, lines)
     assert "identical 5 of 5" in out, out
+
+
+def test_emulated_filter_matches_oracle(emu_bin, tmp_path):
+    """The FBP filter kernel (radix-2 transforms in LDS, two rows per block) against
+    the FP64 oracle filter for all five filters: odd row counts, several padded
+    lengths, 16-bit storage."""
+    from oracle import filtering
+    U = inputs.uniform_angles
+    specs = [("par", 16, U(7), 23, 1.0, 3, 0), ("par", 24, U(6), 91, 0.5, 1, 0),
+             ("par", 20, U(5), 33, 1.0, 2, 1), ("par", 20, U(5), 40, 1.5, 1, 2)]
+    lines = [_line(b, n, a, D, sp, batch=B, dt=dt) for b, n, a, D, sp, B, dt in specs]
+    geo = tmp_path / "geos.txt"
+    geo.write_text("\n".join(lines) + "\n")
+    dump = tmp_path / "filter.bin"
+    r = subprocess.run([str(emu_bin), str(geo), "filter", str(dump)], capture_output=True, text=True,
+                       env=dict(os.environ, ASAN_OPTIONS="detect_leaks=0"), timeout=900)
+    assert "ERROR: AddressSanitizer" not in r.stderr, r.stderr[-6000:]
+    assert r.returncode == 0, r.stdout[-3000:] + r.stderr[-3000:]
+    data = np.fromfile(dump, dtype=np.float64)
+    pos = 0
+    for _, n, a, D, sp, B, dt in specs:
+        A = len(a)
+        size = B * A * D
+        y = data[pos:pos + size].reshape(B, A, D)
+        pos += size
+        for name in filtering.FILTERS:
+            got = data[pos:pos + size].reshape(B, A, D)
+            pos += size
+            ref = filtering.filter_sinogram(y, name, sp)
+            err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+            assert err <= (TOL_F32 if dt == 0 else TOL_16), (n, D, dt, name, err)
+    assert pos == data.size
