@@ -289,7 +289,8 @@ def variants(op, x, x_np, B, A, D):
     image (latency, eager and graph-replayed); the 16 x 256^2 batch; 200 uneven jobs
     in one persistent launch (eager, graph, and one call per job); the 64 x 512^2
     fan beam with 16-bit storage and a 10-step unrolled gradient descent
-    differentiated end to end."""
+    differentiated end to end; the FBP filter on the headline sinograms and FBP in
+    the paper's 512^2 configuration."""
     import math
     import torch
     import oracle
@@ -333,6 +334,34 @@ def variants(op, x, x_np, B, A, D):
         "note": "forward + loss + backward (transpose kernel) + FP64 loss reduction"}
     print(f"[bench] autograd loss step: {ms:.3f} ms", file=sys.stderr, flush=True)
     del ymeas, xg, y32
+
+    # -- FBP (Sec. 3.1.3): the filter on the headline sinograms, and the paper's FBP
+    #    configuration (512^2, 512 angles over [0, pi), ceil(512 sqrt 2) bins, Ram-Lak)
+    y128 = op.forward_raw(x)
+    ms_f = _timed(lambda: op.filter_sinogram_raw(y128, "ram-lak"))
+    rows = B * A
+    L = 1 << max(6, (2 * D - 1).bit_length())
+    res["fbp_filter_batch128_512"] = {
+        "ms_per_call": round(ms_f, 4), "projections_per_s": round(rows / (ms_f * 1e-3), 1),
+        "padded_length": L,
+        "note": "ram-lak filter of 128 x 720 rows of 724 bins (two rows per complex transform)"}
+    print(f"[bench] fbp filter 128x720x724: {ms_f:.3f} ms", file=sys.stderr, flush=True)
+    del y128
+    Dp = int(math.ceil(math.sqrt(2) * 512))
+    opf = Radon(512, inputs.uniform_angles(512), Dp)
+    xf_np = inputs.phantom(512, 10, [12, 0])[0][None]
+    xf = torch.from_numpy(xf_np).cuda()
+    yf = opf.forward_raw(xf)
+    ms_fbp = _timed(lambda: opf.backprojection_raw(opf.filter_sinogram_raw(yf, "ram-lak")), reps=20)
+    rec = opf.backprojection_raw(opf.filter_sinogram_raw(yf, "ram-lak"))[0].double().cpu().numpy()
+    rr = np.hypot(*(np.mgrid[0:512, 0:512] - 255.5))
+    inside = rr < 248
+    res["fbp_paper_512"] = {
+        "ms_per_fbp": round(ms_fbp, 4),
+        "mse_vs_phantom_inside": float(np.mean((rec[inside] - xf_np[0][inside]) ** 2)),
+        "note": "filter + backprojection of one 512^2 sinogram (512 angles, 725 bins); random "
+                "ellipses stand in for the paper's Shepp-Logan phantom (its MSE 2.22e-4 is on that)"}
+    print(f"[bench] fbp 512^2 paper configuration: {ms_fbp:.3f} ms", file=sys.stderr, flush=True)
 
     # -- single 64x64 image (latency)
     w0 = inputs.WORKLOADS["single64"]
