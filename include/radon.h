@@ -146,6 +146,62 @@ int radon_filter_sinogram(const radon_geometry_t *geometry, const void *y, void 
 int radon_dot_f64(const void *a, const void *b, int64_t n, int32_t dtype, double *out,
                   void *stream);
 
+/* ---------------------------------------------------------------- solvers
+ * Iterative reconstruction with the projector pair (TorchRadon Sec. 4.2: Landweber
+ * iteration and conjugate gradient on the normal equations; Sec. 4.3: conjugate
+ * gradient for a symmetric positive definite operator).  A batch holds independent
+ * systems stored one after another; every system has its own step sizes.  Scalars stay
+ * in device memory, so a solve is queued on the stream without waiting on the host. */
+
+/* Per-system FP64 inner products: out[k] = sum_{i<n} a[k n + i] * b[k n + i] for
+ * k < batch (a, b: device, `dtype`, 16-byte aligned; out: device, batch doubles).
+ * Deterministic (fixed reduction tree).  batch <= 65535, else RADON_ERR_INVALID_ARG;
+ * n == 0 writes zeros.  Uses a library-owned partials buffer (grown outside stream
+ * capture; RADON_ERR_NOT_PREPARED if it must grow under capture). */
+int radon_dot_f64_batched(const void *a, const void *b, int64_t n, int32_t batch, int32_t dtype,
+                          double *out, void *stream);
+
+/* Per-system scaled update out[k n + i] = u[k n + i] + c_k v[k n + i] with
+ * c_k = c0 * num[k] / den[k] evaluated in FP64 (num or den NULL reads as 1; c_k = 0
+ * where den[k] == 0, which freezes a system whose search direction has vanished).
+ * The element arithmetic is FP64, rounded once to FP32 and then to `dtype`.  Where
+ * c_k == 0 the output is u exactly and v is not read.  out may equal u or v.
+ * u, v, out: device, `dtype`, 16-byte aligned; num, den: device doubles (8-byte
+ * aligned) or NULL.  batch <= 65535. */
+int radon_axpy_ratio(const void *u, const void *v, void *out, const double *num,
+                     const double *den, double c0, int64_t n, int32_t batch, int32_t dtype,
+                     void *stream);
+
+enum { RADON_SOLVER_LANDWEBER = 0, RADON_SOLVER_CGNE = 1 };
+
+/* Bytes of workspace radon_landweber (RADON_SOLVER_LANDWEBER) or radon_cgne
+ * (RADON_SOLVER_CGNE) needs for `batch` systems of this geometry and dtype; negative
+ * status on a bad argument. */
+int64_t radon_solver_workspace_bytes(const radon_geometry_t *geometry, int32_t solver,
+                                     int32_t batch, int32_t dtype);
+
+/* Landweber iteration x <- x - alpha R^T (R x - y), `iterations` times, in place on x
+ * [batch][N][N] (device, the initial guess on entry); y [batch][A][D] (device).
+ * alpha is applied inside the backprojection kernel (no unscaled gradient is stored).
+ * workspace: device, 16-byte aligned, at least radon_solver_workspace_bytes(...,
+ * RADON_SOLVER_LANDWEBER, ...) bytes, owned by the caller and not used after the
+ * queued work completes.  Any dtype.  Status codes as radon_forward. */
+int radon_landweber(const radon_geometry_t *geometry, const void *y, void *x, int32_t batch,
+                    double alpha, int32_t iterations, int32_t dtype, void *workspace,
+                    int64_t workspace_bytes, void *stream);
+
+/* Conjugate gradient on the normal equations R^T R x = R^T y (CGNE, TorchRadon
+ * Sec. 4.2), `iterations` steps from the guess in x, in place, every batch entry its
+ * own system: r = y - R x, s = R^T r, p = s; then per step q = R p,
+ * a = <s,s>/<q,q>, x += a p, r -= a q, s' = R^T r, p = s' + (<s',s'>/<s,s>) p.  Inner
+ * products in FP64 (radon_dot_f64_batched), updates by radon_axpy_ratio, so a system
+ * whose normal-equation residual reaches exactly zero stays where it is.  FP32 only
+ * (RADON_ERR_UNSUPPORTED otherwise: R^T r is stored unscaled).  workspace as for
+ * radon_landweber with RADON_SOLVER_CGNE.  Status codes as radon_forward. */
+int radon_cgne(const radon_geometry_t *geometry, const void *y, void *x, int32_t batch,
+               int32_t iterations, int32_t dtype, void *workspace, int64_t workspace_bytes,
+               void *stream);
+
 /* Free every plan and queue the library holds (synchronises the device). */
 int radon_release_plans(void);
 

@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(_HERE, "libradon.so")
 RADON_PARALLEL = 0
 RADON_FANBEAM = 1
 RADON_F32, RADON_F16, RADON_BF16 = 0, 1, 2
+RADON_SOLVER_LANDWEBER, RADON_SOLVER_CGNE = 0, 1
 FILTERS = {"ram-lak": 0, "shepp-logan": 1, "cosine": 2, "hamming": 3, "hann": 4}
 
 STATUS = {
@@ -73,6 +74,13 @@ def _load():
         "radon_backproject_batched": ([ctypes.POINTER(Job), i32, i32, vp], ctypes.c_int),
         "radon_filter_sinogram": ([G, vp, vp, i32, i32, i32, vp], ctypes.c_int),
         "radon_dot_f64": ([vp, vp, ctypes.c_int64, i32, vp, vp], ctypes.c_int),
+        "radon_dot_f64_batched": ([vp, vp, ctypes.c_int64, i32, i32, vp, vp], ctypes.c_int),
+        "radon_axpy_ratio": ([vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_int64, i32, i32, vp],
+                             ctypes.c_int),
+        "radon_solver_workspace_bytes": ([G, i32, i32, i32], ctypes.c_int64),
+        "radon_landweber": ([G, vp, vp, i32, ctypes.c_double, i32, i32, vp, ctypes.c_int64, vp],
+                            ctypes.c_int),
+        "radon_cgne": ([G, vp, vp, i32, i32, i32, vp, ctypes.c_int64, vp], ctypes.c_int),
         "radon_release_plans": ([], ctypes.c_int),
         "radon_plan_info": ([G, i32, i32, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
         "radon_status_string": ([ctypes.c_int], ctypes.c_char_p),

@@ -112,7 +112,12 @@ Plan::~Plan() {
 
 static std::mutex g_mutex;
 static std::unordered_map<PlanKey, std::unique_ptr<Plan>, PlanKeyHash> g_plans;
-struct DeviceScratch { double *dot_partials = nullptr; };
+struct DeviceScratch {
+    double *dot_partials = nullptr;
+    double *row_partials = nullptr;   // per-system partials of radon_dot_f64_batched
+    size_t row_count = 0;
+    std::vector<void *> retired;      // replaced partial buffers a graph may still use
+};
 static std::unordered_map<int, DeviceScratch> g_scratch;
 constexpr int kDotPartials = 1024;
 
@@ -332,6 +337,25 @@ static int dot_scratch(hipStream_t stream, double **out) {
             return RADON_ERR_ALLOC;
     }
     *out = s.dot_partials;
+    return RADON_OK;
+}
+
+static int row_scratch(hipStream_t stream, size_t count, double **out) {
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return RADON_ERR_NO_DEVICE;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    DeviceScratch &s = g_scratch[device];
+    if (s.row_count < count) {
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(stream, &cap) != hipSuccess) return RADON_ERR_HIP;
+        if (cap != hipStreamCaptureStatusNone) return RADON_ERR_NOT_PREPARED;
+        double *p = nullptr;
+        if (hipMalloc(&p, count * sizeof(double)) != hipSuccess) return RADON_ERR_ALLOC;
+        if (s.row_partials) s.retired.push_back(s.row_partials);
+        s.row_partials = p;
+        s.row_count = count;
+    }
+    *out = s.row_partials;
     return RADON_OK;
 }
 
@@ -606,8 +630,11 @@ static int release_all() {
         for (void *r : kv.second.retired) (void)hipFree(r);
     }
     g_workspaces.clear();
-    for (auto &kv : g_scratch)
+    for (auto &kv : g_scratch) {
         if (kv.second.dot_partials) (void)hipFree(kv.second.dot_partials);
+        if (kv.second.row_partials) (void)hipFree(kv.second.row_partials);
+        for (void *r : kv.second.retired) (void)hipFree(r);
+    }
     g_scratch.clear();
     return RADON_OK;
 }
@@ -772,6 +799,39 @@ int radon_dot_f64(const void *a, const void *b, int64_t n, int32_t dtype, double
     double *partials = nullptr;
     if ((rc = dot_scratch(s, &partials)) != RADON_OK) return rc;
     hipError_t e = launch_dot_f64(a, b, (long long)n, dtype, out, partials, kDotPartials, s);
+    return e == hipSuccess ? RADON_OK : RADON_ERR_HIP;
+}
+
+int radon_dot_f64_batched(const void *a, const void *b, int64_t n, int32_t batch, int32_t dtype,
+                          double *out, void *stream) {
+    int rc = check_dtype(dtype);
+    if (rc != RADON_OK) return rc;
+    if (n < 0 || batch < 0 || batch > 65535 || !out) return RADON_ERR_INVALID_ARG;
+    if (batch == 0) return RADON_OK;
+    if (reinterpret_cast<uintptr_t>(out) % alignof(double)) return RADON_ERR_ALIGN;
+    if (n > 0 && ((rc = check_ptr(a)) != RADON_OK || (rc = check_ptr(b)) != RADON_OK)) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double *partials = nullptr;
+    if ((rc = row_scratch(s, (size_t)batch * dot_rows_chunks(n), &partials)) != RADON_OK) return rc;
+    hipError_t e = launch_dot_rows(a, b, (long long)n, batch, dtype, out, partials, s);
+    return e == hipSuccess ? RADON_OK : RADON_ERR_HIP;
+}
+
+int radon_axpy_ratio(const void *u, const void *v, void *out, const double *num,
+                     const double *den, double c0, int64_t n, int32_t batch, int32_t dtype,
+                     void *stream) {
+    int rc = check_dtype(dtype);
+    if (rc != RADON_OK) return rc;
+    if (n < 0 || batch < 0 || batch > 65535 || !std::isfinite(c0)) return RADON_ERR_INVALID_ARG;
+    if (n == 0 || batch == 0) return RADON_OK;
+    if ((rc = check_ptr(u)) != RADON_OK || (rc = check_ptr(v)) != RADON_OK ||
+        (rc = check_ptr(out)) != RADON_OK)
+        return rc;
+    if (reinterpret_cast<uintptr_t>(num) % alignof(double) ||
+        reinterpret_cast<uintptr_t>(den) % alignof(double))
+        return RADON_ERR_ALIGN;
+    hipError_t e = launch_axpy_ratio(u, v, out, num, den, c0, (long long)n, batch, dtype,
+                                     static_cast<hipStream_t>(stream));
     return e == hipSuccess ? RADON_OK : RADON_ERR_HIP;
 }
 

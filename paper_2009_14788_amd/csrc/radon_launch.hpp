@@ -105,4 +105,16 @@ size_t interleaved_sino_bytes(int n_angles, int det_count, int window, int batch
 hipError_t launch_dot_f64(const void *a, const void *b, long long n, int dtype, double *out,
                           double *partials, int n_partials, hipStream_t s);
 
+// Per-system FP64 inner products of `batch` systems of n elements: out[b] = <a_b, b_b>.
+// partials holds batch * dot_rows_chunks(n) doubles.  batch <= 65535.
+constexpr int kDotRowChunks = 64;
+int dot_rows_chunks(long long n);
+hipError_t launch_dot_rows(const void *a, const void *b, long long n, int batch, int dtype,
+                           double *out, double *partials, hipStream_t s);
+// out_b = u_b + c_b v_b with c_b = c0 * num[b] / den[b] in FP64 (null arrays read as 1,
+// c_b = 0 where den[b] == 0, and then out_b = u_b without reading v).  batch <= 65535.
+hipError_t launch_axpy_ratio(const void *u, const void *v, void *out, const double *num,
+                             const double *den, double c0, long long n, int batch, int dtype,
+                             hipStream_t s);
+
 }  // namespace radon

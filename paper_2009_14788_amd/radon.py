@@ -261,5 +261,60 @@ def dot_f64(a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
     return out
 
 
+def _aligned(t: torch.Tensor) -> torch.Tensor:
+    t = t.contiguous()
+    return t.clone() if t.data_ptr() % 16 else t
+
+
+def dot_f64_batched(a: torch.Tensor, b: torch.Tensor, systems: int) -> torch.Tensor:
+    """Per-system FP64 inner products: the tensors are `systems` equal parts stored one
+    after another; returns a float64 tensor [systems] on a's device (deterministic)."""
+    _check_tensor(a, "a")
+    _check_tensor(b, "b")
+    if a.shape != b.shape or a.dtype != b.dtype:
+        raise ValueError("a and b must have the same shape and dtype")
+    systems = int(systems)
+    if systems < 1 or a.numel() % systems:
+        raise ValueError(f"{a.numel()} elements do not split into {systems} systems")
+    a, b = _aligned(a), _aligned(b)
+    out = torch.empty(systems, dtype=torch.float64, device=a.device)
+    with torch.cuda.device(a.device):
+        rc = _lib.lib.radon_dot_f64_batched(a.data_ptr(), b.data_ptr(), a.numel() // systems,
+                                            systems, dtype_code(a.dtype), out.data_ptr(),
+                                            _stream_ptr(a.device))
+    _lib.check("radon_dot_f64_batched", rc)
+    return out
+
+
+def axpy_ratio_(out: torch.Tensor, u: torch.Tensor, v: torch.Tensor, num=None, den=None,
+                c0: float = 1.0, systems: int = 1) -> torch.Tensor:
+    """In place: out_k = u_k + c_k v_k for each of `systems` equal parts, with
+    c_k = c0 * num[k] / den[k] (float64 device tensors or None; c_k = 0 where
+    den[k] == 0).  out may be u or v; all three contiguous, same shape and dtype."""
+    for t, w in ((out, "out"), (u, "u"), (v, "v")):
+        _check_tensor(t, w)
+        if t.shape != out.shape or t.dtype != out.dtype:
+            raise ValueError("out, u and v must have the same shape and dtype")
+        if not t.is_contiguous() or t.data_ptr() % 16:
+            raise ValueError(f"{w} must be contiguous and 16-byte aligned")
+    systems = int(systems)
+    if systems < 1 or out.numel() % systems:
+        raise ValueError(f"{out.numel()} elements do not split into {systems} systems")
+    ptrs = []
+    for c in (num, den):
+        if c is None:
+            ptrs.append(None)
+            continue
+        if c.dtype != torch.float64 or c.numel() != systems or c.device != out.device:
+            raise ValueError("num and den must be float64 tensors with one entry per system")
+        ptrs.append(c.contiguous().data_ptr())
+    with torch.cuda.device(out.device):
+        rc = _lib.lib.radon_axpy_ratio(u.data_ptr(), v.data_ptr(), out.data_ptr(), ptrs[0], ptrs[1],
+                                       float(c0), out.numel() // systems, systems,
+                                       dtype_code(out.dtype), _stream_ptr(out.device))
+    _lib.check("radon_axpy_ratio", rc)
+    return out
+
+
 def release_plans() -> None:
     _lib.check("radon_release_plans", _lib.lib.radon_release_plans())

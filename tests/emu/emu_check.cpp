@@ -7,10 +7,12 @@
 //
 // Line format: beam n D spacing S E step batch dtype A angle_0 ... angle_{A-1}
 // Output: one "geometry ..." line per geometry, then "batched ..." and "summary ...".
+// The "filter" and "solver" modes write their results to a file instead.
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <random>
 #include <vector>
 
@@ -117,10 +119,64 @@ static int filter_mode(std::vector<Geo> &geos, const char *path) {
     return fails ? 1 : 0;
 }
 
+// "solver" mode: for every geometry, `iters` steps of radon_landweber (step alpha) and
+// of radon_cgne from the geometry's random image x towards its random sinogram y, and
+// the per-system inner products <x, x>; writes, per geometry, x, y, the Landweber
+// result, the CGNE result (FP64) and the batch inner products to argv[3].
+static int solver_mode(std::vector<Geo> &geos, const char *path, double alpha, int iters) {
+    FILE *out = std::fopen(path, "wb");
+    if (!out) return 2;
+    int fails = 0;
+    for (size_t k = 0; k < geos.size(); ++k) {
+        Geo &g = geos[k];
+        const size_t es = esize(g.dt);
+        void *x = dev_alloc(g.nx * es), *y = dev_alloc(g.ny * es), *dots = dev_alloc(g.batch * 8);
+        std::vector<double> buf(std::max(g.nx, g.ny));
+        auto dump = [&](const void *p, size_t n) {
+            for (size_t i = 0; i < n; ++i) buf[i] = to_double(p, i, g.dt);
+            std::fwrite(buf.data(), sizeof(double), n, out);
+        };
+        dump(g.x.data(), g.nx);
+        dump(g.y.data(), g.ny);
+        std::memcpy(y, g.y.data(), g.ny * es);
+        int rc = 0;
+        for (int solver = 0; solver < 2; ++solver) {
+            std::fprintf(stderr, "[emu] solver %d geometry %zu\n", solver, k);
+            std::memcpy(x, g.x.data(), g.nx * es);
+            const int64_t bytes = radon_solver_workspace_bytes(&g.g, solver, g.batch, g.dt);
+            void *ws = bytes > 0 ? dev_alloc((size_t)bytes) : nullptr;
+            rc = bytes < 0 ? (int)bytes
+                 : solver == RADON_SOLVER_LANDWEBER
+                     ? radon_landweber(&g.g, y, x, g.batch, alpha, iters, g.dt, ws, bytes, nullptr)
+                     : radon_cgne(&g.g, y, x, g.batch, iters, g.dt, ws, bytes, nullptr);
+            std::free(ws);
+            if (rc) {
+                std::printf("geometry %zu solver %d status %d\n", k, solver, rc);
+                ++fails;
+            }
+            dump(x, g.nx);
+        }
+        std::memcpy(x, g.x.data(), g.nx * es);
+        rc = radon_dot_f64_batched(x, x, (int64_t)g.n * g.n, g.batch, g.dt, (double *)dots, nullptr);
+        if (rc) {
+            std::printf("geometry %zu dot status %d\n", k, rc);
+            ++fails;
+        }
+        std::fwrite(dots, sizeof(double), g.batch, out);
+        std::free(x);
+        std::free(y);
+        std::free(dots);
+    }
+    std::fclose(out);
+    std::printf("summary geometries %zu failures %d\n", geos.size(), fails);
+    return fails ? 1 : 0;
+}
+
 int main(int argc, char **argv) {
     if (argc < 2) return 2;
     const bool batched = argc > 2 && std::strcmp(argv[2], "batched") == 0;
     const bool filtering = argc > 3 && std::strcmp(argv[2], "filter") == 0;
+    const bool solving = argc > 5 && std::strcmp(argv[2], "solver") == 0;
     FILE *f = std::fopen(argv[1], "r");
     if (!f) return 2;
     std::vector<Geo> geos;
@@ -140,6 +196,16 @@ int main(int argc, char **argv) {
     int fails = 0;
     for (size_t k = 0; k < geos.size(); ++k) {
         Geo &g = geos[k];
+        if (solving) {
+            g.g = radon_geometry_t{g.beam, g.n, g.A, g.D, g.angles.data(), g.sp, g.S, g.E, g.step};
+            g.nx = (size_t)g.batch * g.n * g.n;
+            g.ny = (size_t)g.batch * g.A * g.D;
+            g.x.resize(g.nx * esize(g.dt));
+            g.y.resize(g.ny * esize(g.dt));
+            for (size_t i = 0; i < g.nx; ++i) from_float(g.x.data(), i, normal(rng), g.dt);
+            for (size_t i = 0; i < g.ny; ++i) from_float(g.y.data(), i, normal(rng), g.dt);
+            continue;
+        }
         if (filtering) {
             g.g = radon_geometry_t{g.beam, g.n, g.A, g.D, g.angles.data(), g.sp, g.S, g.E, g.step};
             g.nx = (size_t)g.batch * g.n * g.n;
@@ -201,6 +267,12 @@ int main(int argc, char **argv) {
         std::free(bd);
     }
     if (filtering) return filter_mode(geos, argv[3]);
+    if (solving) {
+        char *end = nullptr;
+        const double alpha = std::strtod(argv[4], &end);
+        if (end == argv[4] || *end) return 2;     // the step must be a plain number
+        return solver_mode(geos, argv[3], alpha, std::atoi(argv[5]));
+    }
     if (batched) {
         std::vector<radon_job_t> jf, jb;
         std::vector<void *> of, ob, ins;

@@ -131,3 +131,55 @@ def test_filter_argument_errors_before_device_use():
     wide = _geom(D=4097)
     assert flt(ctypes.byref(wide), 0x1000, 0x2000, 1, 0, 0, None) == -3  # padded length > 8192
     assert _lib.FILTERS == {"ram-lak": 0, "shepp-logan": 1, "cosine": 2, "hamming": 3, "hann": 4}
+
+
+def test_solver_argument_errors_before_device_use():
+    """The solver entry points and their vector steps validate everything first."""
+    g = _geom()
+    L = _lib.lib
+    N, A, D = g.image_size, g.n_angles, g.det_count
+    # workspace sizes: Landweber holds one sinogram and one image per system, CGNE two
+    # of each plus its FP64 scalars and partial sums (256-byte aligned pieces)
+    up = lambda b: (b + 255) // 256 * 256
+    lw = L.radon_solver_workspace_bytes(ctypes.byref(g), 0, 3, 0)
+    assert lw == up(3 * A * D * 4) + up(3 * N * N * 4)
+    cg = L.radon_solver_workspace_bytes(ctypes.byref(g), 1, 3, 0)
+    assert cg == 2 * up(3 * A * D * 4) + 2 * up(3 * N * N * 4) + 3 * 256 + up(3 * 64 * 8)
+    assert L.radon_solver_workspace_bytes(ctypes.byref(g), 1, 3, 1) < cg
+    assert L.radon_solver_workspace_bytes(ctypes.byref(g), 2, 3, 0) == -1     # unknown solver
+    assert L.radon_solver_workspace_bytes(ctypes.byref(g), 0, -1, 0) == -1
+    assert L.radon_solver_workspace_bytes(ctypes.byref(g), 0, 70000, 0) == -1
+    assert L.radon_solver_workspace_bytes(ctypes.byref(_geom(sp=0.0)), 0, 1, 0) == -1
+    ok = 0x1000, 0x2000
+    # zero systems or zero iterations: nothing to do
+    assert L.radon_landweber(ctypes.byref(g), None, None, 0, 0.1, 5, 0, None, 0, None) == 0
+    assert L.radon_cgne(ctypes.byref(g), *ok, 3, 0, 0, 0x3000, 0, None) == 0
+    # bad step, pointers, sizes, dtype
+    assert L.radon_landweber(ctypes.byref(g), *ok, 3, float("nan"), 5, 0, 0x3000, lw, None) == -1
+    assert L.radon_landweber(ctypes.byref(g), *ok, 3, 1e300, 5, 0, 0x3000, lw, None) == -1
+    assert L.radon_landweber(ctypes.byref(g), *ok, 3, 0.1, -1, 0, 0x3000, lw, None) == -1
+    assert L.radon_landweber(ctypes.byref(g), *ok, 3, 0.1, 5, 0, 0x3000, lw - 1, None) == -1
+    assert L.radon_landweber(ctypes.byref(g), *ok, 3, 0.1, 5, 0, None, lw, None) == -1
+    assert L.radon_landweber(ctypes.byref(g), *ok, 3, 0.1, 5, 0, 0x3008, lw, None) == -2
+    assert L.radon_landweber(ctypes.byref(g), *ok, 3, 0.1, 5, 4, 0x3000, lw, None) == -1
+    assert L.radon_cgne(ctypes.byref(g), *ok, 3, 5, 0, 0x3000, cg - 256, None) == -1
+    assert L.radon_cgne(ctypes.byref(g), 0x1004, 0x2000, 3, 5, 0, 0x3000, cg, None) == -2
+    assert L.radon_cgne(ctypes.byref(g), *ok, 3, 5, 1, 0x3000, cg, None) == -3     # FP32 only
+    assert L.radon_cgne(ctypes.byref(g), *ok, 70000, 5, 0, 0x3000, cg, None) == -1
+    # per-system inner products and updates
+    dot = L.radon_dot_f64_batched
+    assert dot(*ok, 10, 0, 0, 0x3000, None) == 0                               # no systems
+    assert dot(*ok, -1, 1, 0, 0x3000, None) == -1
+    assert dot(*ok, 10, 70000, 0, 0x3000, None) == -1
+    assert dot(*ok, 10, 1, 0, None, None) == -1
+    assert dot(*ok, 10, 1, 0, 0x3004, None) == -2
+    assert dot(0x1004, 0x2000, 10, 1, 0, 0x3000, None) == -2
+    assert dot(*ok, 10, 1, 5, 0x3000, None) == -1
+    ax = L.radon_axpy_ratio
+    assert ax(*ok, 0x3000, None, None, 1.0, 0, 4, 0, None) == 0                # empty
+    assert ax(*ok, 0x3000, None, None, float("inf"), 10, 1, 0, None) == -1
+    assert ax(*ok, 0x3000, None, None, 1.0, 10, 70000, 0, None) == -1
+    assert ax(*ok, None, None, None, 1.0, 10, 1, 0, None) == -1
+    assert ax(*ok, 0x3004, None, None, 1.0, 10, 1, 0, None) == -2
+    assert ax(*ok, 0x3000, 0x4004, None, 1.0, 10, 1, 0, None) == -2
+    assert ax(*ok, 0x3000, None, None, 1.0, 10, 1, 3, None) == -1

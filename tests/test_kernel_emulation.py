@@ -168,3 +168,52 @@ def test_emulated_filter_matches_oracle(emu_bin, tmp_path):
             err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
             assert err <= (TOL_F32 if dt == 0 else TOL_16), (n, D, dt, name, err)
     assert pos == data.size
+
+
+def test_emulated_solvers_match_oracle(emu_bin, tmp_path):
+    """The solver loops (radon_landweber, radon_cgne) and the per-system inner products,
+    run through the emulated kernels: a few iterations of each, every batch entry its
+    own system, against the FP64 oracle solvers on the same inputs."""
+    import oracle
+    from oracle import solvers
+    U = inputs.uniform_angles
+    specs = [("par", 24, U(20), 35, 1.0, 0.0, 0.0, 3), ("fan", 20, U(16, 2 * math.pi), 30, 1.5, 100.0, 50.0, 2)]
+    lines = [_line(b, n, a, D, sp, S, E, batch=B) for b, n, a, D, sp, S, E, B in specs]
+    geos = [oracle.Geometry(n, a, D, sp, beam=oracle.FANBEAM if b == "fan" else oracle.PARALLEL,
+                            source_distance=S, det_distance=E) for b, n, a, D, sp, S, E, B in specs]
+    iters = 3
+    # a step below 2 / ||R||^2 (both systems share it; the value only has to agree)
+    alpha = 1.0 / max(np.linalg.norm(oracle.dense_matrix(g), 2) ** 2 for g in geos)
+    geo = tmp_path / "geos.txt"
+    geo.write_text("\n".join(lines) + "\n")
+    dump = tmp_path / "solver.bin"
+    r = subprocess.run([str(emu_bin), str(geo), "solver", str(dump), repr(float(alpha)), str(iters)],
+                       capture_output=True, text=True,
+                       env=dict(os.environ, ASAN_OPTIONS="detect_leaks=0"), timeout=900)
+    assert "ERROR: AddressSanitizer" not in r.stderr, r.stderr[-6000:]
+    assert r.returncode == 0, r.stdout[-3000:] + r.stderr[-3000:]
+    data = np.fromfile(dump, dtype=np.float64)
+    pos = 0
+
+    def take(shape):
+        nonlocal pos
+        size = int(np.prod(shape))
+        out = data[pos:pos + size].reshape(shape)
+        pos += size
+        return out
+
+    for (b, n, a, D, sp, S, E, B), g in zip(specs, geos):
+        x0, y = take((B, n, n)), take((B, len(a), D))
+        lw, cg_ne, dots = take((B, n, n)), take((B, n, n)), take((B,))
+        fwd = lambda v: oracle.forward(g, v)
+        bp = lambda v: oracle.backproject(g, v)
+        ref_lw = solvers.landweber(fwd, bp, y, alpha, iters, x0)[-1]
+        e_lw = np.linalg.norm(lw - ref_lw) / np.linalg.norm(ref_lw)
+        for k in range(B):
+            ref_cg = solvers.cgne(fwd, bp, y[k], x0[k], iters)[-1]
+            e_cg = np.linalg.norm(cg_ne[k] - ref_cg) / np.linalg.norm(ref_cg)
+            assert e_cg <= TOL_F32, (b, k, e_cg)
+        assert e_lw <= TOL_F32, (b, e_lw)
+        ref_dots = np.einsum("kij,kij->k", x0, x0)
+        assert np.allclose(dots, ref_dots, rtol=1e-12, atol=0), (dots, ref_dots)
+    assert pos == data.size
