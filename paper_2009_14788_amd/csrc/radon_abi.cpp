@@ -660,7 +660,13 @@ static void call_shapes(Plan *p, int dtype, int batch, LaunchShape &fwd, LaunchS
     }
     std::lock_guard<std::mutex> lock(g_mutex);
     auto it = p->tuned.find({dtype, batch_class(batch)});
-    if (it == p->tuned.end() || !it->second.valid) return;
+    if (it == p->tuned.end() || !it->second.valid) {
+        // untuned small batches: the narrowest tiled shapes leave the fewest lanes
+        // without an image (one 16-byte chunk forward, 16 images per lane backward)
+        if (fwd.variant == VARIANT_TILED && dtype == F32 && batch <= 4) fwd.images = 4;
+        if (bp.variant == VARIANT_TILED && batch <= 16) bp.images = 16;
+        return;
+    }
     fwd.variant = it->second.fwd_variant;
     bp.variant = it->second.bp_variant;
     fwd.images = it->second.fwd_images;

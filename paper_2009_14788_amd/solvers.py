@@ -80,6 +80,7 @@ def _solver_call(fn_name, op, y, x, solver, *args):
         raise ValueError("sinogram and guess must have the same dtype")
     code = dtype_code(x.dtype)
     batch = _systems(x)
+    op.prepare(x.dtype, batch, x.device)          # tuned launch shapes for this batch
     nbytes = _lib.lib.radon_solver_workspace_bytes(op.geometry, solver, batch, code)
     if nbytes < 0:
         _lib.check("radon_solver_workspace_bytes", int(nbytes))
