@@ -9,14 +9,16 @@ built (there is no CPU fallback).
 import importlib
 
 __all__ = ["Radon", "RadonFanbeam", "RadonForward", "RadonBackprojection", "dot_f64",
-           "default_fan_spacing", "release_plans", "power_iteration", "unrolled_gd",
-           "BatchedRadon", "inputs"]
+           "dot_f64_batched", "autocast_dtype", "default_fan_spacing", "release_plans",
+           "power_iteration", "unrolled_gd", "Landweber", "cg", "cgne", "BatchedRadon",
+           "inputs"]
 
 _LAZY = {
     "Radon": "radon", "RadonFanbeam": "radon", "RadonForward": "radon",
     "RadonBackprojection": "radon", "dot_f64": "radon", "default_fan_spacing": "radon",
-    "release_plans": "radon", "power_iteration": "solvers", "unrolled_gd": "solvers",
-    "BatchedRadon": "batched",
+    "release_plans": "radon", "dot_f64_batched": "radon", "autocast_dtype": "radon",
+    "power_iteration": "solvers", "unrolled_gd": "solvers", "Landweber": "solvers",
+    "cg": "solvers", "cgne": "solvers", "BatchedRadon": "batched",
 }
 
 

@@ -26,6 +26,18 @@ def dtype_code(t: torch.dtype) -> int:
         raise TypeError(f"unsupported dtype {t}; use float32, float16 or bfloat16") from None
 
 
+def autocast_dtype(t: torch.Tensor) -> torch.dtype:
+    """Storage type a differentiable projection of t runs in.  Under torch.autocast on
+    the GPU with a 16-bit type, an FP32 input is projected with that storage type (16-bit
+    data, FP32 arithmetic: the half-precision mode of TorchRadon Sec. 3.3, usable with
+    AMP as Sec. 2 states); otherwise t's own type."""
+    if t.dtype == torch.float32 and torch.is_autocast_enabled("cuda"):
+        dt = torch.get_autocast_dtype("cuda")
+        if dt in (torch.float16, torch.bfloat16):
+            return dt
+    return t.dtype
+
+
 def _stream_ptr(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
@@ -104,12 +116,15 @@ class _Base:
 
     # ---------------------------------------------------------------- autograd-aware
     def forward(self, x: torch.Tensor, scale: float = 1.0) -> torch.Tensor:
-        """Sinogram scale * R x; differentiable (the gradient is scale * R^T g)."""
-        return RadonForward.apply(x, self, float(scale))
+        """Sinogram scale * R x; differentiable (the gradient is scale * R^T g, formed
+        in x's own type).  Under torch.autocast an FP32 x is projected in the autocast
+        16-bit type (see autocast_dtype) and its gradient still comes back in FP32."""
+        return RadonForward.apply(x, self, float(scale), autocast_dtype(x))
 
     def backprojection(self, y: torch.Tensor, scale: float = 1.0) -> torch.Tensor:
-        """Backprojection scale * R^T y; differentiable (the gradient is scale * R g)."""
-        return RadonBackprojection.apply(y, self, float(scale))
+        """Backprojection scale * R^T y; differentiable (the gradient is scale * R g,
+        formed in y's own type); autocast as for forward."""
+        return RadonBackprojection.apply(y, self, float(scale), autocast_dtype(y))
 
     # the paper's ADMM example calls the backprojection `backward` (Sec. 4.3)
     backward = backprojection
@@ -145,7 +160,11 @@ class _Base:
         "hamming", "hann") and scaled by pi / (A * det_spacing), so that
         ``backprojection(filter_sinogram(y))`` reconstructs the image when the angles
         cover [0, pi) uniformly.  Parallel beam.  Differentiable: the filter is
-        symmetric, so its gradient is the same filter."""
+        symmetric, so its gradient is the same filter.  Under torch.autocast a 16-bit
+        sinogram is filtered in FP32 and the result is FP32, as the paper's
+        half-precision FBP filters in single precision (Sec. 3.3)."""
+        if y.dtype in (torch.float16, torch.bfloat16) and torch.is_autocast_enabled("cuda"):
+            y = y.float()
         return RadonFilter.apply(y, self, filter_name)
 
     def prepare(self, dtype=torch.float32, batch: int = 1, device=None) -> None:
@@ -199,32 +218,42 @@ class RadonFanbeam(_Base):
         super().__init__(resolution, angles, D, sp, step, S, E)
 
 
+def _grad_in(g: torch.Tensor, dtype: torch.dtype) -> torch.Tensor:
+    g = g.contiguous()
+    return g if g.dtype == dtype else g.to(dtype)
+
+
 class RadonForward(torch.autograd.Function):
-    """y = scale * R x; backward applies the hand-written transpose kernel."""
+    """y = scale * R x stored as `dtype`; backward applies the hand-written transpose
+    kernel in x's own type (so a 16-bit forward of an FP32 input has an FP32 gradient,
+    which cannot overflow the 16-bit range)."""
 
     @staticmethod
-    def forward(ctx, x, op, scale):
+    def forward(ctx, x, op, scale, dtype):
         ctx.op = op
         ctx.scale = scale
-        return op.forward_raw(x, scale)
+        ctx.in_dtype = x.dtype
+        return op.forward_raw(x if x.dtype == dtype else x.to(dtype), scale)
 
     @staticmethod
     def backward(ctx, g):
-        return ctx.op.backprojection_raw(g.contiguous(), ctx.scale), None, None
+        return ctx.op.backprojection_raw(_grad_in(g, ctx.in_dtype), ctx.scale), None, None, None
 
 
 class RadonBackprojection(torch.autograd.Function):
-    """x = scale * R^T y; backward applies the forward kernel."""
+    """x = scale * R^T y stored as `dtype`; backward applies the forward kernel in y's
+    own type."""
 
     @staticmethod
-    def forward(ctx, y, op, scale):
+    def forward(ctx, y, op, scale, dtype):
         ctx.op = op
         ctx.scale = scale
-        return op.backprojection_raw(y, scale)
+        ctx.in_dtype = y.dtype
+        return op.backprojection_raw(y if y.dtype == dtype else y.to(dtype), scale)
 
     @staticmethod
     def backward(ctx, g):
-        return ctx.op.forward_raw(g.contiguous(), ctx.scale), None, None
+        return ctx.op.forward_raw(_grad_in(g, ctx.in_dtype), ctx.scale), None, None, None
 
 
 class RadonFilter(torch.autograd.Function):

@@ -1,0 +1,136 @@
+"""Automatic mixed precision (TorchRadon Sec. 2: half precision usable with AMP;
+Sec. 3.3: 16-bit storage, FP32 arithmetic, FBP filtered in single precision): under
+torch.autocast the differentiable projections of FP32 inputs run with 16-bit storage
+and hand back FP32 gradients; the FBP filter runs in FP32; outside autocast every call
+keeps its input's type."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import filtering
+from paper_2009_14788_amd import inputs
+from _helpers import TOL_F32, TOL_16, rel_l2, report
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TDT = {"f16": torch.float16, "bf16": torch.bfloat16}
+
+
+def _pair(n, A, D):
+    from paper_2009_14788_amd.radon import Radon
+    ang = inputs.uniform_angles(A)
+    return Radon(n, ang, D), oracle.Geometry(n, ang, D, 1.0)
+
+
+@pytest.mark.parametrize("dt", ["f16", "bf16"])
+def test_autocast_forward_16bit_with_fp32_gradient(dt):
+    op, g = _pair(64, 60, 91)
+    x_np = inputs.phantom_batch(61, 2, 64).astype(np.float32)
+    w_np = inputs.randn((2, 60, 91), 62, np.float32)
+    x = torch.from_numpy(x_np).cuda().requires_grad_(True)
+    w = torch.from_numpy(w_np).cuda()
+    print(f"[gpu-step] autocast forward {dt}", flush=True)
+    with torch.autocast("cuda", dtype=TDT[dt]):
+        y = op.forward(x)
+        loss = (y.float() * w).sum()
+    loss.backward()
+    assert y.dtype == TDT[dt] and x.grad.dtype == torch.float32
+    # the same kernels as the raw calls: 16-bit forward of the rounded image, FP32
+    # backprojection of the gradient as it arrives (w rounded to the output's type)
+    assert torch.equal(y, op.forward_raw(x.detach().to(TDT[dt])))
+    g16 = w.to(TDT[dt]).float()
+    assert torch.equal(x.grad, op.backprojection_raw(g16))
+    e_y = rel_l2(y.detach().double().cpu().numpy(), oracle.forward(g, x_np.astype(np.float64)))
+    e_g = rel_l2(x.grad.double().cpu().numpy(), oracle.backproject(g, g16.double().cpu().numpy()))
+    report(f"autocast_forward_{dt}", rel_l2=e_y, grad_rel_l2=e_g)
+    assert e_y <= (TOL_16 if dt == "f16" else 2 * TOL_16)
+    assert e_g <= TOL_F32
+
+
+@pytest.mark.parametrize("dt", ["f16", "bf16"])
+def test_autocast_backprojection_16bit_with_fp32_gradient(dt):
+    op, g = _pair(48, 40, 70)
+    y_np = inputs.randn((3, 40, 70), 63, np.float32)
+    w_np = inputs.randn((3, 48, 48), 64, np.float32)
+    y = torch.from_numpy(y_np).cuda().requires_grad_(True)
+    w = torch.from_numpy(w_np).cuda()
+    with torch.autocast("cuda", dtype=TDT[dt]):
+        x = op.backprojection(y, scale=0.01)
+        loss = (x.float() * w).sum()
+    loss.backward()
+    assert x.dtype == TDT[dt] and y.grad.dtype == torch.float32
+    assert torch.equal(x, op.backprojection_raw(y.detach().to(TDT[dt]), scale=0.01))
+    assert torch.equal(y.grad, op.forward_raw(w.to(TDT[dt]).float(), scale=0.01))
+    e = rel_l2(x.detach().double().cpu().numpy(), oracle.backproject(g, y_np.astype(np.float64), 0.01))
+    report(f"autocast_backprojection_{dt}", rel_l2=e)
+    assert e <= (TOL_16 if dt == "f16" else 2 * TOL_16)
+
+
+def test_types_kept_outside_autocast():
+    op, _ = _pair(32, 20, 46)
+    for t in (torch.float32, torch.float16, torch.bfloat16):
+        x = torch.from_numpy(inputs.randn((1, 32, 32), 65, np.float32)).cuda().to(t).requires_grad_(True)
+        y = op.forward(x)
+        y.float().sum().backward()
+        assert y.dtype == t and x.grad.dtype == t
+        assert torch.equal(y, op.forward_raw(x.detach()))
+
+
+def test_autocast_half_precision_fbp():
+    """The paper's half-precision FBP (Sec. 3.3): 16-bit sinogram, filter in FP32,
+    backprojection with 16-bit storage; its reconstruction error against the phantom
+    equals the FP32 pipeline's to within 1% (the paper quotes 2.0566e-4 vs 2.0567e-4)."""
+    n, A = 256, 256
+    D = int(math.ceil(n * math.sqrt(2)))
+    op, g = _pair(n, A, D)
+    x_np = inputs.phantom(n, 67, [6, 0])[0].astype(np.float32)[None]
+    x = torch.from_numpy(x_np).cuda()
+    y = op.forward(x)
+    rec32 = op.backprojection(op.filter_sinogram(y, "ram-lak"))
+    with torch.autocast("cuda", dtype=torch.float16):
+        y16 = op.forward(x)
+        q = op.filter_sinogram(y16, "ram-lak")
+        rec16 = op.backprojection(q)
+    assert y16.dtype == torch.float16 and q.dtype == torch.float32 and rec16.dtype == torch.float16
+    assert torch.equal(q, op.filter_sinogram_raw(y16.float(), "ram-lak"))
+    r = np.hypot(*(np.mgrid[0:n, 0:n] - 0.5 * (n - 1)))
+    inside = r < 0.5 * n - 4
+    m32 = float(np.mean((rec32[0].double().cpu().numpy()[inside] - x_np[0][inside]) ** 2))
+    m16 = float(np.mean((rec16[0].double().cpu().numpy()[inside] - x_np[0][inside]) ** 2))
+    ref = oracle.backproject(g, filtering.filter_sinogram(oracle.forward(g, x_np.astype(np.float64)), "ram-lak"))
+    e16 = rel_l2(rec16.double().cpu().numpy(), ref)
+    report("autocast_fbp_256", mse_fp32=m32, mse_fp16=m16, rel_l2_fp16=e16)
+    assert abs(m16 - m32) <= 0.01 * m32
+    assert e16 <= TOL_16
+
+
+def test_gradscaler_training_step():
+    """An AMP loop (autocast + GradScaler) fitting an FP32 image to a sinogram: gradients
+    reach the FP32 parameter, overflowing scaled steps are skipped by the scaler, and
+    the data misfit falls."""
+    op, g = _pair(64, 45, 91)
+    target = torch.from_numpy(oracle.forward(g, inputs.phantom_batch(68, 1, 64)).astype(np.float32)).cuda()
+    from paper_2009_14788_amd.solvers import power_iteration
+    theta = torch.zeros(1, 64, 64, device="cuda", requires_grad=True)
+    # the mean-square misfit's gradient is (2 / M) R^T (R theta - y): a Landweber step
+    # of 1 / ||R||^2 needs lr = M / (2 ||R||^2)
+    lr = target.numel() / (2.0 * power_iteration(op))
+    opt = torch.optim.SGD([theta], lr=lr)
+    scaler = torch.amp.GradScaler("cuda")
+    losses = []
+    for _ in range(30):
+        opt.zero_grad(set_to_none=True)
+        with torch.autocast("cuda", dtype=torch.float16):
+            y = op.forward(theta)
+            loss = ((y.float() - target) ** 2).mean()
+        scaler.scale(loss).backward()
+        assert theta.grad.dtype == torch.float32
+        scaler.step(opt)
+        scaler.update()
+        losses.append(float(loss))
+    report("gradscaler_fit", first=losses[0], last=losses[-1], scale=float(scaler.get_scale()))
+    assert torch.isfinite(theta).all()
+    assert losses[-1] < 0.5 * losses[0]
