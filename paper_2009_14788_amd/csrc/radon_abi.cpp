@@ -510,7 +510,7 @@ static int build_batch_table(const std::vector<Plan *> &plans, const radon_job_t
                 const int nimg = p->geom.n;
                 const int tiles = ((nimg + kBpTile - 1) / kBpTile) * ((nimg + kBpTile - 1) / kBpTile);
                 const size_t need = !p->geom.fan
-                    ? (size_t)planes * kBpAngles * j.window * sizeof(uint4)
+                    ? (size_t)planes * kBpAngles * kBpWinPar * sizeof(uint4)
                     : (size_t)planes * kBpAnglesFan * j.window * sizeof(uint4) +
                           (size_t)kBpAnglesFan * j.window * sizeof(double4);
                 lds = std::max(lds, need);
@@ -662,9 +662,11 @@ static void call_shapes(Plan *p, int dtype, int batch, LaunchShape &fwd, LaunchS
     auto it = p->tuned.find({dtype, batch_class(batch)});
     if (it == p->tuned.end() || !it->second.valid) {
         // untuned small batches: the narrowest tiled shapes leave the fewest lanes
-        // without an image (one 16-byte chunk forward, 16 images per lane backward)
+        // without an image (one 16-byte chunk per lane: 4 FP32 or 8 16-bit images)
+        const int chunk = dtype == F32 ? 4 : 8;
         if (fwd.variant == VARIANT_TILED && dtype == F32 && batch <= 4) fwd.images = 4;
-        if (bp.variant == VARIANT_TILED && batch <= 16) bp.images = 16;
+        if (bp.variant == VARIANT_TILED && batch <= 16) bp.images = batch <= chunk ? 4 : 16;
+        if (bp.variant == VARIANT_TILED && batch <= chunk) bp.stage = 0;   // no copy for one chunk
         return;
     }
     fwd.variant = it->second.fwd_variant;

@@ -3,7 +3,8 @@
 //
 // Forward candidates: images per lane {8, 4 (FP32 only), 16 (16-bit only)} x slab
 // staging {interleaved copy, caller's images}, and the direct kernel.
-// Backprojection candidates: images per lane {64, 32, 16} x angles per LDS block {8, 4}
+// Backprojection candidates: images per lane {64, 32, 16, one chunk (batches <= 8)} x
+// angles per LDS block {8, 4}
 // (parallel beam; the fan beam's block is fixed at 4 because its rays are staged
 // too) x sinogram staging {interleaved copy, caller's sinograms}, and the direct kernel.  The direct kernels win on tiny problems, where the
 // tiled kernels' sequential slabs and angle blocks are latency-bound.  Results live in the plan
@@ -146,8 +147,10 @@ int autotune(Plan &p, int dtype, int batch, void *ws, size_t ws_bytes, TunedShap
         out.bp_variant = VARIANT_DIRECT;
         const std::vector<int> abs = p.geom.fan ? std::vector<int>{kBpAnglesFan}
                                                 : std::vector<int>{kBpAngles, 4};
-        const std::vector<int> ims{64, 32, 16};
+        // one chunk per lane (4 FP32 or 8 16-bit images) only pays for small batches
+        const std::vector<int> ims{64, 32, 16, 4};
         for (int im : ims)
+            if (im >= 16 || batch <= 8)
             for (int ab : abs)
                 for (int st : {1, 0}) {
                     LaunchShape sh = p.bp_shape;

@@ -110,8 +110,10 @@ __global__ __launch_bounds__(256) void bp_tiled_par(Geom g, const T *__restrict_
 }
 
 // Same, staging from the interleaved, zero-padded copy yi of the batch's sinograms.
+// Four resident blocks (four waves per SIMD) cap the registers at 128, so the plane
+// pipeline of the inner loop does not lower the occupancy.
 template <typename T, int BC, int NB, int NK, int AB>
-__global__ __launch_bounds__(256) void bp_tiled_par_il(Geom g, const uint4 *__restrict__ yi,
+__global__ __launch_bounds__(256, 4) void bp_tiled_par_il(Geom g, const uint4 *__restrict__ yi,
                                                        T *__restrict__ x, int batch, float scale_dt,
                                                        int W) {
     extern __shared__ uint4 lds[];
@@ -125,7 +127,7 @@ __global__ __launch_bounds__(256) void bp_tiled_par_il(Geom g, const uint4 *__re
     src.base = yi + (size_t)(b0 / CH) * src.plane_stride;
     src.D = g.det_count;
     src.Dp = Dp;
-    src.setup(W, AB * W);
+    src.setup(W, AB * kBpWinPar);
     bp_tile_par<T, BC, NB, NK, AB>(g, blockIdx.x, imgs, src, W, lds);
 }
 
@@ -221,7 +223,7 @@ static hipError_t launch_bp_tiled(const Geom &g, const BpWork &work, const Launc
     const uint4 *yi = (const uint4 *)ws;
     if (!g.fan) {
         if (shape.angles <= 4) {
-            const size_t lds = (size_t)PLANES * 4 * W * sizeof(uint4);
+            const size_t lds = (size_t)PLANES * 4 * kBpWinPar * sizeof(uint4);
             if (il)
                 hipLaunchKernelGGL((bp_tiled_par_il<T, BC, 3, 3, 4>), grid, dim3(256), lds, s, g, yi,
                                    (T *)x, batch, scale_dt, W);
@@ -229,7 +231,7 @@ static hipError_t launch_bp_tiled(const Geom &g, const BpWork &work, const Launc
                 hipLaunchKernelGGL((bp_tiled_par<T, BC, 3, 3, 4>), grid, dim3(256), lds, s, g,
                                    (const T *)y, (T *)x, batch, scale_dt, W);
         } else {
-            const size_t lds = (size_t)PLANES * kBpAngles * W * sizeof(uint4);
+            const size_t lds = (size_t)PLANES * kBpAngles * kBpWinPar * sizeof(uint4);
             if (il)
                 hipLaunchKernelGGL((bp_tiled_par_il<T, BC, 3, 3, kBpAngles>), grid, dim3(256), lds, s,
                                    g, yi, (T *)x, batch, scale_dt, W);
@@ -267,16 +269,20 @@ hipError_t launch_backproject(const Geom &g, const BpWork &work, int dtype, cons
     if (shape.variant == VARIANT_TILED && work.window > 0) {
         const int im = shape.images;
 #define RADON_BP_TILED(T, BC) launch_bp_tiled<T, BC>(g, work, shape, y, x, batch, scale_dt, ws, ws_bytes, s)
+        // images per lane: 64, 32, 16, or one 16-byte chunk (4 FP32 / 8 16-bit images)
         switch (dtype) {
         case F32:
             return im >= 64 ? RADON_BP_TILED(float, 64)
-                 : im >= 32           ? RADON_BP_TILED(float, 32) : RADON_BP_TILED(float, 16);
+                 : im >= 32 ? RADON_BP_TILED(float, 32)
+                 : im >= 16 ? RADON_BP_TILED(float, 16) : RADON_BP_TILED(float, 4);
         case F16:
             return im >= 64 ? RADON_BP_TILED(__half, 64)
-                 : im >= 32           ? RADON_BP_TILED(__half, 32) : RADON_BP_TILED(__half, 16);
+                 : im >= 32 ? RADON_BP_TILED(__half, 32)
+                 : im >= 16 ? RADON_BP_TILED(__half, 16) : RADON_BP_TILED(__half, 8);
         case BF16:
             return im >= 64 ? RADON_BP_TILED(bf16_t, 64)
-                 : im >= 32           ? RADON_BP_TILED(bf16_t, 32) : RADON_BP_TILED(bf16_t, 16);
+                 : im >= 32 ? RADON_BP_TILED(bf16_t, 32)
+                 : im >= 16 ? RADON_BP_TILED(bf16_t, 16) : RADON_BP_TILED(bf16_t, 8);
         default: return hipErrorInvalidValue;
         }
 #undef RADON_BP_TILED

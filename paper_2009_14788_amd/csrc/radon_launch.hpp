@@ -81,6 +81,11 @@ size_t interleaved_bytes(int n, int batch, int dtype);
 constexpr int kBpTile = 16;        // pixels per tile side (one lane per pixel)
 constexpr int kBpAngles = 8;       // angles per LDS block (parallel beam)
 constexpr int kBpAnglesFan = 4;    // angles per LDS block (fan beam; rays are staged too)
+// Parallel beam: LDS pitch (in chunks) of one staged angle's bin window.  The planner's
+// window is 4 * ceil((floor(15 h / spacing) + 6) / 4) with h = |cos| + |sin| <= 1.5
+// spacing (3 candidate bins must cover a footprint), so it never exceeds 28; a fixed
+// pitch makes every plane offset of the LDS reads a compile-time immediate.
+constexpr int kBpWinPar = 28;
 
 struct BpWork {
     int window = 0;                // bins staged per (tile, angle); 0 = use the direct kernel

@@ -129,6 +129,7 @@ BpWork plan_backproject(int beam, int n, const std::vector<double2> &trig, doubl
         // 3 candidate bins must cover the footprint's extent across the rays
         if (2.0 * hmax / spacing > 3.0) return w;
         const int win = (int)std::floor((kBpTile - 1) * hmax / spacing) + 3 + 3;
+        if (((win + 3) & ~3) > kBpWinPar) return w;     // cannot happen (see kBpWinPar)
         w.window = (win + 3) & ~3;
         w.bins = 3;
         return w;

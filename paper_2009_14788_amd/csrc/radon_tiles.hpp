@@ -377,7 +377,8 @@ __device__ __forceinline__ void bp_tile_par(const Geom &g, int tile, const Image
     const int c = tx0 + (threadIdx.x % kBpTile), r = ty0 + (threadIdx.x / kBpTile);
     const double qx = (double)c - g.cn, qy = (double)r - g.cn;
     const double tcx = tx0 + 0.5 * (kBpTile - 1) - g.cn, tcy = ty0 + 0.5 * (kBpTile - 1) - g.cn;
-    const int per_plane = AB * W;
+    // planes at a fixed pitch (W <= kBpWinPar): the reads below use immediate offsets
+    constexpr int per_plane = AB * kBpWinPar;
     const float dt = (float)g.step, sp = (float)g.spacing;
 
     float acc[BC];
@@ -435,10 +436,24 @@ __device__ __forceinline__ void bp_tile_par(const Geom &g, int tile, const Image
             int lb = (int)db + 1 - wlo_s[al];
             lb = min(max(lb, 0), W - NB);               // memory safety; real pixels are inside
             const uint4 *row = lds + al * W + lb;
+            // planes in a register pipeline: the next plane's NB chunks are read while
+            // the current plane's are applied, so LDS latency overlaps the multiply-adds
+            uint4 cur[NB];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) cur[i] = row[i];
 #pragma unroll
             for (int qq = 0; qq < PLANES; ++qq) {
+                uint4 nxt[NB];
+                if (qq + 1 < PLANES) {
 #pragma unroll
-                for (int i = 0; i < NB; ++i) Chunk<T>::fma(wgt[i], row[qq * per_plane + i], part + qq * CH);
+                    for (int i = 0; i < NB; ++i) nxt[i] = row[(qq + 1) * per_plane + i];
+                }
+#pragma unroll
+                for (int i = 0; i < NB; ++i) Chunk<T>::fma(wgt[i], cur[i], part + qq * CH);
+                if (qq + 1 < PLANES) {
+#pragma unroll
+                    for (int i = 0; i < NB; ++i) cur[i] = nxt[i];
+                }
             }
         }
         if (kTwoLevel) {

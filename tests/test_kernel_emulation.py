@@ -112,7 +112,7 @@ def test_emulated_kernels_match_oracle(emu_bin, tmp_path):
     assert rows[2][:2] == (1, 1) and rows[10][:2] == (1, 1), rows
 
 
-@pytest.mark.parametrize("shape", ["8,0,16,4,0", "4,1,32,4,1", "16,1,32,8,0", "8,1,16,8,1", "4,1,64,4,1", "8,0,64,8,0"])
+@pytest.mark.parametrize("shape", ["8,0,16,4,0", "4,1,32,4,1", "16,1,32,8,0", "8,1,16,8,1", "4,1,64,4,1", "8,0,64,8,0", "8,1,4,8,1", "4,0,4,4,0"])
 def test_emulated_launch_shapes(emu_bin, tmp_path, shape):
     """Every forced launch shape (images per lane, staging, angle block) stays in
     bounds and at parity, with a ragged batch of 11 images."""
