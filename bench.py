@@ -28,16 +28,21 @@ PEAK_HBM_GBS = 8000.0         # MI355X HBM3E
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "hbm_traffic_batch128_512.md")
 
 
+# the sources that define the forward and backprojection kernels, their launches and
+# their work plans: the HBM traffic record is valid while these are unchanged
+PROJECTOR_SOURCES = ("radon_abi.cpp", "radon_bp.hip", "radon_common.hpp", "radon_fwd.hip",
+                     "radon_launch.hpp", "radon_plan.hpp", "radon_planner.cpp", "radon_tiles.hpp")
+
+
 def kernel_sources_sha256():
-    """SHA-256 over the library's kernel and planner sources (name + bytes, sorted)."""
+    """SHA-256 over the projector kernel and planner sources (name + bytes, sorted)."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2009_14788_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp", ".cpp")):
-            h.update(name.encode())
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(f.read())
+    for name in sorted(PROJECTOR_SOURCES):
+        h.update(name.encode())
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()
 
 

@@ -8,9 +8,11 @@
 // One block filters two rows at once: row 0 is the real part and row 1 the
 // imaginary part of one complex sequence; because H is real and even, the filtered
 // sequence's real and imaginary parts are the two filtered rows.  The transforms are
-// radix-2 in LDS: decimation in time from bit-reversed input for the forward
-// transform, decimation in frequency with conjugate twiddles for the inverse, so no
-// reordering pass is needed.  FP32 arithmetic; twiddles are FP64 values rounded once.
+// Stockham autosort FFTs in LDS (natural order in and out, no reordering pass): radix-8
+// passes with one or two radix-4 passes first when log2 L is not a multiple of 3, each
+// pass a register DFT per butterfly between two barriers (4 passes for L = 2048
+// instead of 11 radix-2 stages).  The inverse transform is the forward one applied to
+// conj(H X), conjugated.  FP32 arithmetic; twiddles are FP64 values rounded once.
 #include <cmath>
 
 #include "radon_common.hpp"
@@ -18,72 +20,133 @@
 
 namespace radon {
 
+constexpr int kFilterThreads = 256;
+
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
 }
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 
-template <typename T>
-__global__ __launch_bounds__(256) void filter_rows(const T *__restrict__ y, T *__restrict__ out,
-                                                   long long rows, int D, int log2L,
-                                                   const float *__restrict__ H,
-                                                   const float2 *__restrict__ tw, float scale) {
+// In-register DFTs, natural order in and out: X_k = sum_n x_n exp(-2 pi i n k / R).
+__device__ __forceinline__ void dft4(float2 &x0, float2 &x1, float2 &x2, float2 &x3) {
+    const float2 a = cadd(x0, x2), b = csub(x0, x2), c = cadd(x1, x3), d = csub(x1, x3);
+    x0 = cadd(a, c);
+    x2 = csub(a, c);
+    x1 = make_float2(b.x + d.y, b.y - d.x);             // b - i d
+    x3 = make_float2(b.x - d.y, b.y + d.x);             // b + i d
+}
+
+template <int R> __device__ __forceinline__ void dft(float2 *v);
+
+template <> __device__ __forceinline__ void dft<4>(float2 *v) { dft4(v[0], v[1], v[2], v[3]); }
+
+template <> __device__ __forceinline__ void dft<8>(float2 *v) {
+    // even and odd halves, then X_k = E_k + W^k O_k, X_{k+4} = E_k - W^k O_k, W = exp(-i pi/4)
+    float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4(e0, e1, e2, e3);
+    dft4(o0, o1, o2, o3);
+    constexpr float c = 0.70710678118654752f;
+    const float2 t1 = make_float2(c * (o1.x + o1.y), c * (o1.y - o1.x));    // W   o1
+    const float2 t2 = make_float2(o2.y, -o2.x);                            // W^2 o2 = -i o2
+    const float2 t3 = make_float2(c * (o3.y - o3.x), -c * (o3.x + o3.y));   // W^3 o3
+    v[0] = cadd(e0, o0);
+    v[4] = csub(e0, o0);
+    v[1] = cadd(e1, t1);
+    v[5] = csub(e1, t1);
+    v[2] = cadd(e2, t2);
+    v[6] = csub(e2, t2);
+    v[3] = cadd(e3, t3);
+    v[7] = csub(e3, t3);
+}
+
+// One Stockham pass of radix R = 2^LOG2R over buf[0, 2^LOG2L) in place, Ns = 2^LOG2NS:
+// every thread first reads all its butterflies' inputs, the block synchronises, then
+// each butterfly j (k = j mod Ns) applies the twiddles exp(-2 pi i r k / (Ns R)) =
+// tw[r k L / (Ns R)], its R-point DFT, and writes output r to (j - k) R + k + r Ns.
+template <int LOG2R, int LOG2L, int LOG2NS>
+__device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *__restrict__ tw) {
+    constexpr int R = 1 << LOG2R;
+    constexpr int nb = 1 << (LOG2L - LOG2R);             // butterflies
+    constexpr int Ns = 1 << LOG2NS;
+    constexpr int sh = LOG2L - LOG2NS - LOG2R;
+    constexpr int JMAX = (nb + kFilterThreads - 1) / kFilterThreads;
+    float2 v[JMAX][R];
+#pragma unroll
+    for (int jj = 0; jj < JMAX; ++jj) {
+        const int j = threadIdx.x + kFilterThreads * jj;
+        if (j < nb) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[jj][r] = buf[j + r * nb];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < JMAX; ++jj) {
+        const int j = threadIdx.x + kFilterThreads * jj;
+        if (j < nb) {
+            const int k = j & (Ns - 1);
+            if (Ns > 1 && k != 0) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[jj][r] = cmul(v[jj][r], tw[(r * k) << sh]);
+            }
+            dft<R>(v[jj]);
+            const int base = ((j - k) << LOG2R) + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[base + r * Ns] = v[jj][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Forward transform of buf[0, 2^LOG2L): radix-4 passes while the remaining exponent is
+// not a multiple of 3, then radix-8 passes.
+template <int LOG2L, int LOG2NS = 0>
+__device__ __forceinline__ void fft_inplace(float2 *buf, const float2 *__restrict__ tw) {
+    if constexpr (LOG2NS < LOG2L) {
+        constexpr int LOG2R = (LOG2L - LOG2NS) % 3 != 0 ? 2 : 3;
+        stockham_pass<LOG2R, LOG2L, LOG2NS>(buf, tw);
+        fft_inplace<LOG2L, LOG2NS + LOG2R>(buf, tw);
+    }
+}
+
+template <typename T, int LOG2L>
+__global__ __launch_bounds__(kFilterThreads) void filter_rows(const T *__restrict__ y, T *__restrict__ out,
+                                                              long long rows, int D,
+                                                              const float *__restrict__ H,
+                                                              const float2 *__restrict__ tw, float scale) {
     extern __shared__ float2 buf[];
-    const int L = 1 << log2L;
+    constexpr int L = 1 << LOG2L;
     const long long r0 = 2 * (long long)blockIdx.x;
     const bool has1 = r0 + 1 < rows;
     const T *y0 = y + r0 * D;
     const T *y1 = y + (has1 ? r0 + 1 : r0) * D;
-    // bit-reversed load: buf[k] = x[brev(k)]
-    for (int k = threadIdx.x; k < L; k += 256) {
-        const int j = (int)(__brev((unsigned)k) >> (32 - log2L));
+    for (int k = threadIdx.x; k < L; k += kFilterThreads) {
         float2 v = make_float2(0.0f, 0.0f);
-        if (j < D) {
-            v.x = Store<T>::load(y0 + j);
-            v.y = has1 ? Store<T>::load(y1 + j) : 0.0f;
+        if (k < D) {
+            v.x = Store<T>::load(y0 + k);
+            v.y = has1 ? Store<T>::load(y1 + k) : 0.0f;
         }
         buf[k] = v;
     }
     __syncthreads();
-    // forward transform, decimation in time: spans 1, 2, 4, ...
-    for (int s = 1; s <= log2L; ++s) {
-        const int half = 1 << (s - 1);
-        for (int b = threadIdx.x; b < (L >> 1); b += 256) {
-            const int pos = b & (half - 1);
-            const int i0 = ((b >> (s - 1)) << s) + pos, i1 = i0 + half;
-            const float2 w = tw[pos << (log2L - s)];           // exp(-2 pi i pos / (2 half))
-            const float2 a = buf[i0], t = cmul(buf[i1], w);
-            buf[i0] = make_float2(a.x + t.x, a.y + t.y);
-            buf[i1] = make_float2(a.x - t.x, a.y - t.y);
-        }
-        __syncthreads();
-    }
-    for (int k = threadIdx.x; k < L; k += 256) {
+    fft_inplace<LOG2L>(buf, tw);
+    // conj(X) H: the inverse transform is conj(FFT(conj(H X))) / L
+    for (int k = threadIdx.x; k < L; k += kFilterThreads) {
         const float h = H[k];
-        buf[k] = make_float2(buf[k].x * h, buf[k].y * h);
+        const float2 x = buf[k];
+        buf[k] = make_float2(x.x * h, -x.y * h);
     }
     __syncthreads();
-    // inverse transform, decimation in frequency with conjugate twiddles: spans
-    // L/2, ..., 1; the result ends in bit-reversed order
-    for (int s = log2L; s >= 1; --s) {
-        const int half = 1 << (s - 1);
-        for (int b = threadIdx.x; b < (L >> 1); b += 256) {
-            const int pos = b & (half - 1);
-            const int i0 = ((b >> (s - 1)) << s) + pos, i1 = i0 + half;
-            const float2 w = tw[pos << (log2L - s)];
-            const float2 wc = make_float2(w.x, -w.y);          // exp(+2 pi i pos / (2 half))
-            const float2 a = buf[i0], c = buf[i1];
-            buf[i0] = make_float2(a.x + c.x, a.y + c.y);
-            buf[i1] = cmul(make_float2(a.x - c.x, a.y - c.y), wc);
-        }
-        __syncthreads();
-    }
+    fft_inplace<LOG2L>(buf, tw);
     const float f = scale / (float)L;
     T *o0 = out + r0 * D;
     T *o1 = out + (r0 + 1) * D;
-    for (int n = threadIdx.x; n < D; n += 256) {
-        const float2 v = buf[__brev((unsigned)n) >> (32 - log2L)];
+    for (int n = threadIdx.x; n < D; n += kFilterThreads) {
+        const float2 v = buf[n];
         Store<T>::store(o0 + n, v.x * f);
-        if (has1) Store<T>::store(o1 + n, v.y * f);
+        if (has1) Store<T>::store(o1 + n, -v.y * f);
     }
 }
 
@@ -120,33 +183,39 @@ void filter_response(int filter, int log2L, std::vector<float> &H) {
 void filter_twiddles(int log2L, std::vector<float2> &tw) {
     const int L = 1 << log2L;
     const double pi = 3.14159265358979323846;
-    tw.resize(L / 2);
-    for (int k = 0; k < L / 2; ++k)
+    tw.resize(L);
+    for (int k = 0; k < L; ++k)
         tw[k] = make_float2((float)std::cos(2.0 * pi * k / L), (float)-std::sin(2.0 * pi * k / L));
+}
+
+template <typename T>
+static hipError_t launch_rows(const void *y, void *out, long long rows, int D, int log2L,
+                              const float *H, const float2 *tw, float scale, hipStream_t s) {
+    const size_t lds = sizeof(float2) << log2L;
+    const dim3 grid((unsigned)((rows + 1) / 2)), block(kFilterThreads);
+    const T *yi = (const T *)y;
+    T *o = (T *)out;
+    switch (log2L) {
+#define RADON_FILTER_CASE(M) \
+    case M: hipLaunchKernelGGL((filter_rows<T, M>), grid, block, lds, s, yi, o, rows, D, H, tw, scale); break;
+    RADON_FILTER_CASE(6) RADON_FILTER_CASE(7) RADON_FILTER_CASE(8) RADON_FILTER_CASE(9)
+    RADON_FILTER_CASE(10) RADON_FILTER_CASE(11) RADON_FILTER_CASE(12) RADON_FILTER_CASE(13)
+#undef RADON_FILTER_CASE
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_filter(int dtype, const void *y, void *out, long long rows, int D, int log2L,
                          const float *H, const float2 *tw, float scale, hipStream_t s) {
     if (rows <= 0) return hipSuccess;
-    const size_t lds = sizeof(float2) << log2L;
-    const long long blocks = (rows + 1) / 2;
-    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    if ((rows + 1) / 2 > 0x7fffffffLL) return hipErrorInvalidValue;
     switch (dtype) {
-    case F32:
-        hipLaunchKernelGGL(filter_rows<float>, dim3((unsigned)blocks), dim3(256), lds, s,
-                           (const float *)y, (float *)out, rows, D, log2L, H, tw, scale);
-        break;
-    case F16:
-        hipLaunchKernelGGL(filter_rows<__half>, dim3((unsigned)blocks), dim3(256), lds, s,
-                           (const __half *)y, (__half *)out, rows, D, log2L, H, tw, scale);
-        break;
-    case BF16:
-        hipLaunchKernelGGL(filter_rows<bf16_t>, dim3((unsigned)blocks), dim3(256), lds, s,
-                           (const bf16_t *)y, (bf16_t *)out, rows, D, log2L, H, tw, scale);
-        break;
+    case F32: return launch_rows<float>(y, out, rows, D, log2L, H, tw, scale, s);
+    case F16: return launch_rows<__half>(y, out, rows, D, log2L, H, tw, scale, s);
+    case BF16: return launch_rows<bf16_t>(y, out, rows, D, log2L, H, tw, scale, s);
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 }  // namespace radon

@@ -15,7 +15,7 @@ constexpr int kFilterMaxLog2 = 13;   // L <= 8192: the row pair's transform fits
 int filter_log2_length(int det_count);
 // Frequency response H[0..L) of a filter (FP64 on the host, rounded to FP32).
 void filter_response(int filter, int log2L, std::vector<float> &H);
-// Forward twiddles exp(-2 pi i k / L), k < L/2.
+// Forward twiddles exp(-2 pi i k / L), k < L.
 void filter_twiddles(int log2L, std::vector<float2> &tw);
 // out[r][0..D) = scale * (row r of y filtered by H), for `rows` rows of D values of
 // `dtype` (in place allowed: out == y).

@@ -24,9 +24,11 @@ def _op(n, A, D, sp=1.0):
 
 
 @pytest.mark.parametrize("D,A,B,sp", [(23, 8, 3, 1.0), (91, 64, 1, 0.7), (725, 16, 2, 1.0),
-                                      (1024, 5, 3, 1.0), (4096, 2, 1, 1.0)])
+                                      (1024, 5, 3, 1.0), (4096, 2, 1, 1.0), (40, 9, 1, 1.0),
+                                      (181, 4, 1, 1.0), (300, 7, 1, 1.0), (1500, 3, 2, 1.0)])
 def test_filter_matches_oracle(D, A, B, sp):
-    """Every filter, FP32: full tensors, odd row counts, padded lengths 64 .. 8192."""
+    """Every filter, FP32: full tensors, odd row counts, padded lengths 64 .. 8192 (every
+    sequence of radix-4 and radix-8 passes)."""
     op = _op(64, A, D, sp)
     y = inputs.randn((B, A, D), 31, np.float32)
     yd = torch.from_numpy(y).cuda()

@@ -139,13 +139,15 @@ def test_emulated_uneven_batch_groups(emu_bin, tmp_path):
 
 
 def test_emulated_filter_matches_oracle(emu_bin, tmp_path):
-    """The FBP filter kernel (radix-2 transforms in LDS, two rows per block) against
-    the FP64 oracle filter for all five filters: odd row counts, several padded
-    lengths, 16-bit storage."""
+    """The FBP filter kernel (Stockham radix-8/radix-4 transforms in LDS, two rows per
+    block) against the FP64 oracle filter for all five filters: odd row counts, padded
+    lengths 64 .. 8192 (every pass sequence), 16-bit storage."""
     from oracle import filtering
     U = inputs.uniform_angles
     specs = [("par", 16, U(7), 23, 1.0, 3, 0), ("par", 24, U(6), 91, 0.5, 1, 0),
-             ("par", 20, U(5), 33, 1.0, 2, 1), ("par", 20, U(5), 40, 1.5, 1, 2)]
+             ("par", 20, U(5), 33, 1.0, 2, 1), ("par", 20, U(5), 40, 1.5, 1, 2),
+             ("par", 8, U(3), 300, 1.0, 1, 0), ("par", 8, U(1), 1500, 1.0, 1, 0),
+             ("par", 8, U(1), 2100, 1.0, 1, 0)]
     lines = [_line(b, n, a, D, sp, batch=B, dt=dt) for b, n, a, D, sp, B, dt in specs]
     geo = tmp_path / "geos.txt"
     geo.write_text("\n".join(lines) + "\n")
