@@ -207,6 +207,33 @@ def main():
             "work": f"8 flop per (image, ray sample); {samples:.4e} samples per launch",
             "algorithmic_bytes": int(bytes_dir)}
 
+    # per direction: throughput and the fractions of the device's measured FP32
+    # multiply-add rate and LDS read bandwidth that the algorithm's own work reaches
+    # (forward: 4 multiply-adds and 4 taps of 4 bytes per image-sample; backprojection:
+    # 3 candidate bins, 3 multiply-adds and 3 x 4 bytes per image, pixel and angle)
+    from paper_2009_14788_amd import _lib
+    import ctypes
+    fma_peak, lds_peak = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    rc = _lib.lib.radon_measure_peaks(ctypes.byref(fma_peak), ctypes.byref(lds_peak))
+    _lib.check("radon_measure_peaks", rc)
+    fma_peak, lds_peak = fma_peak.value, lds_peak.value
+    triples = float(B) * N * N * A
+
+    def direction(ms, fmas, lds_bytes):
+        t = ms * 1e-3
+        return {"ms": round(ms, 4), "projections_per_s": round(B * A / t, 1),
+                "rays_per_s": round(B * A * D / t, 1),
+                "hbm_gbs_algorithmic": round(bytes_dir / t / 1e9, 2),
+                "hbm_frac": round(bytes_dir / t / 1e9 / PEAK_HBM_GBS, 5),
+                "fma_frac_of_measured": round(fmas / t / fma_peak, 4),
+                "lds_frac_of_measured": round(lds_bytes / t / lds_peak, 4)}
+
+    directions = {"forward": direction(fwd_ms, 4.0 * samples, 16.0 * samples),
+                  "backprojection": direction(bp_ms, 3.0 * triples, 12.0 * triples)}
+    peaks = {"fma_per_s": fma_peak, "lds_bytes_per_s": lds_peak,
+             "method": "radon_measure_peaks: v_fmac_f32 chains (packed FP32 off) and conflict-free "
+                       "ds_read_b128 streams on this GPU, best of 3 runs"}
+
     # sampled correctness of this very output against the oracle (8 rays)
     import oracle
     og = oracle.Geometry(N, angles, D, 1.0)
@@ -229,6 +256,8 @@ def main():
         "forward_ms": round(fwd_ms, 4), "backprojection_ms": round(bp_ms, 4),
         "sampled_rel_l2_vs_oracle": err,
         "roofline": roof,
+        "directions": directions,
+        "device_peaks": peaks,
     }
     if not args.quick:
         out["workloads"] = variants(op, x, x_np, B, A, D)

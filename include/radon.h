@@ -202,6 +202,14 @@ int radon_cgne(const radon_geometry_t *geometry, const void *y, void *x, int32_t
                int32_t iterations, int32_t dtype, void *workspace, int64_t workspace_bytes,
                void *stream);
 
+/* Calibration of the current device for roofline fractions: the FP32 multiply-add
+ * rate (multiply-adds per second, v_fmac_f32 with packed FP32 off, many independent
+ * chains) and the LDS read bandwidth (bytes per second, conflict-free 16-byte reads)
+ * that two fixed-length microbenchmark kernels reach; best of three timed runs after a
+ * warm-up run.  Host outputs.  Synchronises the null stream; allocates and frees a small
+ * device buffer.  RADON_ERR_INVALID_ARG for a null output. */
+int radon_measure_peaks(double *fma_per_s, double *lds_bytes_per_s);
+
 /* Free every plan and queue the library holds (synchronises the device). */
 int radon_release_plans(void);
 

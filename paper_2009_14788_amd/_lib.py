@@ -81,6 +81,8 @@ def _load():
         "radon_landweber": ([G, vp, vp, i32, ctypes.c_double, i32, i32, vp, ctypes.c_int64, vp],
                             ctypes.c_int),
         "radon_cgne": ([G, vp, vp, i32, i32, i32, vp, ctypes.c_int64, vp], ctypes.c_int),
+        "radon_measure_peaks": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
+                                ctypes.c_int),
         "radon_release_plans": ([], ctypes.c_int),
         "radon_plan_info": ([G, i32, i32, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
         "radon_status_string": ([ctypes.c_int], ctypes.c_char_p),

@@ -183,3 +183,10 @@ def test_solver_argument_errors_before_device_use():
     assert ax(*ok, 0x3004, None, None, 1.0, 10, 1, 0, None) == -2
     assert ax(*ok, 0x3000, 0x4004, None, 1.0, 10, 1, 0, None) == -2
     assert ax(*ok, 0x3000, None, None, 1.0, 10, 1, 3, None) == -1
+
+
+def test_measure_peaks_null_outputs():
+    """radon_measure_peaks checks its outputs before touching a device."""
+    d = ctypes.c_double(0.0)
+    assert _lib.lib.radon_measure_peaks(None, ctypes.byref(d)) == -1
+    assert _lib.lib.radon_measure_peaks(ctypes.byref(d), None) == -1

@@ -99,3 +99,15 @@ np.save(sys.argv[2], op.forward_raw(x).cpu().numpy())
     assert r2.returncode == 0, r2.stderr[-2000:]
     assert len(cache.read_text().strip().splitlines()) == 1
     assert np.array_equal(np.load(tmp_path / "y2.npy"), y)
+
+
+def test_measure_peaks_plausible():
+    """The device calibration returns finite rates within a broad plausible band for one
+    MI355X-class GPU (multiply-adds per second and LDS bytes per second)."""
+    import ctypes
+    from paper_2009_14788_amd import _lib
+    f, l = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    assert _lib.lib.radon_measure_peaks(ctypes.byref(f), ctypes.byref(l)) == 0
+    print(f"[parity] device_peaks fma_per_s={f.value:.3e} lds_bytes_per_s={l.value:.3e}", flush=True)
+    assert 1e12 < f.value < 1e15
+    assert 1e12 < l.value < 1e15
