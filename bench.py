@@ -47,9 +47,9 @@ def kernel_sources_sha256():
 
 
 def recorded_traffic(direction, shape):
-    """HBM bytes per launch of one direction from the committed counter record, or
-    None when there is no record, the launch shape differs, or the kernel sources
-    changed since the counters were taken."""
+    """HBM bytes per launch of one direction and launch shape from the committed
+    counter record, or None when there is no record, the shape was not recorded, or
+    the kernel sources changed since the counters were taken."""
     import re
     try:
         text = open(TRAFFIC_RECORD).read()
@@ -58,10 +58,9 @@ def recorded_traffic(direction, shape):
     m = re.search(r"traffic-record sources_sha256=(\w+) (.*?)-->", text)
     if not m or m.group(1) != kernel_sources_sha256():
         return None
+    # one "<direction>:<launch shape>=<bytes>" entry per recorded shape
     fields = dict(kv.split("=", 1) for kv in m.group(2).split())
-    if fields.get(f"{direction}_shape") != shape:
-        return None
-    v = fields.get(f"{direction}_bytes")
+    v = fields.get(f"{direction}:{shape}")
     return int(v) if v is not None else None
 
 

@@ -108,9 +108,15 @@ int autotune(Plan &p, int dtype, int batch, void *ws, size_t ws_bytes, TunedShap
     void *x = nullptr, *y = nullptr;
     if (hipMalloc(&x, std::max<size_t>(xb, 16)) != hipSuccess) return -1;
     if (hipMalloc(&y, std::max<size_t>(yb, 16)) != hipSuccess) { (void)hipFree(x); return -1; }
-    (void)hipMemset(x, 0, xb);
-    (void)hipMemset(y, 0, yb);
     hipStream_t s = nullptr;
+    // data-like inputs: the kernels' speed depends on the data (power), and zeros
+    // favour shapes that lose on real images
+    if (launch_fill_pattern(x, (long long)(xb / es), dtype, 1u, s) != hipSuccess ||
+        launch_fill_pattern(y, (long long)(yb / es), dtype, 2u, s) != hipSuccess) {
+        (void)hipFree(x);
+        (void)hipFree(y);
+        return -1;
+    }
 
     if (p.fwd_shape.variant == VARIANT_TILED) {
         std::vector<int> imgs = dtype == F32 ? std::vector<int>{8, 4} : std::vector<int>{8, 16};

@@ -121,5 +121,7 @@ hipError_t launch_dot_rows(const void *a, const void *b, long long n, int batch,
 hipError_t launch_axpy_ratio(const void *u, const void *v, void *out, const double *num,
                              const double *den, double c0, long long n, int batch, int dtype,
                              hipStream_t s);
+// p[0, n) = a reproducible pseudo-random pattern in [-0.5, 0.5) of type `dtype`.
+hipError_t launch_fill_pattern(void *p, long long n, int dtype, unsigned seed, hipStream_t s);
 
 }  // namespace radon

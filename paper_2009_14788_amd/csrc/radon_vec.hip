@@ -79,6 +79,45 @@ __global__ __launch_bounds__(kVecThreads) void axpy_ratio_rows(const T *__restri
     }
 }
 
+// A reproducible pseudo-random pattern in [-0.5, 0.5) (an integer hash of the index
+// and seed), for buffers whose content only has to look like data.
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void fill_pattern(T *__restrict__ p, long long n,
+                                                            unsigned seed) {
+    const long long stride = (long long)gridDim.x * kVecThreads;
+    for (long long i = (long long)blockIdx.x * kVecThreads + threadIdx.x; i < n; i += stride) {
+        unsigned h = (unsigned)i * 2654435761u ^ (unsigned)(i >> 32) ^ seed;
+        h ^= h >> 15;
+        h *= 0x2c1b3c6du;
+        h ^= h >> 12;
+        h *= 0x297a2d39u;
+        h ^= h >> 15;
+        Store<T>::store(p + i, (float)(h >> 8) * (1.0f / 16777216.0f) - 0.5f);
+    }
+}
+
+hipError_t launch_fill_pattern(void *p, long long n, int dtype, unsigned seed, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    long long blocks = (n + kVecThreads - 1) / kVecThreads;
+    if (blocks > 4096) blocks = 4096;
+    switch (dtype) {
+    case F32:
+        hipLaunchKernelGGL(fill_pattern<float>, dim3((unsigned)blocks), dim3(kVecThreads), 0, s,
+                           (float *)p, n, seed);
+        break;
+    case F16:
+        hipLaunchKernelGGL(fill_pattern<__half>, dim3((unsigned)blocks), dim3(kVecThreads), 0, s,
+                           (__half *)p, n, seed);
+        break;
+    case BF16:
+        hipLaunchKernelGGL(fill_pattern<bf16_t>, dim3((unsigned)blocks), dim3(kVecThreads), 0, s,
+                           (bf16_t *)p, n, seed);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 int dot_rows_chunks(long long n) {
     const long long per = (long long)kVecThreads * 16;
     long long c = (n + per - 1) / per;
