@@ -209,6 +209,19 @@ static int build_plan(const radon_geometry_t *g, int device, std::unique_ptr<Pla
     if (!want_direct &&
         plan_forward_tiles(g->image_size, g->n_angles, g->det_count, rays, items, ranges, tile_t) &&
         !items.empty()) {
+        // longest items first (slabs the item's rays cross): blocks are dispatched in
+        // index order, so the short items fill the tail of the launch
+        std::vector<int> slabs(items.size(), 0);
+        for (size_t i = 0; i < items.size(); ++i)
+            for (int si = 0; si < items[i].nslab; ++si)
+                slabs[i] += ranges[items[i].range + si].x <= ranges[items[i].range + si].y;
+        std::vector<size_t> order(items.size());
+        for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](size_t a, size_t b) { return slabs[a] > slabs[b]; });
+        std::vector<FwdItem> sorted(items.size());
+        for (size_t i = 0; i < order.size(); ++i) sorted[i] = items[order[i]];
+        items.swap(sorted);
         if (hipMalloc(&p->fwd_items, items.size() * sizeof(FwdItem)) != hipSuccess)
             return RADON_ERR_ALLOC;
         if (hipMemcpy(p->fwd_items, items.data(), items.size() * sizeof(FwdItem),
