@@ -468,17 +468,73 @@ __device__ __forceinline__ void bp_tile_par(const Geom &g, int tile, const Image
             Store<T>::store(imgs.out[i] + (size_t)r * n + c, acc[i] * imgs.scale[i]);
 }
 
+// The angles al of one staged block with NBX candidate bins per pixel (NBX <= the
+// plan's bin count: the caller checked that NBX bins cover every footprint of the tile
+// at these angles).
+template <typename T, int BC, int NBX, int NK>
+__device__ __forceinline__ void fan_angle_block(const Geom &g, int a0, int na, int W, const int *wlo_s,
+                                                const double4 *rays_s, const uint4 *lds, int per_plane,
+                                                double qx, double qy, int c, int r, double is2,
+                                                float *part) {
+    constexpr int CH = Chunk<T>::kImages;
+    constexpr int PLANES = BC / CH;
+    for (int al = 0; al < na; ++al) {
+        const double2 cs = g.trig[a0 + al];
+        // detector coordinate of the pixel centre and its gradient (bins per pixel)
+        const double pu = fma(qx, cs.x, qy * cs.y), pv = fma(-qx, cs.y, qy * cs.x);
+        const double den = 1.0 / (g.sd + pv);
+        const double sb = g.sde * pu * den * g.inv_spacing + g.half_d;
+        const double gsx = g.sde * (cs.x * (g.sd + pv) + pu * cs.y) * den * den * g.inv_spacing;
+        const double gsy = g.sde * (cs.y * (g.sd + pv) - pu * cs.x) * den * den * g.inv_spacing;
+        const double hb = fabs(gsx) + fabs(gsy);
+        const int dfirst = (int)ceil(sb - hb * 1.01 - 0.05);
+        int lb = dfirst - wlo_s[al];
+        lb = min(max(lb, 0), W - NBX);              // memory safety; real pixels are inside
+        float wgt[NBX];
+#pragma unroll
+        for (int i = 0; i < NBX; ++i) {
+            const double4 rp = rays_s[al * W + lb + i];
+            const double ex = rp.x - (double)c, ey = rp.y - (double)r;   // F - Q
+            const double kc = -fma(ex, rp.z, ey * rp.w) * is2;           // pixel along the ray
+            const double hk = (fabs(rp.z) + fabs(rp.w)) * is2;
+            const double k0 = floor(kc - hk);
+            float dx = (float)fma(k0 + 1.0, rp.z, ex), dy = (float)fma(k0 + 1.0, rp.w, ey);
+            const float sx = (float)rp.z, sy = (float)rp.w;
+            float w = 0.0f;
+#pragma unroll
+            for (int jj = 0; jj < NK; ++jj) {
+                const float tx = __builtin_amdgcn_fmed3f(1.0f - fabsf(dx), 0.0f, 1.0f);
+                const float ty = __builtin_amdgcn_fmed3f(1.0f - fabsf(dy), 0.0f, 1.0f);
+                w = fmaf(tx, ty, w);
+                dx += sx;
+                dy += sy;
+            }
+            wgt[i] = w;
+        }
+        const uint4 *row = lds + al * W + lb;
+#pragma unroll
+        for (int qq = 0; qq < PLANES; ++qq) {
+#pragma unroll
+            for (int i = 0; i < NBX; ++i) Chunk<T>::fma(wgt[i], row[qq * per_plane + i], part + qq * CH);
+        }
+    }
+}
+
 // Fan beam.  Same tiling as the parallel kernel; every bin has its own ray, so the
 // block also stages the rays (FP64 foot point and step) of its bin window.  Per
 // (pixel, angle) the candidate bins are those within the projected half-width of
 // the pixel's footprint around the projection of its centre (first-order bound
 // plus a margin far larger than the footprint's curvature); per bin, the NK
 // candidate samples around the pixel's position along that ray are evaluated with
-// FP64 anchors and FP32 offsets, exactly as in the parallel kernel.
+// FP64 anchors and FP32 offsets, exactly as in the parallel kernel.  The plan's NB
+// bins cover the worst magnification in the image; per block of angles the tile's
+// own bound (its footprint's smallest distance to the source and largest lateral
+// offset) often needs only 4, and then the 4-bin loop runs.
 template <typename T, int BC, int NB, int NK, class Source>
 __device__ __forceinline__ void bp_tile_fan(const Geom &g, int tile, const ImageSet<T, BC> &imgs,
                                             const Source &src, int W, uint4 *lds) {
     __shared__ int wlo_s[kBpAnglesFan];
+    __shared__ int nb_s[kBpAnglesFan];
     constexpr int CH = Chunk<T>::kImages;
     constexpr int PLANES = BC / CH;
     static_assert(BC % CH == 0, "BC must be a multiple of the images per chunk");
@@ -499,17 +555,25 @@ __device__ __forceinline__ void bp_tile_fan(const Geom &g, int tile, const Image
         const int na = min(kBpAnglesFan, A - a0);
         __syncthreads();
         if (threadIdx.x < na) {
-            // bin window of the tile: projections of the corners of its footprint
+            // bin window of the tile: projections of the corners of its footprint; and
+            // the bins a footprint can need there: |grad s| <= SE/(S+v) sqrt(1 + (u/(S+v))^2)
+            // with v the smallest and |u| the largest over the corners (both linear)
             const double2 cs = g.trig[a0 + threadIdx.x];
-            double lo = 1e30;
+            double lo = 1e30, vmin = 1e30, umax = 0.0;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const double px = tx0 - 1.0 + ((k & 1) ? kBpTile + 1.0 : 0.0) - g.cn;
                 const double py = ty0 - 1.0 + ((k & 2) ? kBpTile + 1.0 : 0.0) - g.cn;
                 const double pu = fma(px, cs.x, py * cs.y), pv = fma(-px, cs.y, py * cs.x);
                 lo = fmin(lo, g.sde * pu / (g.sd + pv) * g.inv_spacing + g.half_d);
+                vmin = fmin(vmin, pv);
+                umax = fmax(umax, fabs(pu));
             }
             wlo_s[threadIdx.x] = (int)floor(lo) - 1;
+            const double near = g.sd + vmin, ratio = umax / near;
+            const double grad = g.sde / near * sqrt(1.0 + ratio * ratio);
+            const double span = 2.0 * 1.4142135623730951 * grad * g.inv_spacing * 1.01 + 0.1;
+            nb_s[threadIdx.x] = near > 0.0 ? (int)floor(span) + 1 : NB;
         }
         __syncthreads();
         src.stage(lds, a0, na, W, wlo_s, per_plane);
@@ -521,6 +585,8 @@ __device__ __forceinline__ void bp_tile_fan(const Geom &g, int tile, const Image
             rays_s[al * W + j] = inside ? g.rays[(size_t)(a0 + al) * D + d]
                                         : make_double4(-1e9, -1e9, 0.0, 0.0);
         }
+        int nb_block = 0;
+        for (int al = 0; al < na; ++al) nb_block = max(nb_block, nb_s[al]);
         __syncthreads();
 
         // two-level summation as in the parallel kernel (single level at 64 images)
@@ -531,46 +597,12 @@ __device__ __forceinline__ void bp_tile_fan(const Geom &g, int tile, const Image
 #pragma unroll
             for (int i = 0; i < BC; ++i) part[i] = 0.0f;
         }
-        for (int al = 0; al < na; ++al) {
-            const double2 cs = g.trig[a0 + al];
-            // detector coordinate of the pixel centre and its gradient (bins per pixel)
-            const double pu = fma(qx, cs.x, qy * cs.y), pv = fma(-qx, cs.y, qy * cs.x);
-            const double den = 1.0 / (g.sd + pv);
-            const double sb = g.sde * pu * den * g.inv_spacing + g.half_d;
-            const double gsx = g.sde * (cs.x * (g.sd + pv) + pu * cs.y) * den * den * g.inv_spacing;
-            const double gsy = g.sde * (cs.y * (g.sd + pv) - pu * cs.x) * den * den * g.inv_spacing;
-            const double hb = fabs(gsx) + fabs(gsy);
-            const int dfirst = (int)ceil(sb - hb * 1.01 - 0.05);
-            int lb = dfirst - wlo_s[al];
-            lb = min(max(lb, 0), W - NB);               // memory safety; real pixels are inside
-            float wgt[NB];
-#pragma unroll
-            for (int i = 0; i < NB; ++i) {
-                const double4 rp = rays_s[al * W + lb + i];
-                const double ex = rp.x - (double)c, ey = rp.y - (double)r;   // F - Q
-                const double kc = -fma(ex, rp.z, ey * rp.w) * is2;           // pixel along the ray
-                const double hk = (fabs(rp.z) + fabs(rp.w)) * is2;
-                const double k0 = floor(kc - hk);
-                float dx = (float)fma(k0 + 1.0, rp.z, ex), dy = (float)fma(k0 + 1.0, rp.w, ey);
-                const float sx = (float)rp.z, sy = (float)rp.w;
-                float w = 0.0f;
-#pragma unroll
-                for (int jj = 0; jj < NK; ++jj) {
-                    const float tx = __builtin_amdgcn_fmed3f(1.0f - fabsf(dx), 0.0f, 1.0f);
-                    const float ty = __builtin_amdgcn_fmed3f(1.0f - fabsf(dy), 0.0f, 1.0f);
-                    w = fmaf(tx, ty, w);
-                    dx += sx;
-                    dy += sy;
-                }
-                wgt[i] = w;
-            }
-            const uint4 *row = lds + al * W + lb;
-#pragma unroll
-            for (int qq = 0; qq < PLANES; ++qq) {
-#pragma unroll
-                for (int i = 0; i < NB; ++i) Chunk<T>::fma(wgt[i], row[qq * per_plane + i], part + qq * CH);
-            }
-        }
+        if (NB > 4 && nb_block <= 4)
+            fan_angle_block<T, BC, 4, NK>(g, a0, na, W, wlo_s, rays_s, lds, per_plane, qx, qy, c, r,
+                                          is2, part);
+        else
+            fan_angle_block<T, BC, NB, NK>(g, a0, na, W, wlo_s, rays_s, lds, per_plane, qx, qy, c, r,
+                                           is2, part);
         if (kTwoLevel) {
 #pragma unroll
             for (int i = 0; i < BC; ++i) acc[i] += part[i];
