@@ -497,8 +497,7 @@ static int build_batch_table(const std::vector<Plan *> &plans, const radon_job_t
         bj.push_back(j);
         for (size_t k = 0; k < v.size();) {
             const size_t left = v.size() - k;
-            const int cap = direction == 0 ? kBatchFwdImages
-                                           : (left >= 14 ? kBatchBpWide : kBatchBpNarrow);
+            const int cap = direction == 0 ? ch : (left >= 14 ? kBatchBpWide : kBatchBpNarrow);
             const int cnt = (int)std::min<size_t>(left, (size_t)cap);
             ImageGroup gr{};
             for (int e = 0; e < kBatchBpWide; ++e) {
@@ -512,7 +511,7 @@ static int build_batch_table(const std::vector<Plan *> &plans, const radon_job_t
             groups.push_back(gr);
             k += cnt;
             if (direction == 0) {
-                lds = std::max(lds, (size_t)(kBatchFwdImages / ch) * (kSlabH + 3) * j.tile_t * sizeof(uint4));
+                lds = std::max(lds, (size_t)(kSlabH + 3) * j.tile_t * sizeof(uint4));
                 for (size_t it = 0; it < p->fwd_items_host.size(); ++it) {
                     const FwdItem &f = p->fwd_items_host[it];
                     units.push_back({{jid, (int)it, gid, 0}, (double)(f.nslab + 1) * f.na * f.nd});

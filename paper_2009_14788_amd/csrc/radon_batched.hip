@@ -2,7 +2,8 @@
 // extended to jobs of different image sizes and angle sets).
 //
 // The host groups the images of all jobs that share a geometry into image groups
-// (8 images for the forward; 8 or 32 for the backprojection) and flattens them into
+// (one 16-byte chunk for the forward: 4 FP32 or 8 16-bit images; 8 or 32 for the
+// backprojection) and flattens them into
 // work units -- forward: (geometry, plan item, image group); backprojection:
 // (geometry, pixel tile, image group) -- sorted longest first.
 // A grid sized to the resident capacity of the GPU pulls units from a device
@@ -51,9 +52,12 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_batched(const BatchJob *__res
         const WorkUnit u = work[w];
         const BatchJob &j = jobs[u.job];
         const FwdItem it = j.items[u.unit];
-        const ImageSet<T, kBatchFwdImages> imgs = group_images<T, kBatchFwdImages>(groups[u.group]);
-        const PointerSource<T, kBatchFwdImages> src{imgs.in, j.g.n};
-        fwd_item<T, kBatchFwdImages>(j.g, it, j.ranges, imgs, src, j.tile_t, lds);
+        // one 16-byte chunk per lane (4 FP32 or 8 16-bit images): one LDS plane per
+        // slab keeps several blocks resident per CU even for the widest job's tile
+        constexpr int BC = Chunk<T>::kImages;
+        const ImageSet<T, BC> imgs = group_images<T, BC>(groups[u.group]);
+        const PointerSource<T, BC> src{imgs.in, j.g.n};
+        fwd_item<T, BC>(j.g, it, j.ranges, imgs, src, j.tile_t, lds);
     }
 }
 

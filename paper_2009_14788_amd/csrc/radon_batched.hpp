@@ -8,7 +8,6 @@
 
 namespace radon {
 
-constexpr int kBatchFwdImages = 8;     // images per lane in forward units
 constexpr int kBatchBpNarrow = 8;      // images per lane in small backprojection units
 constexpr int kBatchBpWide = 32;       // images per lane in large backprojection units
 
