@@ -69,9 +69,16 @@ __global__ __launch_bounds__(256) void fwd_direct(Geom g, const T *__restrict__ 
 }
 
 // ------------------------------------------------------------------ tiled variant
+// Waves per SIMD the tiled kernels are compiled for: the FP32 8-image kernel is held
+// to <= 80 registers (it needs 68 then, against 84 unbounded), so that it is LDS, not
+// registers, that caps it, at three blocks (6 waves per SIMD) for items up to ~120
+// columns wide; the 16-bit 16-image kernels would spill under that bound.
+template <typename T, int BC>
+constexpr int kFwdMinWaves = (sizeof(T) == 4 && BC == 8) ? 6 : 1;
+
 // One block = one work item of the plan x BC images (blockIdx.y selects the images).
 template <typename T, int BC>
-__global__ __launch_bounds__(kFwdThreads) void fwd_tiled(Geom g, FwdWork work, const T *__restrict__ x,
+__global__ __launch_bounds__(kFwdThreads, (kFwdMinWaves<T, BC>)) void fwd_tiled(Geom g, FwdWork work, const T *__restrict__ x,
                                                  T *__restrict__ y, int batch, float scale_dt,
                                                  int tile_t) {
     extern __shared__ uint4 lds[];
@@ -85,7 +92,7 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_tiled(Geom g, FwdWork work, c
 // Same, staging from the interleaved, zero-bordered copies of the batch: xi holds
 // the row-major copy [groups][N+4][N+4] followed by the transposed copy.
 template <typename T, int BC>
-__global__ __launch_bounds__(kFwdThreads) void fwd_tiled_il(Geom g, FwdWork work, const uint4 *__restrict__ xi,
+__global__ __launch_bounds__(kFwdThreads, (kFwdMinWaves<T, BC>)) void fwd_tiled_il(Geom g, FwdWork work, const uint4 *__restrict__ xi,
                                                     T *__restrict__ y, int batch, float scale_dt,
                                                     int tile_t, int groups) {
     extern __shared__ uint4 lds[];

@@ -37,10 +37,12 @@ struct FwdItem {
 };
 
 #ifndef RADON_SLAB_H
-#define RADON_SLAB_H 12
+#define RADON_SLAB_H 11
 #endif
-constexpr int kSlabH = RADON_SLAB_H;   // pixel rows (columns) per slab (a sweep on the
-                                       // MI355X: 12 beat 8, 10 and 16)
+// pixel rows (columns) per slab.  11 keeps the FP32 8-image slab of a 512^2 item
+// under 53 KB, so three 512-thread blocks share a compute unit's 160 KB of LDS;
+// on the MI355X that beat 12 (two blocks), 10, 8 and 7 (with four blocks)
+constexpr int kSlabH = RADON_SLAB_H;
 #ifndef RADON_FWD_WAVES
 #define RADON_FWD_WAVES 8
 #endif
