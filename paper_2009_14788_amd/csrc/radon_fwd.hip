@@ -91,8 +91,10 @@ __global__ __launch_bounds__(kFwdThreads, (kFwdMinWaves<T, BC>)) void fwd_tiled(
 }
 
 // Same, staging from the interleaved, zero-bordered copies of the batch: xi holds
-// the row-major copy [groups][N+4][N+4] followed by the transposed copy.
-template <typename T, int BC>
+// the row-major copy [groups][N+4][N+4] followed by the transposed copy.  PITCH > 0:
+// LDS rows of that many chunks (the plan's windows are at most that wide), fixed at
+// compile time so the tap offsets are immediates.
+template <typename T, int BC, int PITCH>
 __global__ __launch_bounds__(kFwdThreads, (kFwdMinWaves<T, BC>)) void fwd_tiled_il(Geom g, FwdWork work, const uint4 *__restrict__ xi,
                                                     T *__restrict__ y, int batch, float scale_dt,
                                                     int tile_t, int groups) {
@@ -106,7 +108,7 @@ __global__ __launch_bounds__(kFwdThreads, (kFwdMinWaves<T, BC>)) void fwd_tiled_
     const int plane = (g.n + 4) * (g.n + 4);
     const uint4 *first = xi + (size_t)(b0 / CH) * plane;
     const InterleavedSource<T, BC> src{first, first + (size_t)groups * plane, g.n, plane};
-    fwd_item<T, BC>(g, it, work.ranges, imgs, src, tile_t, lds);
+    fwd_item<T, BC, InterleavedSource<T, BC>, PITCH>(g, it, work.ranges, imgs, src, tile_t, lds);
 }
 
 // Interleave a batch x[B][N][N] into chunks of CH images with a zero border of 2
@@ -170,6 +172,7 @@ static hipError_t launch_fwd_tiled(const Geom &g, const FwdWork &work, const voi
     constexpr int CH = Chunk<T>::kImages;
     constexpr int PLANES = BC / CH;
     const size_t lds = (size_t)PLANES * (kSlabH + 3) * work.tile_t * sizeof(uint4);
+    const size_t lds_fixed = (size_t)PLANES * (kSlabH + 3) * kFwdPitchFixed * sizeof(uint4);
     dim3 grid(work.n_items, (batch + BC - 1) / BC);
     const int dt = sizeof(T) == 4 ? F32 : F16;
     if (ws && stage && ws_bytes >= interleaved_bytes(g.n, batch, dt)) {
@@ -180,8 +183,13 @@ static hipError_t launch_fwd_tiled(const Geom &g, const FwdWork &work, const voi
                            (const T *)x, (uint4 *)ws, g.n, batch, groups);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((fwd_tiled_il<T, BC>), grid, dim3(kFwdThreads), lds, s, g, work,
-                           (const uint4 *)ws, (T *)y, batch, scale_dt, work.tile_t, groups);
+        if (work.tile_t <= kFwdPitchFixed)
+            hipLaunchKernelGGL((fwd_tiled_il<T, BC, kFwdPitchFixed>), grid, dim3(kFwdThreads),
+                               lds_fixed, s, g, work, (const uint4 *)ws, (T *)y, batch, scale_dt,
+                               kFwdPitchFixed, groups);
+        else
+            hipLaunchKernelGGL((fwd_tiled_il<T, BC, 0>), grid, dim3(kFwdThreads), lds, s, g, work,
+                               (const uint4 *)ws, (T *)y, batch, scale_dt, work.tile_t, groups);
     } else {
         hipLaunchKernelGGL((fwd_tiled<T, BC>), grid, dim3(kFwdThreads), lds, s, g, work, (const T *)x,
                            (T *)y, batch, scale_dt, work.tile_t);

@@ -57,6 +57,11 @@ constexpr int kFwdQAngles = 16 / kFwdQBins;       // angles per quarter wave
 #define RADON_FWD_PITCH_MOD 8
 #endif
 constexpr int kFwdPitchMod = RADON_FWD_PITCH_MOD; // LDS row pitch = 16k + this (chunks)
+// Compile-time LDS row pitch (chunks, 16k + kFwdPitchMod) of the interleaved forward
+// for plans whose windows all fit it (512^2 parallel plans need 118 columns); two
+// planes of it leave room for three blocks in 160 KB.
+constexpr int kFwdPitchFixed = 120;
+static_assert(kFwdPitchFixed % 16 == kFwdPitchMod, "fixed pitch keeps the bank offset");
 constexpr int kFwdLanes = 64;      // bins per forward item
 constexpr int kTileTMax = 192;     // largest transverse extent of a staged slab
 

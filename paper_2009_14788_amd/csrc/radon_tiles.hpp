@@ -144,13 +144,19 @@ struct InterleavedSource {
 // The samples of one lane's ray inside one slab: `cnt` samples at frame offsets
 // (fxa + j sx, fya + j sy) >= 1 from the lane's anchor chunk.  SWAP: the frame is the
 // transposed image; the two middle taps are then taken in the image frame's order,
-// so both frames give bitwise identical sums.
-template <typename T, int BC, bool SWAP>
+// so both frames give bitwise identical sums.  PITCH > 0: the row pitch is that
+// compile-time number of chunks (planes of kSlabH + 3 rows), so every tap offset is an
+// immediate of the LDS read instead of a per-sample address add.
+template <typename T, int BC, bool SWAP, int PITCH>
 __device__ __forceinline__ void slab_samples(const uint4 *lane_lds, int pitch, int plane_chunks,
                                              double fxa, double fya, double sx, double sy, int cnt,
                                              float *part) {
     constexpr int CH = Chunk<T>::kImages;
     constexpr int PLANES = BC / CH;
+    if (PITCH > 0) {
+        pitch = PITCH;
+        plane_chunks = (kSlabH + 3) * PITCH;
+    }
     // byte addressing: one multiply-add and one shift-add per sample, the tap
     // offsets (+16 bytes, +pitch, +plane) are loop invariants
     const char *base = reinterpret_cast<const char *>(lane_lds);
@@ -194,10 +200,13 @@ __device__ __forceinline__ void slab_samples(const uint4 *lane_lds, int pitch, i
 // FP64 boundary crossings (consistent across slabs); sample positions are FP64
 // offsets from the lane's first cell in the slab and only the bilinear fractions
 // drop to FP32, so weights are accurate to FP32 rounding anywhere in the image.
-template <typename T, int BC, class Source>
+// PITCH > 0 (march-frame sources only): tile_t is that compile-time pitch.
+template <typename T, int BC, class Source, int PITCH = 0>
 __device__ __forceinline__ void fwd_item(const Geom &g, const FwdItem &it, const int2 *__restrict__ ranges,
                                          const ImageSet<T, BC> &imgs, const Source &src, int tile_t,
                                          uint4 *lds) {
+    static_assert(PITCH == 0 || Source::kMarchFrame, "a fixed pitch needs the march frame");
+    if (PITCH > 0) tile_t = PITCH;
     const int plane_chunks = (kSlabH + 3) * tile_t;
 
     // rays of the item -> lanes: each 16-lane quarter of a wave takes kFwdQBins
@@ -265,11 +274,12 @@ __device__ __forceinline__ void fwd_item(const Geom &g, const FwdItem &it, const
 #pragma unroll
         for (int i = 0; i < BC; ++i) part[i] = 0.0f;
         if (swap)
-            slab_samples<T, BC, Source::kMarchFrame>(lane_lds, pitch, plane_chunks, px64 - bx,
-                                                     py64 - by, r.z, r.w, je - jb, part);
+            slab_samples<T, BC, Source::kMarchFrame, PITCH>(lane_lds, pitch, plane_chunks,
+                                                            px64 - bx, py64 - by, r.z, r.w,
+                                                            je - jb, part);
         else
-            slab_samples<T, BC, false>(lane_lds, pitch, plane_chunks, px64 - bx, py64 - by, r.z,
-                                       r.w, je - jb, part);
+            slab_samples<T, BC, false, PITCH>(lane_lds, pitch, plane_chunks, px64 - bx, py64 - by,
+                                              r.z, r.w, je - jb, part);
 #pragma unroll
         for (int i = 0; i < BC; ++i) acc[i] += part[i];
     }
