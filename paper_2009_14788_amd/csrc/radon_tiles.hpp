@@ -142,7 +142,10 @@ struct InterleavedSource {
 };
 
 // The samples of one lane's ray inside one slab: `cnt` samples at frame offsets
-// (fxa + j sx, fya + j sy) >= 1 from the lane's anchor chunk.  SWAP: the frame is the
+// (fxa + j sx, fya + j sy) >= 1 from the lane's anchor chunk, stepped in FP32: the
+// offsets stay below ~20 pixels, so a position carries at most ~2e-6 pixel of
+// rounding (FP32 image coordinates would carry 3e-5 at the edge of a 512^2 image),
+// and the two FP64 conversions per sample are saved.  SWAP: the frame is the
 // transposed image; the two middle taps are then taken in the image frame's order,
 // so both frames give bitwise identical sums.  PITCH > 0: the row pitch is that
 // compile-time number of chunks (planes of kSlabH + 3 rows), so every tap offset is an
@@ -161,11 +164,12 @@ __device__ __forceinline__ void slab_samples(const uint4 *lane_lds, int pitch, i
     // offsets (+16 bytes, +pitch, +plane) are loop invariants
     const char *base = reinterpret_cast<const char *>(lane_lds);
     const unsigned row_bytes = (unsigned)pitch * 16u, plane_bytes = (unsigned)plane_chunks * 16u;
-    const double end = (double)cnt;
-    for (double jd = 0.0; jd < end; jd += 1.0) {
-        const double px = fma(jd, sx, fxa), py = fma(jd, sy, fya);
-        const int cx = (int)px, cy = (int)py;                       // px, py >= 1
-        const float fx = (float)__builtin_amdgcn_fract(px), fy = (float)__builtin_amdgcn_fract(py);
+    const float end = (float)cnt, fxa32 = (float)fxa, fya32 = (float)fya;
+    const float sx32 = (float)sx, sy32 = (float)sy;
+    for (float jf = 0.0f; jf < end; jf += 1.0f) {
+        const float px = fmaf(jf, sx32, fxa32), py = fmaf(jf, sy32, fya32);
+        const int cx = (int)px, cy = (int)py;                       // px, py >= 1 - 1e-6
+        const float fx = __builtin_amdgcn_fractf(px), fy = __builtin_amdgcn_fractf(py);
         const float gx = 1.0f - fx, gy = 1.0f - fy;
         const float w00 = __fmul_rn(gx, gy), w01 = __fmul_rn(fx, gy);
         const float w10 = __fmul_rn(gx, fy), w11 = __fmul_rn(fx, fy);
@@ -197,9 +201,9 @@ __device__ __forceinline__ void slab_samples(const uint4 *lane_lds, int pitch, i
 // then every lane walks its ray's samples inside the slab.  A sample costs one
 // address and weight computation shared by the BC images and four 16-byte LDS
 // reads per plane.  The split of each ray's samples between slabs is fixed by
-// FP64 boundary crossings (consistent across slabs); sample positions are FP64
-// offsets from the lane's first cell in the slab and only the bilinear fractions
-// drop to FP32, so weights are accurate to FP32 rounding anywhere in the image.
+// FP64 boundary crossings (consistent across slabs); each lane's anchor cell in the
+// slab is found in FP64 and its samples are FP32 offsets from it, so the weights'
+// accuracy does not depend on where in the image the slab lies.
 // PITCH > 0 (march-frame sources only): tile_t is that compile-time pitch.
 template <typename T, int BC, class Source, int PITCH = 0>
 __device__ __forceinline__ void fwd_item(const Geom &g, const FwdItem &it, const int2 *__restrict__ ranges,
@@ -260,8 +264,8 @@ __device__ __forceinline__ void fwd_item(const Geom &g, const FwdItem &it, const
         const int je = min(jhi + 1, (int)ceil(((double)(m_lo + kSlabH) - om) * inv_sm));
         if (jb >= je) continue;
         // anchor: one cell below the lowest cell over the slab's samples, so that every
-        // sample offset is >= 1 (truncation is floor even after rounding) and small
-        // (FP64; only the fraction drops to FP32)
+        // sample offset is >= 1 in FP64 (>= 1 - 2e-6 once stepped in FP32, so
+        // truncation is still floor) and small
         const double px64 = fma((double)jb, r.z, r.x) - (double)ox0;
         const double py64 = fma((double)jb, r.w, r.y) - (double)oy0;
         const double lx64 = fma((double)(je - 1 - jb), r.z, px64);

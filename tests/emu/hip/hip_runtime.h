@@ -58,6 +58,8 @@ inline unsigned __float_as_uint(float f) { unsigned u; std::memcpy(&u, &f, 4); r
 inline double emu_fract(double x) { return x - std::floor(x); }
 inline float emu_med3(float a, float b, float c) { return std::fmax(std::fmin(a, b), std::fmin(std::fmax(a, b), c)); }
 #define __builtin_amdgcn_fract(x) emu_fract(x)
+inline float emu_fractf(float x) { return x - std::floor(x); }
+#define __builtin_amdgcn_fractf(x) emu_fractf(x)
 #define __builtin_amdgcn_fmed3f(a, b, c) emu_med3(a, b, c)
 #define __builtin_amdgcn_readfirstlane(x) (x)
 template <class T> inline T atomicAdd(T *p, T v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
