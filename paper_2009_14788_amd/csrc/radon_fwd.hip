@@ -72,8 +72,8 @@ __global__ __launch_bounds__(256) void fwd_direct(Geom g, const T *__restrict__ 
 // Waves per SIMD the tiled kernels are compiled for: two-plane kernels (FP32 with 8
 // images, 16-bit with 16) are held to <= 80 registers, so that LDS, not registers,
 // caps them, at three blocks (6 waves per SIMD) for items up to ~120 columns wide.
-// The FP32 kernel needs 68 registers then (84 unbounded); the 16-bit ones spill one
-// (FP16) or three (BF16) registers and still run 9-12% faster than at two blocks.
+// The FP32 kernel needs 66 registers then; the BF16 one spills one or two registers
+// and still runs 12% faster than at two blocks.
 template <typename T, int BC>
 constexpr int kFwdMinWaves = (sizeof(T) == 2 || BC == 8) ? 6 : 1;
 
