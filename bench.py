@@ -26,6 +26,7 @@ METRIC = "fwd+backproj projections/s & rays/s, 512², 720 angles, batch 128; HBM
 PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak
 PEAK_HBM_GBS = 8000.0         # MI355X HBM3E
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "hbm_traffic_batch128_512.md")
+COUNTER_RECORD = os.path.join(ROOT, "profiles", "cache_hit_rates_batch128_512_f32.md")
 
 
 # the sources that define the forward and backprojection kernels, their launches and
@@ -46,22 +47,39 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
+def _record_fields(path, tag):
+    """The "<direction>:<launch shape>=<value>" fields of a committed counter record,
+    or None when there is no record or the kernel sources changed since the counters
+    were taken."""
+    import re
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    m = re.search(tag + r" sources_sha256=(\w+) (.*?)-->", text)
+    if not m or m.group(1) != kernel_sources_sha256():
+        return None
+    return dict(kv.split("=", 1) for kv in m.group(2).split())
+
+
 def recorded_traffic(direction, shape):
     """HBM bytes per launch of one direction and launch shape from the committed
     counter record, or None when there is no record, the shape was not recorded, or
     the kernel sources changed since the counters were taken."""
-    import re
-    try:
-        text = open(TRAFFIC_RECORD).read()
-    except OSError:
-        return None
-    m = re.search(r"traffic-record sources_sha256=(\w+) (.*?)-->", text)
-    if not m or m.group(1) != kernel_sources_sha256():
-        return None
-    # one "<direction>:<launch shape>=<bytes>" entry per recorded shape
-    fields = dict(kv.split("=", 1) for kv in m.group(2).split())
-    v = fields.get(f"{direction}:{shape}")
+    fields = _record_fields(TRAFFIC_RECORD, "traffic-record")
+    v = (fields or {}).get(f"{direction}:{shape}")
     return int(v) if v is not None else None
+
+
+def recorded_cache_counters(direction, shape):
+    """L2 and vector-L1 hit rates and the LDS bank-conflict fraction of one direction's
+    main kernel at one launch shape, from the committed counter record; None under the
+    same conditions as the traffic record."""
+    fields = _record_fields(COUNTER_RECORD, "counter-record")
+    v = (fields or {}).get(f"{direction}:{shape}")
+    if v is None:
+        return None
+    return {k: float(x) for k, x in (kv.split(":") for kv in v.split(","))}
 
 
 def support_samples(n, angles, det_count, spacing, step, beam="parallel", S=0.0, E=0.0):
@@ -229,6 +247,10 @@ def main():
 
     directions = {"forward": direction(fwd_ms, 4.0 * samples, 16.0 * samples),
                   "backprojection": direction(bp_ms, 3.0 * triples, 12.0 * triples)}
+    for d in directions:
+        di = op.plan_info(torch.float32, B)[d]
+        directions[d]["counters"] = recorded_cache_counters(
+            d, f"{di['variant']},{di['images']},{di['angles']},{di['staging']}")
     peaks = {"fma_per_s": fma_peak, "lds_bytes_per_s": lds_peak,
              "method": "radon_measure_peaks: v_fmac_f32 chains (packed FP32 off) and conflict-free "
                        "ds_read_b128 streams on this GPU, best of 3 runs"}
