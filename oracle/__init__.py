@@ -54,6 +54,8 @@ def _load():
     lib.oracle_backproject_pixels.restype = ctypes.c_int
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_num_threads.restype = None
     _lib = lib
     return lib
 
@@ -110,6 +112,8 @@ def backproject(g: Geometry, y, scale=1.0):
     yb = y.reshape(-1, g.n_angles, g.det_count)
     x = np.empty((yb.shape[0], g.n, g.n), dtype=np.float64)
     rc = lib.oracle_backproject(*g._args(), _dptr(yb), yb.shape[0], float(scale), _dptr(x))
+    if rc == -2:
+        raise MemoryError("oracle_backproject: accumulators could not be allocated")
     if rc != 0:
         raise ValueError("oracle_backproject: invalid geometry")
     return x[0] if squeeze else x
@@ -156,3 +160,8 @@ def backproject_pixels(g: Geometry, y, idx, scale=1.0):
 
 def num_threads():
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n):
+    """Threads the oracle's OpenMP loops use from now on (for timing only)."""
+    _load().oracle_set_num_threads(int(n))

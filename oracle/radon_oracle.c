@@ -173,40 +173,70 @@ int oracle_forward(GEOM_ARGS, const double *x, int batch, double scale, double *
     return 0;
 }
 
-/* Backprojection y[B][A][D] -> x[B][N][N] in scatter form: every sample of
- * every ray hands its value, times its four bilinear weights, to the pixels
- * it was interpolated from.  This is the literal transpose of oracle_forward. */
-int oracle_backproject(GEOM_ARGS, const double *y, int batch, double scale, double *x)
+/* Scatter of the rays of angles [a0, a1) of one sinogram into acc[N][N]: every
+ * sample of every ray hands its value, times its four bilinear weights, to the
+ * pixels it was interpolated from. */
+static void scatter_angles(const oracle_geom *g, const double *sino, double scale, int a0,
+                           int a1, double *acc)
 {
-    MAKE_GEOM;
-    if (check_geom(&g)) return -1;
-    double h = 0.5 * (double)(g.n - 1);
-    memset(x, 0, sizeof(double) * (size_t)batch * g.n * g.n);
-#pragma omp parallel for schedule(dynamic, 1)
-    for (long b = 0; b < batch; ++b) {
-        double *img = x + (size_t)b * g.n * g.n;
-        for (int a = 0; a < g.n_angles; ++a) {
-            for (int d = 0; d < g.det_count; ++d) {
-                double val = scale * g.step * y[((size_t)b * g.n_angles + a) * g.det_count + d];
-                oracle_ray ry = ray_of(&g, a, d);
-                long klo, khi;
-                k_range(&g, &ry, &klo, &khi);
-                for (long k = klo; k <= khi; ++k) {
-                    double t = (double)k * g.step;
-                    double cx = ry.fx + t * ry.wx + h, cy = ry.fy + t * ry.wy + h;
-                    int c0 = (int)floor(cx), r0 = (int)floor(cy);
-                    for (int r = r0; r <= r0 + 1; ++r) {
-                        if (r < 0 || r >= g.n) continue;
-                        double wy = tent(cy - (double)r);
-                        for (int c = c0; c <= c0 + 1; ++c) {
-                            if (c < 0 || c >= g.n) continue;
-                            img[(size_t)r * g.n + c] += val * tent(cx - (double)c) * wy;
-                        }
+    double h = 0.5 * (double)(g->n - 1);
+    for (int a = a0; a < a1; ++a) {
+        for (int d = 0; d < g->det_count; ++d) {
+            double val = scale * g->step * sino[(size_t)a * g->det_count + d];
+            oracle_ray ry = ray_of(g, a, d);
+            long klo, khi;
+            k_range(g, &ry, &klo, &khi);
+            for (long k = klo; k <= khi; ++k) {
+                double t = (double)k * g->step;
+                double cx = ry.fx + t * ry.wx + h, cy = ry.fy + t * ry.wy + h;
+                int c0 = (int)floor(cx), r0 = (int)floor(cy);
+                for (int r = r0; r <= r0 + 1; ++r) {
+                    if (r < 0 || r >= g->n) continue;
+                    double wy = tent(cy - (double)r);
+                    for (int c = c0; c <= c0 + 1; ++c) {
+                        if (c < 0 || c >= g->n) continue;
+                        acc[(size_t)r * g->n + c] += val * tent(cx - (double)c) * wy;
                     }
                 }
             }
         }
     }
+}
+
+/* Backprojection y[B][A][D] -> x[B][N][N] in scatter form, the literal transpose
+ * of oracle_forward.  The angles of each image are cut into a fixed number of
+ * contiguous blocks (independent of the thread count); every block scatters into
+ * its own accumulator and the accumulators are added in block order, so the
+ * result is the same on any number of threads.  Returns -2 if the accumulators
+ * cannot be allocated. */
+int oracle_backproject(GEOM_ARGS, const double *y, int batch, double scale, double *x)
+{
+    MAKE_GEOM;
+    if (check_geom(&g)) return -1;
+    const size_t npix = (size_t)g.n * g.n;
+    int nblk = g.n_angles < 32 ? g.n_angles : 32;
+    const size_t cap = ((size_t)512 << 20) / (npix * sizeof(double));
+    if ((size_t)nblk > cap) nblk = cap > 0 ? (int)cap : 1;
+    double *part = (double *)malloc((size_t)nblk * npix * sizeof(double));
+    if (!part) return -2;
+    for (long b = 0; b < batch; ++b) {
+        const double *sino = y + (size_t)b * g.n_angles * g.det_count;
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int k = 0; k < nblk; ++k) {
+            double *acc = part + (size_t)k * npix;
+            memset(acc, 0, npix * sizeof(double));
+            scatter_angles(&g, sino, scale, (int)((long)k * g.n_angles / nblk),
+                           (int)((long)(k + 1) * g.n_angles / nblk), acc);
+        }
+        double *img = x + (size_t)b * npix;
+#pragma omp parallel for schedule(static)
+        for (long i = 0; i < (long)npix; ++i) {
+            double v = 0.0;
+            for (int k = 0; k < nblk; ++k) v += part[(size_t)k * npix + i];
+            img[i] = v;
+        }
+    }
+    free(part);
     return 0;
 }
 
@@ -296,6 +326,16 @@ int oracle_backproject_pixels(GEOM_ARGS, const double *y, double scale, long n_i
         out[i] = scale * acc;
     }
     return 0;
+}
+
+/* Threads the OpenMP loops use from now on (n >= 1); for timing only. */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
 }
 
 int oracle_num_threads(void)
