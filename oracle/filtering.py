@@ -21,9 +21,14 @@ Readings (the paper names the filters but gives no formulas):
   * the windows multiply the ramp's transform at the normalised frequency f in
     [-1/2, 1/2) (numpy's fftfreq): Shepp-Logan sin(pi f)/(pi f), cosine cos(pi f),
     Hamming 0.54 + 0.46 cos(2 pi f), Hann 0.5 + 0.5 cos(2 pi f), Ram-Lak 1;
-  * filter_sinogram returns (pi / A) * Q for A angles, so that the exact transpose of
-    the projector applied to it reconstructs the image when the angles cover [0, pi)
-    uniformly (the paper's example backprojects the filtered sinogram directly).
+  * filter_sinogram returns (pi / A) * tau * Q for A angles and bin spacing tau, so that
+    the exact transpose of the projector applied to it reconstructs the image when the
+    angles cover [0, pi) uniformly (the paper's example backprojects the filtered
+    sinogram directly).  The transpose gathers the rays through a pixel at a density
+    of 1/tau bins per unit of detector length (its weights of one angle sum to 1/tau
+    over the detector for a smooth projection), which is the 1/tau that Q's kernel
+    carries, so the result no longer depends on tau:
+    (pi / A) * tau * Q = (pi / A) * sum_k h_1(n - k) p(k tau), h_1 = h at tau = 1.
 """
 import numpy as np
 
@@ -76,20 +81,20 @@ def frequency_response(name, det_count):
     return np.real(np.fft.fft(ramp_impulse(L))) * window(name, L)
 
 
-def filter_sinogram(y, name="ram-lak", det_spacing=1.0):
-    """(pi / A) * Q for every projection of y[..., A, D] (FP64): zero-pad each row to
-    L, multiply its transform by H, transform back, keep the first D samples, and
-    apply the 1/tau of the sampled kernel (tau = det_spacing)."""
+def filter_sinogram(y, name="ram-lak"):
+    """(pi / A) * tau * Q for every projection of y[..., A, D] (FP64): zero-pad each row
+    to L, multiply its transform by H (the kernel at tau = 1), transform back, keep the
+    first D samples, times pi / A.  Independent of the bin spacing tau."""
     y = np.asarray(y, dtype=np.float64)
     A, D = y.shape[-2], y.shape[-1]
     L = padded_length(D)
     H = frequency_response(name, D)
     P = np.fft.fft(y, n=L, axis=-1)
     Q = np.real(np.fft.ifft(P * H, axis=-1))[..., :D]
-    return Q * (np.pi / A) / det_spacing
+    return Q * (np.pi / A)
 
 
-def filter_sinogram_direct(y, name="ram-lak", det_spacing=1.0):
+def filter_sinogram_direct(y, name="ram-lak"):
     """The same filter as a plain truncated circular convolution with the spatial
     kernel g = inverse transform of H (only for small cases: O(D^2) per row)."""
     y = np.asarray(y, dtype=np.float64)
@@ -98,4 +103,4 @@ def filter_sinogram_direct(y, name="ram-lak", det_spacing=1.0):
     g = np.real(np.fft.ifft(frequency_response(name, D)))
     n = np.arange(D)
     T = g[(n[:, None] - n[None, :]) % L]          # Q[n] = sum_k g[(n - k) mod L] p[k]
-    return (y @ T.T) * (np.pi / A) / det_spacing
+    return (y @ T.T) * (np.pi / A)

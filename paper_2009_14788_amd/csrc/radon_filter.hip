@@ -1,7 +1,7 @@
 // Sinogram filter of filtered backprojection (TorchRadon Sec. 3.1.3): every
 // projection row is zero-padded to L = 2^m >= 2D, transformed, multiplied by the
 // real, even frequency response H of the chosen filter, transformed back, and the
-// first D samples are kept, scaled by pi / (A * spacing).  H is the transform of the
+// first D samples are kept, scaled by pi / A.  H is the transform of the
 // sampled impulse response of the band-limited ramp (Kak & Slaney, ch. 3, eq. 61)
 // times the filter's window; it is formed on the host in FP64.
 //

@@ -157,9 +157,9 @@ class _Base:
         """Filter of filtered backprojection (TorchRadon Sec. 3.1.3): each projection is
         filtered in the frequency domain by the Kak & Slaney band-limited ramp (ch. 3
         eq. 61) times the window of `filter_name` ("ram-lak", "shepp-logan", "cosine",
-        "hamming", "hann") and scaled by pi / (A * det_spacing), so that
+        "hamming", "hann") and scaled by pi / A, so that
         ``backprojection(filter_sinogram(y))`` reconstructs the image when the angles
-        cover [0, pi) uniformly.  Parallel beam.  Differentiable: the filter is
+        cover [0, pi) uniformly, at any det_spacing.  Parallel beam.  Differentiable: the filter is
         symmetric, so its gradient is the same filter.  Under torch.autocast a 16-bit
         sinogram is filtered in FP32 and the result is FP32, as the paper's
         half-precision FBP filters in single precision (Sec. 3.3)."""

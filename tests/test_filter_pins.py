@@ -47,16 +47,18 @@ def test_windows_at_nyquist_and_dc():
 def test_fft_route_equals_direct_convolution(name):
     rng = np.random.default_rng(3)
     y = rng.standard_normal((2, 7, 41))
-    a = filtering.filter_sinogram(y, name, det_spacing=0.75)
-    b = filtering.filter_sinogram_direct(y, name, det_spacing=0.75)
+    a = filtering.filter_sinogram(y, name)
+    b = filtering.filter_sinogram_direct(y, name)
     assert np.max(np.abs(a - b)) < 1e-12 * np.max(np.abs(b))
 
 
-def test_fbp_reconstructs_disc():
+@pytest.mark.parametrize("sp", [1.0, 0.5, 0.7])
+def test_fbp_reconstructs_disc(sp):
     """Project a disc (area-sampled), filter, backproject: the interior comes back at
-    the disc's intensity and the outside at zero (parallel beam over [0, pi))."""
+    the disc's intensity and the outside at zero (parallel beam over [0, pi)), at bin
+    spacing 1, 0.5 and 0.7 (the detector covers the image in every case)."""
     n, A = 96, 180
-    D = int(math.ceil(n * math.sqrt(2)))
+    D = int(math.ceil(n * math.sqrt(2) / sp))
     R, rho = 30.0, 1.0
     yy, xx = np.mgrid[0:n, 0:n] - 0.5 * (n - 1)
     m = 8
@@ -67,7 +69,7 @@ def test_fbp_reconstructs_disc():
             img += ((xx + dx) ** 2 + (yy + dy) ** 2 < R * R)
     img *= rho / (m * m)
     ang = inputs.uniform_angles(A)
-    g = oracle.Geometry(n, ang, D, 1.0)
+    g = oracle.Geometry(n, ang, D, sp)
     y = oracle.forward(g, img[None])
     rec = oracle.backproject(g, filtering.filter_sinogram(y, "ram-lak"))[0]
     r = np.hypot(xx, yy)
@@ -75,9 +77,13 @@ def test_fbp_reconstructs_disc():
     assert abs(rec[inner].mean() - rho) < 0.02
     assert np.abs(rec[inner] - rho).max() < 0.08
     assert np.abs(rec[outer]).mean() < 0.01
-    # a wrong angular weight or detector scale is caught
-    rec2 = oracle.backproject(g, filtering.filter_sinogram(y, "ram-lak", det_spacing=0.5))[0]
-    assert abs(rec2[inner].mean() - rho) > 0.5
+    # a wrong angular weight is caught, and so is a filter that divides by the bin
+    # spacing once more (the transpose already gathers 1/spacing bins per unit length)
+    rec2 = oracle.backproject(g, 0.5 * filtering.filter_sinogram(y, "ram-lak"))[0]
+    assert abs(rec2[inner].mean() - rho) > 0.4
+    if sp != 1.0:
+        rec3 = oracle.backproject(g, filtering.filter_sinogram(y, "ram-lak") / sp)[0]
+        assert abs(rec3[inner].mean() - rho) > 0.3
     # smoother windows trade resolution for noise but keep the level
     for name in ("shepp-logan", "hann"):
         recw = oracle.backproject(g, filtering.filter_sinogram(y, name))[0]
