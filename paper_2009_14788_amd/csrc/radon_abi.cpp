@@ -112,14 +112,34 @@ Plan::~Plan() {
 
 static std::mutex g_mutex;
 static std::unordered_map<PlanKey, std::unique_ptr<Plan>, PlanKeyHash> g_plans;
-struct DeviceScratch {
-    double *dot_partials = nullptr;
+
+// Scratch of the FP64 inner products, one set per (device, stream): calls on
+// different streams may run at the same time, so they never share partial sums.
+// The single-system partials are slots of pooled blocks, so a stream seen for the
+// first time while it captures (a graph's own capture stream) takes a free slot
+// without allocating; the per-system partials of radon_dot_f64_batched are grown
+// outside capture only.  A replaced buffer stays allocated (a captured graph may
+// still use it) until radon_release_plans.
+constexpr int kDotPartials = 1024;   // doubles per single-system slot
+constexpr int kDotSlots = 64;        // slots per pooled block
+struct StreamScratch {
+    double *dot_partials = nullptr;   // one slot of a DeviceScratch block
     double *row_partials = nullptr;   // per-system partials of radon_dot_f64_batched
     size_t row_count = 0;
-    std::vector<void *> retired;      // replaced partial buffers a graph may still use
+};
+struct DeviceScratch {
+    std::vector<double *> dot_blocks; // kDotSlots slots of kDotPartials doubles each
+    size_t dot_used = 0;
+    std::vector<void *> retired;      // replaced per-system buffers
 };
 static std::unordered_map<int, DeviceScratch> g_scratch;
-constexpr int kDotPartials = 1024;
+static std::map<std::pair<int, hipStream_t>, StreamScratch> g_stream_scratch;
+
+static bool is_capturing(hipStream_t stream, int *rc) {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    *rc = hipStreamIsCapturing(stream, &cap) == hipSuccess ? RADON_OK : RADON_ERR_HIP;
+    return cap != hipStreamCaptureStatusNone;
+}
 
 // Host FP64 angle and ray tables.
 // rays[a*D+d] = (ox, oy, sx, sy): foot point in index coordinates, step * direction.
@@ -341,15 +361,23 @@ static int dot_scratch(hipStream_t stream, double **out) {
     int device = 0;
     if (hipGetDevice(&device) != hipSuccess) return RADON_ERR_NO_DEVICE;
     std::lock_guard<std::mutex> lock(g_mutex);
-    DeviceScratch &s = g_scratch[device];
-    if (!s.dot_partials) {
-        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-        if (hipStreamIsCapturing(stream, &cap) != hipSuccess) return RADON_ERR_HIP;
-        if (cap != hipStreamCaptureStatusNone) return RADON_ERR_NOT_PREPARED;
-        if (hipMalloc(&s.dot_partials, kDotPartials * sizeof(double)) != hipSuccess)
-            return RADON_ERR_ALLOC;
+    StreamScratch &ss = g_stream_scratch[{device, stream}];
+    if (!ss.dot_partials) {
+        DeviceScratch &d = g_scratch[device];
+        if (d.dot_used == d.dot_blocks.size() * kDotSlots) {
+            int rc;
+            const bool cap = is_capturing(stream, &rc);
+            if (rc != RADON_OK) return rc;
+            if (cap) return RADON_ERR_NOT_PREPARED;
+            double *b = nullptr;
+            if (hipMalloc(&b, (size_t)kDotSlots * kDotPartials * sizeof(double)) != hipSuccess)
+                return RADON_ERR_ALLOC;
+            d.dot_blocks.push_back(b);
+        }
+        ss.dot_partials = d.dot_blocks[d.dot_used / kDotSlots] + (d.dot_used % kDotSlots) * kDotPartials;
+        ++d.dot_used;
     }
-    *out = s.dot_partials;
+    *out = ss.dot_partials;
     return RADON_OK;
 }
 
@@ -357,18 +385,19 @@ static int row_scratch(hipStream_t stream, size_t count, double **out) {
     int device = 0;
     if (hipGetDevice(&device) != hipSuccess) return RADON_ERR_NO_DEVICE;
     std::lock_guard<std::mutex> lock(g_mutex);
-    DeviceScratch &s = g_scratch[device];
-    if (s.row_count < count) {
-        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-        if (hipStreamIsCapturing(stream, &cap) != hipSuccess) return RADON_ERR_HIP;
-        if (cap != hipStreamCaptureStatusNone) return RADON_ERR_NOT_PREPARED;
+    StreamScratch &ss = g_stream_scratch[{device, stream}];
+    if (ss.row_count < count) {
+        int rc;
+        const bool cap = is_capturing(stream, &rc);
+        if (rc != RADON_OK) return rc;
+        if (cap) return RADON_ERR_NOT_PREPARED;
         double *p = nullptr;
         if (hipMalloc(&p, count * sizeof(double)) != hipSuccess) return RADON_ERR_ALLOC;
-        if (s.row_partials) s.retired.push_back(s.row_partials);
-        s.row_partials = p;
-        s.row_count = count;
+        if (ss.row_partials) g_scratch[device].retired.push_back(ss.row_partials);
+        ss.row_partials = p;
+        ss.row_count = count;
     }
-    *out = s.row_partials;
+    *out = ss.row_partials;
     return RADON_OK;
 }
 
@@ -416,12 +445,18 @@ static int filter_table(hipStream_t stream, int log2L, int filter, FilterTable *
 // ---------------------------------------------------------------- uneven batches
 // Device job/work tables of one uneven batch, built once per job list (by content:
 // plans, buffers, batch sizes, scales) and reused, so later calls (and graph
-// captures) only launch.
+// captures) only launch.  Every stream that launches a table gets its own work
+// counter (slots of pooled blocks, so a capture stream takes one without
+// allocating): launches of one job list on two streams never share a queue.
+constexpr int kCounterSlots = 64;       // counters per block, 64 bytes apart
+constexpr int kCounterStride = 16;      // ints between two counters
 struct BatchTable {
     BatchJob *jobs = nullptr;
     ImageGroup *groups = nullptr;
     WorkUnit *work = nullptr;
-    int *counter = nullptr;
+    std::vector<int *> counter_blocks;
+    std::map<hipStream_t, int *> counters;
+    bool captured = false;       // launched under stream capture: a graph may replay it
     BatchLaunch launch;
     std::vector<int> fallback;   // jobs without a tiled plan, run with per-call kernels
     BatchTable() = default;
@@ -431,12 +466,40 @@ struct BatchTable {
         if (jobs) (void)hipFree(jobs);
         if (groups) (void)hipFree(groups);
         if (work) (void)hipFree(work);
-        if (counter) (void)hipFree(counter);
+        for (int *b : counter_blocks) (void)hipFree(b);
     }
 };
 static std::unordered_map<std::string, std::unique_ptr<BatchTable>> g_batches;
 static std::deque<std::string> g_batch_order;
+// tables dropped from the cache after a graph captured them: kept until
+// radon_release_plans, since the graph may still replay them
+static std::vector<std::unique_ptr<BatchTable>> g_batch_retired;
 constexpr size_t kMaxBatchTables = 32;
+
+static int alloc_counter_block(BatchTable &t) {
+    int *b = nullptr;
+    if (hipMalloc(&b, (size_t)kCounterSlots * kCounterStride * sizeof(int)) != hipSuccess)
+        return RADON_ERR_ALLOC;
+    t.counter_blocks.push_back(b);
+    return RADON_OK;
+}
+
+// Work counter of table t for stream s (caller holds g_mutex).
+static int stream_counter(BatchTable &t, hipStream_t s, bool capturing, int **out) {
+    auto it = t.counters.find(s);
+    if (it == t.counters.end()) {
+        const size_t used = t.counters.size();
+        if (used == t.counter_blocks.size() * kCounterSlots) {
+            if (capturing) return RADON_ERR_NOT_PREPARED;
+            const int rc = alloc_counter_block(t);
+            if (rc != RADON_OK) return rc;
+        }
+        int *c = t.counter_blocks[used / kCounterSlots] + (used % kCounterSlots) * kCounterStride;
+        it = t.counters.emplace(s, c).first;
+    }
+    *out = it->second;
+    return RADON_OK;
+}
 
 template <typename V>
 static int upload(V **dst, const std::vector<V> &src) {
@@ -543,14 +606,13 @@ static int build_batch_table(const std::vector<Plan *> &plans, const radon_job_t
         if ((rc = upload(&t->jobs, bj)) != RADON_OK) return rc;
         if ((rc = upload(&t->groups, groups)) != RADON_OK) return rc;
         if ((rc = upload(&t->work, wu)) != RADON_OK) return rc;
-        if (hipMalloc(&t->counter, 64) != hipSuccess) return RADON_ERR_ALLOC;
+        if ((rc = alloc_counter_block(*t)) != RADON_OK) return rc;
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, device) != hipSuccess) return RADON_ERR_HIP;
         const int per_cu = batched_blocks_per_cu(direction, dtype, lds);
         t->launch.jobs = t->jobs;
         t->launch.groups = t->groups;
         t->launch.work = t->work;
-        t->launch.counter = t->counter;
         t->launch.n_work = (int)wu.size();
         t->launch.grid = std::max(1, std::min((int)wu.size(), per_cu * prop.multiProcessorCount));
         t->launch.lds = lds;
@@ -590,30 +652,40 @@ static int run_batched(const radon_job_t *jobs, int32_t n, int32_t dtype, int di
         put(&jobs[i].scale, sizeof(float));
     }
     BatchTable *t = nullptr;
+    BatchLaunch launch;
     {
+        const bool capturing = is_capturing(s, &rc);
+        if (rc != RADON_OK) return rc;
         std::lock_guard<std::mutex> lock(g_mutex);
         auto it = g_batches.find(key);
         if (it != g_batches.end()) {
             t = it->second.get();
         } else {
-            hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-            if (hipStreamIsCapturing(s, &cap) != hipSuccess) return RADON_ERR_HIP;
-            if (cap != hipStreamCaptureStatusNone) return RADON_ERR_NOT_PREPARED;
+            if (capturing) return RADON_ERR_NOT_PREPARED;
             std::unique_ptr<BatchTable> nt;
             if ((rc = build_batch_table(plans, jobs, n, dtype, direction, device, nt)) != RADON_OK)
                 return rc;
             if (g_batch_order.size() >= kMaxBatchTables) {
-                (void)hipDeviceSynchronize();   // an evicted table may still be in use
-                g_batches.erase(g_batch_order.front());
+                auto old = g_batches.find(g_batch_order.front());
+                if (old->second->captured) {
+                    g_batch_retired.push_back(std::move(old->second));   // a graph may replay it
+                } else {
+                    (void)hipDeviceSynchronize();   // eager launches of it may still run
+                }
+                g_batches.erase(old);
                 g_batch_order.pop_front();
             }
             t = nt.get();
             g_batches.emplace(key, std::move(nt));
             g_batch_order.push_back(key);
         }
+        launch = t->launch;
+        if (launch.n_work > 0 && (rc = stream_counter(*t, s, capturing, &launch.counter)) != RADON_OK)
+            return rc;
+        t->captured = t->captured || capturing;
     }
-    if (t->launch.n_work > 0) {
-        hipError_t e = launch_batched(direction, dtype, t->launch, s);
+    if (launch.n_work > 0) {
+        hipError_t e = launch_batched(direction, dtype, launch, s);
         if (e != hipSuccess) return RADON_ERR_HIP;
     }
     for (int i : t->fallback) {
@@ -631,10 +703,11 @@ static int run_batched(const radon_job_t *jobs, int32_t n, int32_t dtype, int di
 static int release_all() {
     std::lock_guard<std::mutex> lock(g_mutex);
     if (!g_plans.empty() || !g_scratch.empty() || !g_batches.empty() || !g_workspaces.empty() ||
-        !g_filters.empty())
+        !g_filters.empty() || !g_batch_retired.empty() || !g_stream_scratch.empty())
         (void)hipDeviceSynchronize();
     g_batches.clear();
     g_batch_order.clear();
+    g_batch_retired.clear();
     g_plans.clear();
     g_filters.clear();
     for (auto &kv : g_workspaces) {
@@ -643,11 +716,13 @@ static int release_all() {
     }
     g_workspaces.clear();
     for (auto &kv : g_scratch) {
-        if (kv.second.dot_partials) (void)hipFree(kv.second.dot_partials);
-        if (kv.second.row_partials) (void)hipFree(kv.second.row_partials);
+        for (double *b : kv.second.dot_blocks) (void)hipFree(b);
         for (void *r : kv.second.retired) (void)hipFree(r);
     }
+    for (auto &kv : g_stream_scratch)
+        if (kv.second.row_partials) (void)hipFree(kv.second.row_partials);
     g_scratch.clear();
+    g_stream_scratch.clear();
     return RADON_OK;
 }
 
@@ -800,8 +875,10 @@ int radon_filter_sinogram(const radon_geometry_t *geometry, const void *y, void 
     hipStream_t s = static_cast<hipStream_t>(stream);
     FilterTable *t = nullptr;
     if ((rc = filter_table(s, log2L, filter, &t)) != RADON_OK) return rc;
+    // pi / A: the sampled kernel's 1/spacing cancels against the 1/spacing density of
+    // bins that the exact transpose gathers per unit of detector length
     const double pi = 3.14159265358979323846;
-    const float scale = (float)(pi / ((double)geometry->n_angles * geometry->det_spacing));
+    const float scale = (float)(pi / (double)geometry->n_angles);
     const long long rows = (long long)batch * geometry->n_angles;
     hipError_t e = launch_filter(dtype, y, out, rows, geometry->det_count, log2L, t->H, t->tw,
                                  scale, s);

@@ -14,7 +14,10 @@
 #include <cstring>
 #include <algorithm>
 #include <random>
+#include <thread>
 #include <vector>
+
+#include <hip/hip_runtime.h>
 
 #include "radon.h"
 
@@ -172,11 +175,114 @@ static int solver_mode(std::vector<Geo> &geos, const char *path, double alpha, i
     return fails ? 1 : 0;
 }
 
+// "lifetime" mode: graph-capture lifetime and stream separation.  The geometries form
+// one job list L0 (forward).  L0 runs eagerly on stream A, then is captured on A and
+// on B; the two captured persistent launches must differ in their arguments (each
+// stream has its own work counter).  Forty more job lists (fresh output buffers) then
+// push L0's table out of the cache; replaying the captured launches afterwards must
+// still reproduce the eager outputs bitwise (AddressSanitizer reports a freed table),
+// also with A's and B's replays running at the same time.  The FP64 inner product is
+// captured on A and B the same way.  No allocation may happen while a stream captures.
+static int lifetime_mode(std::vector<Geo> &geos) {
+    hipStream_t A = reinterpret_cast<hipStream_t>(0x1000), B = reinterpret_cast<hipStream_t>(0x2000);
+    const int dt = geos[0].dt;
+    const size_t es = esize(dt);
+    std::vector<radon_job_t> l0;
+    std::vector<void *> outs, eager, keep;
+    for (Geo &g : geos) {
+        void *xin = dev_alloc(g.nx * es);
+        std::memcpy(xin, g.x.data(), g.nx * es);
+        keep.push_back(xin);
+        outs.push_back(dev_alloc(g.ny * es));
+        eager.push_back(dev_alloc(g.ny * es));
+        l0.push_back(radon_job_t{&g.g, xin, outs.back(), g.batch, 1.0f});
+    }
+    int fails = 0;
+    auto expect = [&](bool ok, const char *what) {
+        std::printf("check %s %s\n", what, ok ? "ok" : "FAILED");
+        fails += !ok;
+    };
+    const int n = (int)l0.size();
+    int rc = radon_forward_batched(l0.data(), n, dt, A);
+    expect(rc == 0, "eager_status");
+    for (int k = 0; k < n; ++k) std::memcpy(eager[k], outs[k], geos[k].ny * es);
+    emu::begin_capture(A);
+    rc = radon_forward_batched(l0.data(), n, dt, A);
+    auto graph_a = emu::end_capture(A);
+    emu::begin_capture(B);
+    const int rc_b = radon_forward_batched(l0.data(), n, dt, B);
+    auto graph_b = emu::end_capture(B);
+    expect(rc == 0 && rc_b == 0 && !graph_a.empty() && graph_a.size() == graph_b.size(),
+           "capture_status");
+    bool differ = false;
+    for (size_t i = 0; i < graph_a.size() && i < graph_b.size(); ++i)
+        differ = differ || graph_a[i].args != graph_b[i].args;
+    expect(differ, "streams_use_own_counters");
+    // forty more job lists evict L0's table from the cache
+    for (int list = 0; list < 40; ++list) {
+        std::vector<radon_job_t> li = l0;
+        for (int k = 0; k < n; ++k) {
+            li[k].output = dev_alloc(geos[k].ny * es);
+            keep.push_back(li[k].output);
+        }
+        if (radon_forward_batched(li.data(), n, dt, A) != 0) {
+            expect(false, "eviction_lists");
+            break;
+        }
+    }
+    auto same = [&]() {
+        bool ok = true;
+        for (int k = 0; k < n; ++k) ok = ok && std::memcmp(outs[k], eager[k], geos[k].ny * es) == 0;
+        return ok;
+    };
+    auto poison = [&]() {
+        for (int k = 0; k < n; ++k) std::memset(outs[k], 0xff, geos[k].ny * es);
+    };
+    poison();
+    emu::replay_graph(graph_a);
+    expect(same(), "replay_after_eviction");
+    poison();
+    std::thread ta([&] { emu::replay_graph(graph_a); });
+    std::thread tb([&] { emu::replay_graph(graph_b); });
+    ta.join();
+    tb.join();
+    expect(same(), "concurrent_replays");
+    // FP64 inner products on two streams
+    const Geo &g0 = geos[0];
+    double *d = (double *)dev_alloc(4 * sizeof(double));
+    rc = radon_dot_f64(keep[0], keep[0], (int64_t)g0.nx, dt, d, A);
+    const double ref = d[0];
+    emu::begin_capture(A);
+    rc |= radon_dot_f64(keep[0], keep[0], (int64_t)g0.nx, dt, d + 1, A);
+    auto dot_a = emu::end_capture(A);
+    emu::begin_capture(B);
+    rc |= radon_dot_f64(keep[0], keep[0], (int64_t)g0.nx, dt, d + 2, B);
+    auto dot_b = emu::end_capture(B);
+    differ = false;
+    for (size_t i = 0; i < dot_a.size() && i < dot_b.size(); ++i)
+        differ = differ || dot_a[i].args != dot_b[i].args;
+    expect(rc == 0 && !dot_a.empty() && dot_a.size() == dot_b.size() && differ,
+           "dot_streams_use_own_partials");
+    std::thread da([&] { emu::replay_graph(dot_a); });
+    std::thread db([&] { emu::replay_graph(dot_b); });
+    da.join();
+    db.join();
+    expect(d[1] == ref && d[2] == ref, "dot_concurrent_replays");
+    expect(emu::capture().allocs_while_capturing == 0, "no_allocation_under_capture");
+    std::printf("summary geometries %zu failures %d\n", geos.size(), fails);
+    std::free(d);
+    for (void *p : outs) std::free(p);
+    for (void *p : eager) std::free(p);
+    for (void *p : keep) std::free(p);
+    return fails ? 1 : 0;
+}
+
 int main(int argc, char **argv) {
     if (argc < 2) return 2;
     const bool batched = argc > 2 && std::strcmp(argv[2], "batched") == 0;
     const bool filtering = argc > 3 && std::strcmp(argv[2], "filter") == 0;
     const bool solving = argc > 5 && std::strcmp(argv[2], "solver") == 0;
+    const bool lifetime = argc > 2 && std::strcmp(argv[2], "lifetime") == 0;
     FILE *f = std::fopen(argv[1], "r");
     if (!f) return 2;
     std::vector<Geo> geos;
@@ -196,7 +302,7 @@ int main(int argc, char **argv) {
     int fails = 0;
     for (size_t k = 0; k < geos.size(); ++k) {
         Geo &g = geos[k];
-        if (solving) {
+        if (solving || lifetime) {
             g.g = radon_geometry_t{g.beam, g.n, g.A, g.D, g.angles.data(), g.sp, g.S, g.E, g.step};
             g.nx = (size_t)g.batch * g.n * g.n;
             g.ny = (size_t)g.batch * g.A * g.D;
@@ -267,6 +373,7 @@ int main(int argc, char **argv) {
         std::free(bd);
     }
     if (filtering) return filter_mode(geos, argv[3]);
+    if (lifetime) return geos.empty() ? 2 : lifetime_mode(geos);
     if (solving) {
         char *end = nullptr;
         const double alpha = std::strtod(argv[4], &end);

@@ -132,8 +132,68 @@ inline void fiber_entry() {
     fiber_yield(true);
 }
 
+// Stream capture: launches on a capturing stream are recorded (with the bytes of
+// their arguments) instead of run, and replay_graph() runs a recorded sequence later,
+// as a graph replay would.  An allocation while any stream captures is counted.
+struct Recorded {
+    hipStream_t stream;
+    std::vector<unsigned char> args;
+    std::function<void()> run;
+};
+struct Capture {
+    std::mutex mu;
+    std::vector<hipStream_t> streams;
+    std::vector<Recorded> launches;
+    long allocs_while_capturing = 0;
+};
+inline Capture &capture() { static Capture c; return c; }
+inline bool capturing(hipStream_t s) {
+    std::lock_guard<std::mutex> lk(capture().mu);
+    for (hipStream_t c : capture().streams)
+        if (c == s) return true;
+    return false;
+}
+inline void begin_capture(hipStream_t s) {
+    std::lock_guard<std::mutex> lk(capture().mu);
+    capture().streams.push_back(s);
+}
+// Ends the capture of s and returns its recorded launches (the "graph").
+inline std::vector<Recorded> end_capture(hipStream_t s) {
+    std::lock_guard<std::mutex> lk(capture().mu);
+    auto &v = capture().streams;
+    v.erase(std::remove(v.begin(), v.end(), s), v.end());
+    std::vector<Recorded> out, keep;
+    for (auto &r : capture().launches) (r.stream == s ? out : keep).push_back(std::move(r));
+    capture().launches.swap(keep);
+    return out;
+}
+inline void replay_graph(const std::vector<Recorded> &g) {
+    for (const Recorded &r : g) r.run();
+}
+template <class T> inline void append_bytes(std::vector<unsigned char> &v, const T &x) {
+    const unsigned char *p = reinterpret_cast<const unsigned char *>(&x);
+    v.insert(v.end(), p, p + sizeof(T));
+}
+
 template <class K, class... A>
-void launch(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t, A... args) {
+void launch_now(K kernel, dim3 grid, dim3 block, size_t lds, A... args);
+
+template <class K, class... A>
+void launch(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t stream, A... args) {
+    if (capturing(stream)) {
+        Recorded r;
+        r.stream = stream;
+        (append_bytes(r.args, args), ...);
+        r.run = [=] { launch_now(kernel, grid, block, lds, args...); };
+        std::lock_guard<std::mutex> lk(capture().mu);
+        capture().launches.push_back(std::move(r));
+        return;
+    }
+    launch_now(kernel, grid, block, lds, args...);
+}
+
+template <class K, class... A>
+void launch_now(K kernel, dim3 grid, dim3 block, size_t lds, A... args) {
     ++launches();
     const int nt = (int)(block.x * block.y * block.z);
     const long nb = (long)grid.x * grid.y * grid.z;
@@ -213,6 +273,10 @@ inline void __syncthreads() { emu::fiber_yield(false); }
 
 inline hipError_t hipGetLastError() { hipError_t e = emu::last_error(); emu::last_error() = hipSuccess; return e; }
 inline hipError_t hipMalloc(void **p, size_t n) {
+    {
+        std::lock_guard<std::mutex> lk(emu::capture().mu);
+        if (!emu::capture().streams.empty()) ++emu::capture().allocs_while_capturing;
+    }
     *p = nullptr;
     if (posix_memalign(p, 256, n ? n : 1) != 0) return hipErrorOutOfMemory;
     return hipSuccess;
@@ -224,7 +288,10 @@ inline hipError_t hipMemset(void *d, int v, size_t n) { std::memset(d, v, n); re
 inline hipError_t hipGetDevice(int *d) { *d = 0; return hipSuccess; }
 inline hipError_t hipGetDeviceProperties(hipDeviceProp_t *p, int) { *p = hipDeviceProp_t{}; return hipSuccess; }
 inline hipError_t hipDeviceSynchronize() { return hipSuccess; }
-inline hipError_t hipStreamIsCapturing(hipStream_t, hipStreamCaptureStatus *s) { *s = hipStreamCaptureStatusNone; return hipSuccess; }
+inline hipError_t hipStreamIsCapturing(hipStream_t st, hipStreamCaptureStatus *s) {
+    *s = emu::capturing(st) ? hipStreamCaptureStatusActive : hipStreamCaptureStatusNone;
+    return hipSuccess;
+}
 inline hipError_t hipEventCreate(hipEvent_t *e) { *e = new int(0); return hipSuccess; }
 inline hipError_t hipEventDestroy(hipEvent_t e) { delete (int *)e; return hipSuccess; }
 inline hipError_t hipEventRecord(hipEvent_t, hipStream_t = nullptr) { return hipSuccess; }
