@@ -29,8 +29,11 @@
  * until the stream's work has completed.  The library owns only its per-geometry
  * plans (angle/ray tables, work items, launch shapes), one workspace per (device,
  * stream) for the interleaved copy of a call's input (grown on demand, never under
- * stream capture), and the tables of uneven batches; all are created on first use
- * (or by radon_prepare()) and kept until radon_release_plans().
+ * stream capture), the tables of uneven batches with one work counter per stream,
+ * and the inner products' partial sums per (device, stream); all are created on
+ * first use (or by radon_prepare()) and kept until radon_release_plans().  A buffer
+ * that a captured graph may still use (a replaced workspace or partials buffer, or
+ * a batch table that a graph captured) is never freed before radon_release_plans().
  *
  * Errors.  Every entry point returns RADON_OK (0) or a negative status; no C++
  * exception crosses the ABI.  A launch error is reported from the call; a fault
@@ -76,12 +79,15 @@ typedef struct radon_geometry {
     double step;               /* sample spacing along each ray, > 0 (usual value 1) */
 } radon_geometry_t;
 
-/* Host-only check of a geometry (no device needed).  RADON_OK or
- * RADON_ERR_INVALID_ARG; never touches the GPU. */
+/* Library utility (no operation of the paper): host-only check of a geometry against
+ * the limits above (no device needed).  RADON_OK, RADON_ERR_INVALID_ARG, or
+ * RADON_ERR_UNSUPPORTED for sizes past the kernels' index ranges; never touches the
+ * GPU. */
 int radon_validate(const radon_geometry_t *geometry);
 
-/* Build (or find) the plan of a geometry on the current device for `dtype` and a
- * batch size: angle and ray tables, work items, the null stream's workspace, and
+/* Library utility (no operation of the paper; it prepares the batch processing of
+ * Sec. 4.1): build (or find) the plan of a geometry on the current device for `dtype`
+ * and a batch size: angle and ray tables, work items, the null stream's workspace, and
  * launch shapes chosen by timing the candidates on the device (unless the environment
  * sets RADON_AUTOTUNE=0; the choice is kept per storage type and power-of-two batch
  * class, in memory and, if RADON_TUNE_CACHE names a file, one text line per choice in
@@ -131,18 +137,23 @@ enum { RADON_FILTER_RAMLAK = 0, RADON_FILTER_SHEPP_LOGAN = 1, RADON_FILTER_COSIN
  * even n, over a zero-padded length L = the smallest power of two >= max(64, 2D) --
  * times the window of `filter` at the normalised frequency f in [-1/2, 1/2)
  * (Shepp-Logan sin(pi f)/(pi f), cosine cos(pi f), Hamming 0.54 + 0.46 cos(2 pi f),
- * Hann 0.5 + 0.5 cos(2 pi f), Ram-Lak 1), and scaled by pi / (A * det_spacing), so
- * that radon_backproject of the result reconstructs the image when the A angles
- * cover [0, pi) uniformly.  out may equal y (in place).  FP32 arithmetic for every
+ * Hann 0.5 + 0.5 cos(2 pi f), Ram-Lak 1), and scaled by pi / A, so that
+ * radon_backproject of the result reconstructs the image when the A angles cover
+ * [0, pi) uniformly, at any det_spacing (the sampled kernel's 1/det_spacing cancels
+ * the transpose's density of 1/det_spacing bins per unit of detector length).  out may equal y (in place).  FP32 arithmetic for every
  * storage type.  Parallel beam only (RADON_ERR_UNSUPPORTED for the fan beam, and for
  * D > 4096).  Builds its FP32 filter table on first use (RADON_ERR_NOT_PREPARED if
  * that first use is under stream capture). */
 int radon_filter_sinogram(const radon_geometry_t *geometry, const void *y, void *out,
                           int32_t batch, int32_t filter, int32_t dtype, void *stream);
 
-/* FP64 inner product sum_i a[i]*b[i] over n elements of `dtype` (device pointers),
- * written to out (device, one double).  Used for the adjoint (dot-product) test and
- * for losses; deterministic (fixed reduction tree). */
+/* Library utility (no operation of the paper; the inner products of the conjugate
+ * gradient solvers of Sec. 4.2 and 4.3, the adjoint (dot-product) test and losses):
+ * FP64 inner product sum_i a[i]*b[i] over n elements of `dtype` (device pointers),
+ * written to out (device, one double).  Deterministic (fixed reduction tree).  Uses
+ * library-owned partials, one set per (device, stream), so calls on different streams
+ * may overlap; the first call on a device must not be under stream capture
+ * (RADON_ERR_NOT_PREPARED). */
 int radon_dot_f64(const void *a, const void *b, int64_t n, int32_t dtype, double *out,
                   void *stream);
 
@@ -153,15 +164,18 @@ int radon_dot_f64(const void *a, const void *b, int64_t n, int32_t dtype, double
  * systems stored one after another; every system has its own step sizes.  Scalars stay
  * in device memory, so a solve is queued on the stream without waiting on the host. */
 
-/* Per-system FP64 inner products: out[k] = sum_{i<n} a[k n + i] * b[k n + i] for
+/* Per-system FP64 inner products of the conjugate-gradient solvers (Sec. 4.2, 4.3):
+ * out[k] = sum_{i<n} a[k n + i] * b[k n + i] for
  * k < batch (a, b: device, `dtype`, 16-byte aligned; out: device, batch doubles).
  * Deterministic (fixed reduction tree).  batch <= 65535, else RADON_ERR_INVALID_ARG;
- * n == 0 writes zeros.  Uses a library-owned partials buffer (grown outside stream
- * capture; RADON_ERR_NOT_PREPARED if it must grow under capture). */
+ * n == 0 writes zeros.  Uses a library-owned partials buffer per (device, stream),
+ * so calls on different streams may overlap; it is grown outside stream capture
+ * (RADON_ERR_NOT_PREPARED if it must be created or grown under capture: call once on
+ * the capturing stream before capturing). */
 int radon_dot_f64_batched(const void *a, const void *b, int64_t n, int32_t batch, int32_t dtype,
                           double *out, void *stream);
 
-/* Per-system scaled update out[k n + i] = u[k n + i] + c_k v[k n + i] with
+/* Per-system scaled update of the solvers (Sec. 4.2, 4.3): out[k n + i] = u[k n + i] + c_k v[k n + i] with
  * c_k = c0 * num[k] / den[k] evaluated in FP64 (num or den NULL reads as 1; c_k = 0
  * where den[k] == 0, which freezes a system whose search direction has vanished).
  * The element arithmetic is FP64, rounded once to FP32 and then to `dtype`.  Where
@@ -174,13 +188,14 @@ int radon_axpy_ratio(const void *u, const void *v, void *out, const double *num,
 
 enum { RADON_SOLVER_LANDWEBER = 0, RADON_SOLVER_CGNE = 1 };
 
-/* Bytes of workspace radon_landweber (RADON_SOLVER_LANDWEBER) or radon_cgne
+/* Library utility (workspace size of the solvers of Sec. 4.2): bytes of workspace
+ * radon_landweber (RADON_SOLVER_LANDWEBER) or radon_cgne
  * (RADON_SOLVER_CGNE) needs for `batch` systems of this geometry and dtype; negative
  * status on a bad argument. */
 int64_t radon_solver_workspace_bytes(const radon_geometry_t *geometry, int32_t solver,
                                      int32_t batch, int32_t dtype);
 
-/* Landweber iteration x <- x - alpha R^T (R x - y), `iterations` times, in place on x
+/* Landweber iteration (Sec. 4.2) x <- x - alpha R^T (R x - y), `iterations` times, in place on x
  * [batch][N][N] (device, the initial guess on entry); y [batch][A][D] (device).
  * alpha is applied inside the backprojection kernel (no unscaled gradient is stored).
  * workspace: device, 16-byte aligned, at least radon_solver_workspace_bytes(...,
@@ -202,7 +217,8 @@ int radon_cgne(const radon_geometry_t *geometry, const void *y, void *x, int32_t
                int32_t iterations, int32_t dtype, void *workspace, int64_t workspace_bytes,
                void *stream);
 
-/* Calibration of the current device for roofline fractions: the FP32 multiply-add
+/* Library utility (no operation of the paper): calibration of the current device for
+ * roofline fractions: the FP32 multiply-add
  * rate (multiply-adds per second, v_fmac_f32 with packed FP32 off, many independent
  * chains) and the LDS read bandwidth (bytes per second, conflict-free 16-byte reads)
  * that two fixed-length microbenchmark kernels reach; best of three timed runs after a
@@ -210,10 +226,13 @@ int radon_cgne(const radon_geometry_t *geometry, const void *y, void *x, int32_t
  * device buffer.  RADON_ERR_INVALID_ARG for a null output. */
 int radon_measure_peaks(double *fma_per_s, double *lds_bytes_per_s);
 
-/* Free every plan and queue the library holds (synchronises the device). */
+/* Library utility (no operation of the paper): free every plan, table, workspace and
+ * scratch buffer the library holds (synchronises the device).  Graphs captured
+ * before must not be replayed afterwards. */
 int radon_release_plans(void);
 
-/* Launch shape chosen for a geometry/dtype/batch (after radon_prepare):
+/* Library utility (no operation of the paper): launch shape chosen for a
+ * geometry/dtype/batch (after radon_prepare):
  * out[0..3] = forward {images per thread, angles per block, staging, variant},
  * out[4..7] = the same for the backprojection.  variant: 0 = direct kernel, 1 = tiled
  * kernel.  staging: 1 when the tiled kernel first copies the call's input (images,
@@ -222,10 +241,11 @@ int radon_release_plans(void);
 int radon_plan_info(const radon_geometry_t *geometry, int32_t dtype, int32_t batch,
                     int32_t *out8);
 
-/* Static description of a status code. */
+/* Library utility (no operation of the paper): static description of a status code. */
 const char *radon_status_string(int status);
 
-/* Library version, major*10000 + minor*100 + patch. */
+/* Library utility (no operation of the paper): version, major*10000 + minor*100 +
+ * patch. */
 int radon_version(void);
 
 #ifdef __cplusplus

@@ -6,11 +6,14 @@
 // (c-(N-1)/2, r-(N-1)/2)) are shifted by cN = (N-1)/2.
 //
 // A ray is (ox, oy) = its foot point F in index coordinates and (sx, sy) =
-// step * its unit direction w; sample k sits at (fma(k, sx, ox), fma(k, sy, oy)).
-// Forward and backprojection evaluate sample positions with exactly this
-// expression from the same ray parameters, and the bilinear weights as the
-// products (1-fx or fx) * (1-fy or fy) of the same FP32 factors, so the two
-// kernels use bit-identical sample weights and differ only in summation order.
+// step * its unit direction w; sample k sits at (ox + k sx, oy + k sy).  The kernels
+// form these positions independently and to different roundings: the direct kernels
+// in FP64 per sample; the tiled forward finds each lane's first sample in a slab in
+// FP64 and steps the following ones as FP32 offsets from it (below ~2e-6 pixel of
+// error); the tiled backprojection forms each pixel's coordinates along and across
+// the rays of an angle in FP64 and the tent arguments as small FP32 differences.
+// Forward and backprojection are therefore transposes of each other up to FP32
+// rounding of the weights (the dot-product gap is at that level, not zero).
 #pragma once
 
 #include <hip/hip_runtime.h>

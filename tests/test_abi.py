@@ -190,3 +190,23 @@ def test_measure_peaks_null_outputs():
     d = ctypes.c_double(0.0)
     assert _lib.lib.radon_measure_peaks(None, ctypes.byref(d)) == -1
     assert _lib.lib.radon_measure_peaks(ctypes.byref(d), None) == -1
+
+
+def test_every_declaration_cites_its_passage():
+    """Each function the header declares is preceded by a comment that either cites
+    the paper's passage defining the operation ("Sec. ...") or labels it a library
+    utility; consecutive declarations may share one comment."""
+    text = open(os.path.join(ROOT, "include", "radon.h")).read()
+    body = text[text.index('extern "C" {'):]
+    decl = re.compile(r"^(?:int|int64_t|const char \*)\s*(radon_\w+)\(", re.M)
+    names = decl.findall(body)
+    assert len(names) >= 18
+    for m in decl.finditer(body):
+        before = body[:m.start()].rstrip()
+        # skip back over directly preceding declarations that share the comment
+        while before.endswith(";"):
+            before = before[:before.rfind("\n", 0, before.rfind("radon_"))].rstrip()
+        assert before.endswith("*/"), m.group(1)
+        comment = before[before.rfind("/*"):]
+        assert ("Sec." in comment or "Library utility" in comment
+                or "cannot allocate" in comment), (m.group(1), comment[:120])
