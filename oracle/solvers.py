@@ -15,6 +15,11 @@ forward and backprojection) and follows the textbook recurrences:
               keeps the residual in data space: r = y - R x, s = R^T r, p = s;
               q = R p;  a = <s,s>/<q,q>;  x += a p;  r -= a q;  s = R^T r;
               p = s + (<s',s'>/<s,s>) p
+  unrolled gradient descent (the Landweber steps above from x_0 = 0, K of them) and
+              the gradient of L = ||x_K - x_true||^2 with respect to the data y: with
+              M = I - alpha R^T R (symmetric), x_K = sum_{j<K} M^j alpha R^T y, so
+              dL/dy = 2 alpha R sum_{j<K} M^j (x_K - x_true)  (the chain rule through
+              the K steps, the adjoint recurrence a backward pass evaluates)
 Inner products run over the whole array (one system per call).
 """
 import numpy as np
@@ -78,3 +83,17 @@ def cgne(fwd, bp, y, x0, iters):
         ss = ss_new
         out.append(x.copy())
     return out
+
+
+def unrolled_gd_grad(fwd, bp, y, alpha, iters, x_true):
+    """K = iters gradient steps x <- x - alpha R^T (R x - y) from x_0 = 0, and the
+    gradient of L = ||x_K - x_true||^2 with respect to y.  Returns (iterates, grad)
+    with iterates = [x_1, ..., x_K]."""
+    it = landweber(fwd, bp, y, alpha, iters, np.zeros_like(np.asarray(x_true, dtype=np.float64)))
+    e = it[-1] - np.asarray(x_true, dtype=np.float64)
+    term = e.copy()                     # M^0 e
+    acc = e.copy()
+    for _ in range(iters - 1):
+        term = term - alpha * bp(fwd(term))     # M^(j+1) e
+        acc = acc + term
+    return it, 2.0 * alpha * fwd(acc)

@@ -86,3 +86,41 @@ def test_landweber_closed_form():
         acc = acc + term
         term = G @ term
         assert np.linalg.norm(it[k].ravel() - acc) < 1e-10 * np.linalg.norm(acc), k
+
+
+def test_unrolled_gd_gradient_matches_matrix_chain_rule():
+    """The gradient of L = ||x_K - x_true||^2 with respect to y after K unrolled
+    gradient steps: the oracle's adjoint recurrence against the explicit Jacobian
+    J = sum_{j<K} (I - alpha R^T R)^j alpha R^T built from the dense matrix (grad =
+    2 J^T (x_K - x_true)), and against central differences, exact for this quadratic
+    loss up to rounding."""
+    n, A, D, K = 16, 10, 23, 10
+    g, R = _dense(n, A, D)
+    rng = np.random.default_rng(6)
+    x_true = inputs.phantom(n, 4, [22, 0])[0].astype(np.float64)
+    y = R @ x_true.ravel() + 0.05 * rng.standard_normal(A * D)
+    alpha = 1.0 / np.linalg.eigvalsh(R.T @ R)[-1]
+    fwd = lambda v: (R @ v.ravel()).reshape(A, D)
+    bp = lambda r: (R.T @ r.ravel()).reshape(n, n)
+    it, grad = solvers.unrolled_gd_grad(fwd, bp, y.reshape(A, D), alpha, K, x_true)
+    G = np.eye(n * n) - alpha * R.T @ R
+    J = np.zeros((n * n, A * D))
+    P = np.eye(n * n)
+    for _ in range(K):
+        J += P @ (alpha * R.T)
+        P = G @ P
+    xk = J @ y
+    assert np.linalg.norm(it[-1].ravel() - xk) < 1e-10 * np.linalg.norm(xk)
+    ref = 2.0 * J.T @ (xk - x_true.ravel())
+    assert np.linalg.norm(grad.ravel() - ref) < 1e-10 * np.linalg.norm(ref)
+    # central differences along random directions
+    loss = lambda yy: float(np.sum((J @ yy - x_true.ravel()) ** 2))
+    for s in range(3):
+        v = rng.standard_normal(A * D)
+        h = 1e-3
+        fd = (loss(y + h * v) - loss(y - h * v)) / (2 * h)
+        assert abs(fd - grad.ravel() @ v) <= 1e-8 * max(1.0, abs(fd)), s
+    # a planted mistake (the sum stopping one term early) fails the pin
+    bad = 2.0 * alpha * fwd(sum((np.linalg.matrix_power(G, j) @ (it[-1] - x_true).ravel()).reshape(n, n)
+                               for j in range(K - 1)))
+    assert np.linalg.norm(bad.ravel() - ref) > 1e-3 * np.linalg.norm(ref)
