@@ -157,6 +157,55 @@ int radon_filter_sinogram(const radon_geometry_t *geometry, const void *y, void 
 int radon_dot_f64(const void *a, const void *b, int64_t n, int32_t dtype, double *out,
                   void *stream);
 
+/* ---------------------------------------------------------------- shearlets
+ * Alpha-shearlet transform (Sec. 2.1 lists it among the GPU routines; Sec. 3.2 uses
+ * real-valued alpha-shearlets, alpha = 0.5, 5 scales, normalised on the Fourier side
+ * to a Parseval frame, 59 channels for a 512 x 512 image).  The Fourier filters psi_m
+ * of the system are built once per (device, shape, alphas) in FP64 on the host and
+ * kept in FP32 on the device; every transform is FFTs and products on the GPU:
+ *   forward  c[b][m] = Re IFFT2(FFT2(x[b]) psi_m)
+ *   adjoint  x[b]    = Re IFFT2(sum_m FFT2(c[b][m]) psi_m)  (adjoint(forward(x)) = x)
+ * The system: r = max(|xi_1|, |xi_2|) of the frequency in cycles per sample; a smooth
+ * low-pass and J radial bands (plateau of the low-pass up to 2^-(J+1)); per scale j,
+ * ceil(2^(j (1 - alpha_j))) shears on each side of the centre in each of the two
+ * frequency cones, with angular windows whose squares sum to 1; the squares of all
+ * filters sum to 1 at every frequency.  Channel order: the low-pass, then per scale
+ * the horizontal cone's shears -K..K and the vertical cone's -K..K. */
+typedef struct radon_shearlet {
+    int32_t width;            /* W, a power of two in [16, 4096] (RADON_ERR_UNSUPPORTED otherwise) */
+    int32_t height;           /* H, a power of two in [16, 4096] */
+    int32_t n_scales;         /* J in [1, 16] */
+    int32_t reserved;         /* 0 */
+    const double *alphas;     /* host [J], each in [0, 1]; read during the call */
+} radon_shearlet_t;
+
+/* Number of coefficient channels M of the system (Sec. 3.2: 59 for 512 x 512, five
+ * scales of alpha = 0.5), or a negative status.  Host only. */
+int radon_shearlet_channels(const radon_shearlet_t *s);
+
+/* Scale of every channel (Sec. 3.2's regularised reconstruction weighs channels by
+ * scale): scales[0] = 0 for the low-pass, j + 1 for the channels of scale j.  scales:
+ * host array of radon_shearlet_channels(s) entries.  Host only. */
+int radon_shearlet_scales(const radon_shearlet_t *s, int32_t *scales);
+
+/* Library utility (prepares the transforms of Sec. 3.2): build the filters of s on the
+ * current device and grow the null stream's workspace for `batch` images (call before
+ * capturing a stream that will use s; synchronises the device). */
+int radon_shearlet_prepare(const radon_shearlet_t *s, int32_t batch);
+
+/* Forward alpha-shearlet transform (Sec. 2.1, 3.2): coeffs[b][m][H][W] for the images
+ * x[b][H][W], b < batch, m < M.  x, coeffs: device, `dtype` (FP32, FP16 or BF16
+ * storage; FP32 arithmetic), contiguous, 16-byte aligned.  Uses the stream's library
+ * workspace (up to ~0.6 GB; RADON_ERR_NOT_PREPARED if it must grow under capture).
+ * Asynchronous on `stream`. */
+int radon_shearlet_forward(const radon_shearlet_t *s, const void *x, void *coeffs, int32_t batch,
+                           int32_t dtype, void *stream);
+
+/* Adjoint (and, the frame being Parseval, inverse) of radon_shearlet_forward (Sec.
+ * 3.2): x[b][H][W] from coeffs[b][m][H][W].  Same layouts, ownership and errors. */
+int radon_shearlet_adjoint(const radon_shearlet_t *s, const void *coeffs, void *x, int32_t batch,
+                           int32_t dtype, void *stream);
+
 /* ---------------------------------------------------------------- solvers
  * Iterative reconstruction with the projector pair (TorchRadon Sec. 4.2: Landweber
  * iteration and conjugate gradient on the normal equations; Sec. 4.3: conjugate

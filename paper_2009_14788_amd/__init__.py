@@ -11,7 +11,7 @@ import importlib
 __all__ = ["Radon", "RadonFanbeam", "RadonForward", "RadonBackprojection", "dot_f64",
            "dot_f64_batched", "autocast_dtype", "default_fan_spacing", "release_plans",
            "power_iteration", "unrolled_gd", "Landweber", "cg", "cgne", "BatchedRadon",
-           "inputs"]
+           "ShearletTransform", "inputs"]
 
 _LAZY = {
     "Radon": "radon", "RadonFanbeam": "radon", "RadonForward": "radon",
@@ -19,6 +19,7 @@ _LAZY = {
     "release_plans": "radon", "dot_f64_batched": "radon", "autocast_dtype": "radon",
     "power_iteration": "solvers", "unrolled_gd": "solvers", "Landweber": "solvers",
     "cg": "solvers", "cgne": "solvers", "BatchedRadon": "batched",
+    "ShearletTransform": "shearlet",
 }
 
 

@@ -50,6 +50,16 @@ class Job(ctypes.Structure):
     ]
 
 
+class Shearlet(ctypes.Structure):
+    _fields_ = [
+        ("width", ctypes.c_int32),
+        ("height", ctypes.c_int32),
+        ("n_scales", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("alphas", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
 def _load():
     # PyTorch ships its own HIP runtime (same soname, libamdhip64.so.7).  Loading torch
     # first makes libradon.so bind to that runtime, so that the library and torch share
@@ -86,6 +96,11 @@ def _load():
         "radon_release_plans": ([], ctypes.c_int),
         "radon_plan_info": ([G, i32, i32, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
         "radon_status_string": ([ctypes.c_int], ctypes.c_char_p),
+        "radon_shearlet_channels": ([ctypes.POINTER(Shearlet)], ctypes.c_int),
+        "radon_shearlet_scales": ([ctypes.POINTER(Shearlet), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+        "radon_shearlet_prepare": ([ctypes.POINTER(Shearlet), i32], ctypes.c_int),
+        "radon_shearlet_forward": ([ctypes.POINTER(Shearlet), vp, vp, i32, i32, vp], ctypes.c_int),
+        "radon_shearlet_adjoint": ([ctypes.POINTER(Shearlet), vp, vp, i32, i32, vp], ctypes.c_int),
         "radon_version": ([], ctypes.c_int),
     }
     for name, (args, res) in sig.items():

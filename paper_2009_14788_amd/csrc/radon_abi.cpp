@@ -23,6 +23,7 @@
 #include "radon_filter.hpp"
 #include "radon_launch.hpp"
 #include "radon_plan.hpp"
+#include "radon_shearlet.hpp"
 
 namespace radon {
 
@@ -335,7 +336,7 @@ struct Workspace {
 };
 static std::unordered_map<std::string, Workspace> g_workspaces;
 
-static void *stream_workspace(hipStream_t stream, size_t need, size_t *have) {
+void *stream_workspace(hipStream_t stream, size_t need, size_t *have) {
     *have = 0;
     int device = 0;
     if (hipGetDevice(&device) != hipSuccess) return nullptr;
@@ -702,9 +703,8 @@ static int run_batched(const radon_job_t *jobs, int32_t n, int32_t dtype, int di
 
 static int release_all() {
     std::lock_guard<std::mutex> lock(g_mutex);
-    if (!g_plans.empty() || !g_scratch.empty() || !g_batches.empty() || !g_workspaces.empty() ||
-        !g_filters.empty() || !g_batch_retired.empty() || !g_stream_scratch.empty())
-        (void)hipDeviceSynchronize();
+    (void)hipDeviceSynchronize();
+    release_shearlet_plans();
     g_batches.clear();
     g_batch_order.clear();
     g_batch_retired.clear();

@@ -16,100 +16,12 @@
 #include <cmath>
 
 #include "radon_common.hpp"
+#include "radon_fft.hpp"
 #include "radon_filter.hpp"
 
 namespace radon {
 
 constexpr int kFilterThreads = 256;
-
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-    return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
-}
-__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-
-// In-register DFTs, natural order in and out: X_k = sum_n x_n exp(-2 pi i n k / R).
-__device__ __forceinline__ void dft4(float2 &x0, float2 &x1, float2 &x2, float2 &x3) {
-    const float2 a = cadd(x0, x2), b = csub(x0, x2), c = cadd(x1, x3), d = csub(x1, x3);
-    x0 = cadd(a, c);
-    x2 = csub(a, c);
-    x1 = make_float2(b.x + d.y, b.y - d.x);             // b - i d
-    x3 = make_float2(b.x - d.y, b.y + d.x);             // b + i d
-}
-
-template <int R> __device__ __forceinline__ void dft(float2 *v);
-
-template <> __device__ __forceinline__ void dft<4>(float2 *v) { dft4(v[0], v[1], v[2], v[3]); }
-
-template <> __device__ __forceinline__ void dft<8>(float2 *v) {
-    // even and odd halves, then X_k = E_k + W^k O_k, X_{k+4} = E_k - W^k O_k, W = exp(-i pi/4)
-    float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
-    float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
-    dft4(e0, e1, e2, e3);
-    dft4(o0, o1, o2, o3);
-    constexpr float c = 0.70710678118654752f;
-    const float2 t1 = make_float2(c * (o1.x + o1.y), c * (o1.y - o1.x));    // W   o1
-    const float2 t2 = make_float2(o2.y, -o2.x);                            // W^2 o2 = -i o2
-    const float2 t3 = make_float2(c * (o3.y - o3.x), -c * (o3.x + o3.y));   // W^3 o3
-    v[0] = cadd(e0, o0);
-    v[4] = csub(e0, o0);
-    v[1] = cadd(e1, t1);
-    v[5] = csub(e1, t1);
-    v[2] = cadd(e2, t2);
-    v[6] = csub(e2, t2);
-    v[3] = cadd(e3, t3);
-    v[7] = csub(e3, t3);
-}
-
-// One Stockham pass of radix R = 2^LOG2R over buf[0, 2^LOG2L) in place, Ns = 2^LOG2NS:
-// every thread first reads all its butterflies' inputs, the block synchronises, then
-// each butterfly j (k = j mod Ns) applies the twiddles exp(-2 pi i r k / (Ns R)) =
-// tw[r k L / (Ns R)], its R-point DFT, and writes output r to (j - k) R + k + r Ns.
-template <int LOG2R, int LOG2L, int LOG2NS>
-__device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *__restrict__ tw) {
-    constexpr int R = 1 << LOG2R;
-    constexpr int nb = 1 << (LOG2L - LOG2R);             // butterflies
-    constexpr int Ns = 1 << LOG2NS;
-    constexpr int sh = LOG2L - LOG2NS - LOG2R;
-    constexpr int JMAX = (nb + kFilterThreads - 1) / kFilterThreads;
-    float2 v[JMAX][R];
-#pragma unroll
-    for (int jj = 0; jj < JMAX; ++jj) {
-        const int j = threadIdx.x + kFilterThreads * jj;
-        if (j < nb) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) v[jj][r] = buf[j + r * nb];
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int jj = 0; jj < JMAX; ++jj) {
-        const int j = threadIdx.x + kFilterThreads * jj;
-        if (j < nb) {
-            const int k = j & (Ns - 1);
-            if (Ns > 1 && k != 0) {
-#pragma unroll
-                for (int r = 1; r < R; ++r) v[jj][r] = cmul(v[jj][r], tw[(r * k) << sh]);
-            }
-            dft<R>(v[jj]);
-            const int base = ((j - k) << LOG2R) + k;
-#pragma unroll
-            for (int r = 0; r < R; ++r) buf[base + r * Ns] = v[jj][r];
-        }
-    }
-    __syncthreads();
-}
-
-// Forward transform of buf[0, 2^LOG2L): radix-4 passes while the remaining exponent is
-// not a multiple of 3, then radix-8 passes.
-template <int LOG2L, int LOG2NS = 0>
-__device__ __forceinline__ void fft_inplace(float2 *buf, const float2 *__restrict__ tw) {
-    if constexpr (LOG2NS < LOG2L) {
-        constexpr int LOG2R = (LOG2L - LOG2NS) % 3 != 0 ? 2 : 3;
-        stockham_pass<LOG2R, LOG2L, LOG2NS>(buf, tw);
-        fft_inplace<LOG2L, LOG2NS + LOG2R>(buf, tw);
-    }
-}
 
 template <typename T, int LOG2L>
 __global__ __launch_bounds__(kFilterThreads) void filter_rows(const T *__restrict__ y, T *__restrict__ out,
@@ -131,7 +43,7 @@ __global__ __launch_bounds__(kFilterThreads) void filter_rows(const T *__restric
         buf[k] = v;
     }
     __syncthreads();
-    fft_inplace<LOG2L>(buf, tw);
+    fft_multi<kFilterThreads, 1, L, LOG2L>(buf, tw);
     // conj(X) H: the inverse transform is conj(FFT(conj(H X))) / L
     for (int k = threadIdx.x; k < L; k += kFilterThreads) {
         const float h = H[k];
@@ -139,7 +51,7 @@ __global__ __launch_bounds__(kFilterThreads) void filter_rows(const T *__restric
         buf[k] = make_float2(x.x * h, -x.y * h);
     }
     __syncthreads();
-    fft_inplace<LOG2L>(buf, tw);
+    fft_multi<kFilterThreads, 1, L, LOG2L>(buf, tw);
     const float f = scale / (float)L;
     T *o0 = out + r0 * D;
     T *o1 = out + (r0 + 1) * D;

@@ -60,4 +60,11 @@ int validate(const radon_geometry_t *g);
 PlanKey make_key(const radon_geometry_t *g, int device);
 int get_plan(const radon_geometry_t *g, hipStream_t stream, Plan **out);
 
+// Library-owned workspace of one (device, stream), grown to `need` bytes outside stream
+// capture (a buffer it replaces stays allocated until radon_release_plans); *have
+// receives its size, which may be smaller than need under capture.  NULL on failure.
+void *stream_workspace(hipStream_t stream, size_t need, size_t *have);
+// Frees the shearlet plans (called by radon_release_plans after a device sync).
+void release_shearlet_plans();
+
 }  // namespace radon

@@ -277,8 +277,58 @@ static int lifetime_mode(std::vector<Geo> &geos) {
     return fails ? 1 : 0;
 }
 
+// "shearlet" mode: argv[1] holds lines "W H batch dtype J alpha_0 .. alpha_{J-1}"; for
+// each, random images x and random coefficients d (seeded), the forward transform of x
+// and the adjoint of d through the emulated kernels; writes x, forward(x), d and
+// adjoint(d) (FP64, storage-rounded inputs) to argv[3].
+static int shearlet_mode(const char *spec, const char *path) {
+    FILE *f = std::fopen(spec, "r");
+    FILE *out = std::fopen(path, "wb");
+    if (!f || !out) return 2;
+    std::mt19937 rng(11);
+    std::normal_distribution<float> normal;
+    int fails = 0, W, H, B, dt, J;
+    while (std::fscanf(f, "%d %d %d %d %d", &W, &H, &B, &dt, &J) == 5) {
+        std::vector<double> alphas(J);
+        for (double &a : alphas)
+            if (std::fscanf(f, "%lf", &a) != 1) return 2;
+        radon_shearlet_t sh{W, H, J, 0, alphas.data()};
+        const int M = radon_shearlet_channels(&sh);
+        if (M <= 0) return 2;
+        const size_t es = esize(dt), nx = (size_t)B * W * H, nc = nx * M;
+        void *x = dev_alloc(nx * es), *c = dev_alloc(nc * es), *d = dev_alloc(nc * es), *y = dev_alloc(nx * es);
+        for (size_t i = 0; i < nx; ++i) from_float(x, i, normal(rng), dt);
+        for (size_t i = 0; i < nc; ++i) from_float(d, i, normal(rng), dt);
+        std::fprintf(stderr, "[emu] shearlet %dx%d batch %d dtype %d channels %d\n", W, H, B, dt, M);
+        int rc = radon_shearlet_forward(&sh, x, c, B, dt, nullptr);
+        if (!rc) rc = radon_shearlet_adjoint(&sh, d, y, B, dt, nullptr);
+        if (rc) {
+            std::printf("shearlet %dx%d status %d\n", W, H, rc);
+            ++fails;
+        }
+        std::vector<double> buf(nc);
+        auto dump = [&](const void *p, size_t n) {
+            for (size_t i = 0; i < n; ++i) buf[i] = rc ? 0.0 : to_double(p, i, dt);
+            std::fwrite(buf.data(), sizeof(double), n, out);
+        };
+        dump(x, nx);
+        dump(c, nc);
+        dump(d, nc);
+        dump(y, nx);
+        std::free(x);
+        std::free(c);
+        std::free(d);
+        std::free(y);
+    }
+    std::fclose(f);
+    std::fclose(out);
+    std::printf("summary shearlet failures %d\n", fails);
+    return fails ? 1 : 0;
+}
+
 int main(int argc, char **argv) {
     if (argc < 2) return 2;
+    if (argc > 3 && std::strcmp(argv[2], "shearlet") == 0) return shearlet_mode(argv[1], argv[3]);
     const bool batched = argc > 2 && std::strcmp(argv[2], "batched") == 0;
     const bool filtering = argc > 3 && std::strcmp(argv[2], "filter") == 0;
     const bool solving = argc > 5 && std::strcmp(argv[2], "solver") == 0;
