@@ -114,26 +114,76 @@ def support_samples(n, angles, det_count, spacing, step, beam="parallel", S=0.0,
     return float(cnt.sum())
 
 
-def cpu_baseline(case_angles, n, det_count, x_np, max_threads=16):
-    """FP64 oracle (forward + scatter backprojection) on the host cores, on a bounded
-    sample: the first `threads` images of the batch at all angles."""
+def cpu_model():
+    """The host CPU's model name (first "model name" line of /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _oracle_proj_rate(og, x, batch_angles):
+    """Projections/s of the FP64 oracle's forward + backprojection of the images x."""
     import oracle
-    threads = oracle.num_threads()
-    k = max(1, min(threads, max_threads, x_np.shape[0]))
-    og = oracle.Geometry(n, case_angles, det_count, 1.0)
-    xs = x_np[:k].astype(np.float64)
     t0 = time.perf_counter()
-    y = oracle.forward(og, xs)
+    y = oracle.forward(og, x)
     t1 = time.perf_counter()
     oracle.backproject(og, y)
     t2 = time.perf_counter()
-    proj = k * len(case_angles)
+    return batch_angles / (t2 - t0), t1 - t0, t2 - t1
+
+
+def cpu_baseline(angles, n, det_count, x_np):
+    """The FP64 oracle (forward ray loop + scatter backprojection, OpenMP) on the host:
+    the headline on a bounded sample, on every thread the oracle has and on one thread,
+    plus the single 64^2 image, the 16 x 256^2 batch and the 200 uneven jobs in full."""
+    import oracle
+    from paper_2009_14788_amd import inputs
+    threads = oracle.num_threads()
+    og = oracle.Geometry(n, angles, det_count, 1.0)
+    k = 8                                                      # images of the headline sample
+    rate_all, tf, tb = _oracle_proj_rate(og, x_np[:k].astype(np.float64), k * len(angles))
+    # one thread: one image at every 8th angle (the per-projection work does not depend
+    # on the angle's position in the list)
+    sub = np.asarray(angles)[::8]
+    og1 = oracle.Geometry(n, sub, det_count, 1.0)
+    oracle.set_num_threads(1)
+    try:
+        rate_one, _, _ = _oracle_proj_rate(og1, x_np[:1].astype(np.float64), len(sub))
+        w0 = inputs.WORKLOADS["single64"]
+        og0 = oracle.Geometry(64, w0.angles(), 91, 1.0)
+        x0 = inputs.phantom(64, 10, [0, 0])[0][None].astype(np.float64)
+        rate0_one, _, _ = _oracle_proj_rate(og0, x0, 64)
+    finally:
+        oracle.set_num_threads(threads)
+    rate0_all, _, _ = _oracle_proj_rate(og0, x0, 64)
+    w1 = inputs.WORKLOADS["batch16_256"]
+    og1 = oracle.Geometry(256, w1.angles(), 363, 1.0)
+    rate1, _, _ = _oracle_proj_rate(og1, inputs.phantom_batch(1, 16, 256).astype(np.float64), 16 * 256)
+    jobs = inputs.uneven_jobs(200)
+    t0 = time.perf_counter()
+    for j in jobs:
+        ogj = oracle.Geometry(j.n, j.angles(), j.det_count, 1.0)
+        oracle.backproject(ogj, oracle.forward(ogj, inputs.uneven_phantom(j)[None].astype(np.float64)))
+    t3 = time.perf_counter() - t0
     return {
-        "value": proj / (t2 - t0), "unit": "projections/s", "cores": int(min(threads, k)),
-        "kind": "oracle",
-        "sample": f"{k} of the 128 images, all {len(case_angles)} angles, forward + backprojection "
-                  f"(FP64, OpenMP over images x angles / images); forward {t1 - t0:.2f} s, "
-                  f"backprojection {t2 - t1:.2f} s",
+        "value": round(rate_all, 1), "unit": "projections/s", "cores": int(threads), "kind": "oracle",
+        "sample": f"{k} of the 128 images at all {len(angles)} angles, forward + backprojection "
+                  f"(FP64; forward {tf:.2f} s, backprojection {tb:.2f} s on {threads} threads)",
+        "threads": int(threads), "cpu_count": os.cpu_count(), "cpu_model": cpu_model(),
+        "all_core_proj_s": round(rate_all, 1),
+        "single_thread_proj_s": round(rate_one, 1),
+        "single_thread_sample": f"1 image at {len(sub)} of the 720 angles (every 8th)",
+        "workloads_full": {
+            "single64": {"all_core_proj_s": round(rate0_all, 1), "single_thread_proj_s": round(rate0_one, 1)},
+            "batch16_256": {"all_core_proj_s": round(rate1, 1)},
+            "uneven200": {"all_core_proj_s": round(sum(j.n_angles for j in jobs) / t3, 1),
+                          "seconds": round(t3, 2)},
+        },
     }
 
 
@@ -255,14 +305,23 @@ def main():
              "method": "radon_measure_peaks: v_fmac_f32 chains (packed FP32 off) and conflict-free "
                        "ds_read_b128 streams on this GPU, best of 3 runs"}
 
-    # sampled correctness of this very output against the oracle (8 rays)
+    # correctness of this very output against the oracle: whole images 0 and 127 (the
+    # first and last lane of the image groups) of the forward, and of the backprojection
+    # (same launch shape) of seeded N(0,1) sinograms
     import oracle
     og = oracle.Geometry(N, angles, D, 1.0)
-    rng = np.random.default_rng(0)
-    idx = np.stack([rng.integers(0, B, 8), rng.integers(0, A, 8), rng.integers(0, D, 8)], 1)
-    yg = y[idx[:, 0], idx[:, 1], idx[:, 2]].double().cpu().numpy()
-    yr = oracle.forward_rays(og, x_np, idx)
+    sel = [0, B - 1]
+    yg = y[sel].double().cpu().numpy()
+    yr = oracle.forward(og, x_np[sel].astype(np.float64))
     err = float(np.linalg.norm(yg - yr) / np.linalg.norm(yr))
+    err_max = float(np.abs(yg - yr).max() / np.abs(yr).max())
+    ys_np = inputs.randn((B, A, D), 2024)
+    xb = op.backprojection_raw(torch.from_numpy(ys_np).to(dev))
+    xg = xb[sel].double().cpu().numpy()
+    del xb
+    xr = oracle.backproject(og, ys_np[sel].astype(np.float64))
+    err_bp = float(np.linalg.norm(xg - xr) / np.linalg.norm(xr))
+    err_bp_max = float(np.abs(xg - xr).max() / np.abs(xr).max())
 
     out = {
         "metric": METRIC, "value": round(proj_s, 1), "unit": "projections/s", "n_gpus": 1,
@@ -275,13 +334,16 @@ def main():
         "rays_per_s": round(rays_s, 1), "hbm_gbs_algorithmic": round(hbm_gbs, 2),
         "hbm_frac": round(hbm_gbs / PEAK_HBM_GBS, 5),
         "forward_ms": round(fwd_ms, 4), "backprojection_ms": round(bp_ms, 4),
-        "sampled_rel_l2_vs_oracle": err,
+        "fwd_rel_l2_vs_oracle": err, "fwd_max_abs_over_max_ref": err_max,
+        "bp_rel_l2_vs_oracle": err_bp, "bp_max_abs_over_max_ref": err_bp_max,
+        "error_sample": "whole images 0 and 127; backprojection of seeded N(0,1) sinograms",
         "roofline": roof,
         "directions": directions,
         "device_peaks": peaks,
     }
     if not args.quick:
-        out["workloads"] = variants(op, x, x_np, B, A, D)
+        ref = {"sel": sel, "y": yr, "ys": ys_np, "xb": xr}
+        out["workloads"] = variants(op, x, x_np, B, A, D, ref)
     if args.copy_calibration:
         # a plain elementwise kernel that reads 1 GiB once and writes 1 GiB once
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
@@ -338,7 +400,33 @@ def _sampled_err(og, x_np, y_dev, n=16, seed=0):
     return float(np.linalg.norm(yg - yr) / np.linalg.norm(yr))
 
 
-def variants(op, x, x_np, B, A, D):
+def _bp_err(og, bp_fn, sino_shape, dt, seed, n_pix=16):
+    """Relative L2 error of n_pix sampled backprojection outputs of seeded N(0,1)
+    sinograms (stored in dt) against the FP64 oracle on the same FP32 values."""
+    import oracle
+    import torch
+    ys = inputs_mod().randn(sino_shape, seed)
+    xb = bp_fn(torch.from_numpy(ys).cuda().to(dt))
+    Bn, N = xb.shape[0], xb.shape[-1]
+    rng = np.random.default_rng(seed)
+    idx = np.stack([rng.integers(0, Bn, n_pix), rng.integers(0, N, n_pix), rng.integers(0, N, n_pix)], 1)
+    got = xb[idx[:, 0], idx[:, 1], idx[:, 2]].double().cpu().numpy()
+    ref = oracle.backproject_pixels(og, ys.astype(np.float64), idx)
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def inputs_mod():
+    from paper_2009_14788_amd import inputs
+    return inputs
+
+
+def _frac(samples, ms):
+    """Fraction of the FP32 vector peak reached by forward + backprojection: 8 flop per
+    image-sample in each direction."""
+    return round(16.0 * samples / (ms * 1e-3) / (PEAK_FP32_TFLOPS * 1e12), 4)
+
+
+def variants(op, x, x_np, B, A, D, ref):
     """The other workloads and forms, each timed on this GPU with its error stated:
     16-bit storage and the differentiable step on the headline batch; the single 64^2
     image (latency, eager and graph-replayed); the 16 x 256^2 batch; 200 uneven jobs
@@ -356,19 +444,30 @@ def variants(op, x, x_np, B, A, D):
     res = {}
     og = oracle.Geometry(op.resolution, op.angles, D, 1.0)
 
-    # -- 16-bit storage on the headline batch
+    samples128 = support_samples(op.resolution, op.angles, D, 1.0, 1.0) * B
+
+    # -- 16-bit storage on the headline batch (errors on whole images 0 and 127 against
+    #    the oracle on the original FP32 values, storage rounding included)
     y32 = op.forward_raw(x)
+    sel = ref["sel"]
+    ys16 = torch.from_numpy(ref["ys"]).cuda()
     for name, dt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
         xh = x.to(dt)
         op.prepare(dt, B)
         ms = _timed(lambda: op.backprojection_raw(op.forward_raw(xh)))
         yh = op.forward_raw(xh)
+        yg = yh[sel].double().cpu().numpy()
+        xbh = op.backprojection_raw(ys16.to(dt))[sel].double().cpu().numpy()
         res[f"batch128_512_{name}"] = {
             "ms_per_step": round(ms, 4), "projections_per_s": round(B * A / (ms * 1e-3), 1),
+            "roofline_frac_fp32_peak": _frac(samples128, ms),
             "fwd_rel_l2_vs_f32_path": float((yh.float() - y32).norm() / y32.norm()),
-            "fwd_rel_l2_vs_oracle_sampled": _sampled_err(og, x_np, yh, seed=1)}
+            "fwd_rel_l2_vs_oracle": float(np.linalg.norm(yg - ref["y"]) / np.linalg.norm(ref["y"])),
+            "bp_rel_l2_vs_oracle": float(np.linalg.norm(xbh - ref["xb"]) / np.linalg.norm(ref["xb"])),
+            "error_sample": "whole images 0 and 127"}
         print(f"[bench] {name}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
         del xh, yh
+    del ys16
 
     # -- differentiable step: loss ||R x - y||^2 (FP64 reduction), backward via R^T
     rng_noise = np.random.default_rng([2, 10 ** 6])
@@ -449,8 +548,9 @@ def variants(op, x, x_np, B, A, D):
     og0 = oracle.Geometry(64, w0.angles(), 91, 1.0)
     e0 = float(np.linalg.norm(op0.forward_raw(x0)[0].double().cpu().numpy() - oracle.forward(og0, x0_np[0].astype(np.float64)))
                / np.linalg.norm(oracle.forward(og0, x0_np[0].astype(np.float64))))
+    e0b = _bp_err(og0, lambda t: op0.backprojection_raw(t), (1, 64, 91), torch.float32, 5, n_pix=64)
     res["single64"] = {"us_per_step_eager": round(eager * 1e3, 2), "us_per_step_graph": round(graph * 1e3, 2),
-                       "fwd_rel_l2_vs_oracle": e0}
+                       "fwd_rel_l2_vs_oracle": e0, "bp_rel_l2_vs_oracle_sampled": e0b}
 
     # -- 16 x 256^2
     w1 = inputs.WORKLOADS["batch16_256"]
@@ -459,13 +559,18 @@ def variants(op, x, x_np, B, A, D):
     x1 = torch.from_numpy(x1_np).cuda()
     op1.prepare(torch.float32, 16)
     ms = _timed(lambda: op1.backprojection_raw(op1.forward_raw(x1)), reps=20)
+    og1 = oracle.Geometry(256, w1.angles(), 363, 1.0)
     res["batch16_256"] = {"ms_per_step": round(ms, 4), "projections_per_s": round(16 * 256 / (ms * 1e-3), 1),
-                          "fwd_rel_l2_vs_oracle_sampled": _sampled_err(oracle.Geometry(256, w1.angles(), 363, 1.0), x1_np, op1.forward_raw(x1), seed=2)}
+                          "roofline_frac_fp32_peak": _frac(support_samples(256, w1.angles(), 363, 1.0, 1.0) * 16, ms),
+                          "fwd_rel_l2_vs_oracle_sampled": _sampled_err(og1, x1_np, op1.forward_raw(x1), seed=2),
+                          "bp_rel_l2_vs_oracle_sampled": _bp_err(og1, lambda t: op1.backprojection_raw(t),
+                                                                 (16, 256, 363), torch.float32, 6)}
 
     # -- 200 uneven jobs in one persistent launch
     jobs = inputs.uneven_jobs(200)
     ops = [Radon(j.n, j.angles(), j.det_count, 1.0) for j in jobs]
     proj = sum(j.n_angles for j in jobs)
+    samples_uneven = sum(support_samples(j.n, j.angles(), j.det_count, 1.0, 1.0) for j in jobs)
     br = BatchedRadon(ops)
     for name, dt in (("f32", torch.float32), ("f16", torch.float16)):
         xs = [torch.from_numpy(inputs.uneven_phantom(j)[None]).cuda().to(dt) for j in jobs]
@@ -479,35 +584,61 @@ def variants(op, x, x_np, B, A, D):
         ms_e = _timed(step, reps=10)
         ms_g = _graph_ms(step, reps=10)
         ms_seq = _timed(lambda: [o.backprojection_raw(o.forward_raw(xx)) for o, xx in zip(ops, xs)], reps=3)
-        step()
-        errs = []
-        for k in (0, 1, 2):
+        # errors of whole jobs: every 20th job, forward of its phantom and backprojection
+        # of seeded N(0,1) sinograms, in the same persistent launches
+        gs = [torch.from_numpy(inputs.randn((1,) + o.sinogram_shape, 900 + i)).cuda().to(dt)
+              for i, o in enumerate(ops)]
+        br.forward(xs, out=ys)
+        br.backprojection(gs, out=bs)
+        ef = eb = 0.0
+        for k in range(0, len(jobs), 20):
             jk = jobs[k]
             ogk = oracle.Geometry(jk.n, jk.angles(), jk.det_count, 1.0)
-            errs.append(_sampled_err(ogk, inputs.uneven_phantom(jk)[None].astype(np.float64), ys[k], seed=3 + k))
+            yr = oracle.forward(ogk, inputs.uneven_phantom(jk)[None].astype(np.float64))
+            ef = max(ef, float(np.linalg.norm(ys[k].double().cpu().numpy() - yr) / np.linalg.norm(yr)))
+            br_ = oracle.backproject(ogk, gs[k].float().double().cpu().numpy())
+            eb = max(eb, float(np.linalg.norm(bs[k].double().cpu().numpy() - br_) / np.linalg.norm(br_)))
         res[f"uneven200_{name}"] = {
             "ms_per_step_eager": round(ms_e, 4), "ms_per_step_graph": round(ms_g, 4),
             "ms_per_step_one_call_per_job": round(ms_seq, 4),
             "projections_per_s_graph": round(proj / (ms_g * 1e-3), 1),
-            "fwd_rel_l2_vs_oracle_sampled_jobs0to2": max(errs)}
+            "roofline_frac_fp32_peak_graph": _frac(samples_uneven, ms_g),
+            "samples_per_direction": samples_uneven,
+            "fwd_rel_l2_vs_oracle_worst_job": ef, "bp_rel_l2_vs_oracle_worst_job": eb,
+            "error_sample": "every 20th job, whole images"}
         print(f"[bench] uneven200 {name}: eager {ms_e:.3f} graph {ms_g:.3f} per-job {ms_seq:.3f} ms",
               file=sys.stderr, flush=True)
         del xs, ys, bs
 
-    # -- fan beam 64 x 512^2, 16-bit storage; unrolled GD differentiated end to end
+    # -- fan beam 64 x 512^2, 16-bit storage; unrolled GD differentiated end to end.  The
+    #    GD error is stated on image 0 against the oracle GD: the oracle's projection of
+    #    the phantom as data (rounded to the storage type), a fixed step 0.95 / 5.2e5 shared
+    #    by both sides (5.2e5 rounds up the power-iteration estimate of ||R||^2), per
+    #    iteration, and the gradient of ||x_10 - x_true||^2 with respect to the data.
+    from oracle import solvers as osolvers
     w4 = inputs.WORKLOADS["fan64_512"]
     op4 = RadonFanbeam(512, w4.angles(), 1000.0, 500.0, 1024, 1.5)
     x4_np = inputs.phantom_batch(4, 64, 512)
     og4 = oracle.Geometry(512, w4.angles(), 1024, 1.5, beam=oracle.FANBEAM, source_distance=1000.0,
                           det_distance=500.0)
+    samples_fan = support_samples(512, w4.angles(), 1024, 1.5, 1.0, "fan", 1000.0, 500.0) * 64
     lam = power_iteration(op4)
     alpha = 1.0 / lam
+    alpha_check = 0.95 / 5.2e5
+    print("[bench] fan GD oracle (image 0)", file=sys.stderr, flush=True)
+    xt0 = x4_np[:1].astype(np.float64)
+    y0_ref = oracle.forward(og4, xt0)
+    it_ref, grad_ref = osolvers.unrolled_gd_grad(lambda v: oracle.forward(og4, v),
+                                                 lambda r: oracle.backproject(og4, r), y0_ref,
+                                                 alpha_check, 10, xt0)
+    from paper_2009_14788_amd.solvers import gd_step
     for name, dt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
         x4 = torch.from_numpy(x4_np).cuda().to(dt)
         op4.prepare(dt, 64)
         ms = _timed(lambda: op4.backprojection_raw(op4.forward_raw(x4), scale=alpha), reps=5)
         y4 = op4.forward_raw(x4)
         e4 = _sampled_err(og4, x4_np, y4, seed=7)
+        e4b = _bp_err(og4, lambda t: op4.backprojection_raw(t), (64, 1024, 1024), dt, 8)
         yreq = y4.clone().requires_grad_(True)
 
         def gd_backward():
@@ -516,13 +647,65 @@ def variants(op, x, x_np, B, A, D):
             ((xk.float() - x4.float()) ** 2).sum().backward()
 
         ms_gd = _timed(gd_backward, reps=2)
+        # GD errors on image 0 (same batch of 64, data of image 0 from the oracle)
+        ye = y4.clone()
+        ye[0] = torch.from_numpy(y0_ref[0].astype(np.float32)).cuda().to(dt)
+        errs = []
+        with torch.no_grad():
+            xk = torch.zeros_like(x4)
+            for k in range(10):
+                xk = gd_step(op4, xk, ye, alpha_check)
+                errs.append(float(np.linalg.norm(xk[0].double().cpu().numpy() - it_ref[k][0])
+                                  / np.linalg.norm(it_ref[k][0])))
+        yr = ye.clone().requires_grad_(True)
+        xk = unrolled_gd(op4, yr, alpha_check, iters=10, checkpoint=True)
+        ((xk.float() - x4.float()) ** 2).sum().backward()
+        g0 = yr.grad[0].double().cpu().numpy()
+        e_grad = float(np.linalg.norm(g0 - grad_ref[0]) / np.linalg.norm(grad_ref[0]))
         res[f"fan64_512_{name}"] = {
             "ms_per_step": round(ms, 4), "projections_per_s": round(64 * 1024 / (ms * 1e-3), 1),
-            "fwd_rel_l2_vs_oracle_sampled": e4, "alpha": alpha,
-            "unrolled_gd10_fwd_bwd_ms": round(ms_gd, 3)}
-        print(f"[bench] fan {name}: {ms:.3f} ms/step, unrolled GD fwd+bwd {ms_gd:.1f} ms",
-              file=sys.stderr, flush=True)
-        del x4, y4, yreq
+            "roofline_frac_fp32_peak": _frac(samples_fan, ms),
+            "fwd_rel_l2_vs_oracle_sampled": e4, "bp_rel_l2_vs_oracle_sampled": e4b, "alpha": alpha,
+            "unrolled_gd10_fwd_bwd_ms": round(ms_gd, 3),
+            "gd10_iterate_rel_l2_vs_oracle": [round(e, 6) for e in errs],
+            "gd10_grad_y_rel_l2_vs_oracle": e_grad,
+            "gd_error_sample": f"image 0, step {alpha_check:.6e} on both sides"}
+        print(f"[bench] fan {name}: {ms:.3f} ms/step, unrolled GD fwd+bwd {ms_gd:.1f} ms, "
+              f"GD error x10 {errs[-1]:.2e} grad {e_grad:.2e}", file=sys.stderr, flush=True)
+        del x4, y4, yreq, ye, yr
+
+    # -- alpha-shearlet transform (Sec. 3.2 configuration: 512^2, alpha = 0.5, 5 scales,
+    #    59 channels), a batch of 16 phantoms: forward, adjoint, and the error of image 0's
+    #    coefficients against the FP64 oracle and of the reconstruction
+    from oracle import shearlets as osh
+    from paper_2009_14788_amd.shearlet import ShearletTransform
+    sh = ShearletTransform(512, 512, [0.5] * 5)
+    Bs = 16
+    xs_np = inputs.phantom_batch(2, Bs, 512)
+    xs = torch.from_numpy(xs_np).cuda()
+    sh.prepare(Bs)
+    ms_f = _timed(lambda: sh.forward_raw(xs), reps=5)
+    cs = sh.forward_raw(xs)
+    ms_a = _timed(lambda: sh.backward_raw(cs), reps=5)
+    rec = sh.backward_raw(cs)
+    psi = osh.filters(512, 512, [0.5] * 5)
+    c0 = cs[0].double().cpu().numpy()
+    c0r = osh.forward(xs_np[0].astype(np.float64), psi)
+    rec_np = rec.double().cpu().numpy()
+    bytes_dir = 4.0 * Bs * 512 * 512 * (1 + sh.channels)
+    res["shearlet_512_a05_s5"] = {
+        "batch": Bs, "channels": sh.channels,
+        "forward_ms": round(ms_f, 4), "adjoint_ms": round(ms_a, 4),
+        "images_per_s_forward": round(Bs / (ms_f * 1e-3), 1),
+        "hbm_gbs_algorithmic_forward": round(bytes_dir / (ms_f * 1e-3) / 1e9, 1),
+        "hbm_frac_forward": round(bytes_dir / (ms_f * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+        "hbm_frac_adjoint": round(bytes_dir / (ms_a * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+        "coeff_rel_l2_vs_oracle_image0": float(np.linalg.norm(c0 - c0r) / np.linalg.norm(c0r)),
+        "reconstruction_rel_l2": float(np.linalg.norm(rec_np - xs_np) / np.linalg.norm(xs_np)),
+        "note": "algorithmic bytes per direction: the images and the 59-channel coefficients, FP32"}
+    print(f"[bench] shearlet 16 x 512^2: forward {ms_f:.3f} ms, adjoint {ms_a:.3f} ms",
+          file=sys.stderr, flush=True)
+    del cs, rec, xs
     return res
 
 
