@@ -588,7 +588,7 @@ static int build_batch_table(const std::vector<Plan *> &plans, const radon_job_t
                 const size_t need = !p->geom.fan
                     ? (size_t)planes * kBpAngles * kBpWinPar * sizeof(uint4)
                     : (size_t)planes * kBpAnglesFan * j.window * sizeof(uint4) +
-                          (size_t)kBpAnglesFan * j.window * sizeof(double4);
+                          (size_t)kBpAnglesFan * j.window * sizeof(float4);
                 lds = std::max(lds, need);
                 // instruction estimate per (pixel, angle): candidate search + 3 or NB FMAs per image
                 const int nb = p->geom.fan ? j.bins : 3;

@@ -241,7 +241,7 @@ static hipError_t launch_bp_tiled(const Geom &g, const BpWork &work, const Launc
         }
     } else {
         const size_t lds = (size_t)PLANES * kBpAnglesFan * W * sizeof(uint4) +
-                           (size_t)kBpAnglesFan * W * sizeof(double4);
+                           (size_t)kBpAnglesFan * W * sizeof(float4);
         if (work.bins <= 4) {
             if (il)
                 hipLaunchKernelGGL((bp_tiled_fan_il<T, BC, 4, 3>), grid, dim3(256), lds, s, g, yi,

@@ -489,44 +489,51 @@ __device__ __forceinline__ void bp_tile_par(const Geom &g, int tile, const Image
 
 // The angles al of one staged block with NBX candidate bins per pixel (NBX <= the
 // plan's bin count: the caller checked that NBX bins cover every footprint of the tile
-// at these angles).
+// at these angles).  FP32 throughout: the first candidate bin comes from the projection
+// of the pixel centre and its first-order half-width with a margin (0.05 bins + 1%)
+// far above FP32 rounding (~1e-4 bins); each bin's ray is a lattice point near the
+// tile and its step, in tile coordinates (|values| <= ~50 px), so the offsets of the
+// candidate samples from the pixel carry ~1e-6 pixel of rounding, as in the parallel
+// kernel.
 template <typename T, int BC, int NBX, int NK>
 __device__ __forceinline__ void fan_angle_block(const Geom &g, int a0, int na, int W, const int *wlo_s,
-                                                const double4 *rays_s, const uint4 *lds, int per_plane,
-                                                double qx, double qy, int c, int r, double is2,
+                                                const float4 *rays_s, const uint4 *lds, int per_plane,
+                                                float qx, float qy, float lx, float ly, float is2,
                                                 float *part) {
     constexpr int CH = Chunk<T>::kImages;
     constexpr int PLANES = BC / CH;
+    const float sd = (float)g.sd, k_sde = (float)(g.sde * g.inv_spacing), hd = (float)g.half_d;
     for (int al = 0; al < na; ++al) {
-        const double2 cs = g.trig[a0 + al];
+        const double2 cs64 = g.trig[a0 + al];
+        const float cx = (float)cs64.x, sy = (float)cs64.y;
         // detector coordinate of the pixel centre and its gradient (bins per pixel)
-        const double pu = fma(qx, cs.x, qy * cs.y), pv = fma(-qx, cs.y, qy * cs.x);
-        const double den = 1.0 / (g.sd + pv);
-        const double sb = g.sde * pu * den * g.inv_spacing + g.half_d;
-        const double gsx = g.sde * (cs.x * (g.sd + pv) + pu * cs.y) * den * den * g.inv_spacing;
-        const double gsy = g.sde * (cs.y * (g.sd + pv) - pu * cs.x) * den * den * g.inv_spacing;
-        const double hb = fabs(gsx) + fabs(gsy);
-        const int dfirst = (int)ceil(sb - hb * 1.01 - 0.05);
+        const float pu = fmaf(qx, cx, qy * sy), pv = fmaf(-qx, sy, qy * cx);
+        const float near = sd + pv;
+        const float den = 1.0f / near;
+        const float sb = fmaf(k_sde * pu, den, hd);
+        const float k2 = k_sde * den * den;
+        const float gsx = k2 * fmaf(cx, near, pu * sy), gsy = k2 * fmaf(sy, near, -pu * cx);
+        const float hb = fabsf(gsx) + fabsf(gsy);
+        const int dfirst = (int)ceilf(sb - hb * 1.01f - 0.05f);
         int lb = dfirst - wlo_s[al];
         lb = min(max(lb, 0), W - NBX);              // memory safety; real pixels are inside
         float wgt[NBX];
 #pragma unroll
         for (int i = 0; i < NBX; ++i) {
-            const double4 rp = rays_s[al * W + lb + i];
-            const double ex = rp.x - (double)c, ey = rp.y - (double)r;   // F - Q
-            const double kc = -fma(ex, rp.z, ey * rp.w) * is2;           // pixel along the ray
-            const double hk = (fabs(rp.z) + fabs(rp.w)) * is2;
-            const double k0 = floor(kc - hk);
-            float dx = (float)fma(k0 + 1.0, rp.z, ex), dy = (float)fma(k0 + 1.0, rp.w, ey);
-            const float sx = (float)rp.z, sy = (float)rp.w;
+            const float4 rp = rays_s[al * W + lb + i];
+            const float ex = rp.x - lx, ey = rp.y - ly;                  // lattice point - pixel
+            const float kc = -fmaf(ex, rp.z, ey * rp.w) * is2;           // pixel along the ray
+            const float hk = (fabsf(rp.z) + fabsf(rp.w)) * is2;
+            const float k1 = floorf(kc - hk) + 1.0f;
+            float dx = fmaf(k1, rp.z, ex), dy = fmaf(k1, rp.w, ey);
             float w = 0.0f;
 #pragma unroll
             for (int jj = 0; jj < NK; ++jj) {
                 const float tx = __builtin_amdgcn_fmed3f(1.0f - fabsf(dx), 0.0f, 1.0f);
                 const float ty = __builtin_amdgcn_fmed3f(1.0f - fabsf(dy), 0.0f, 1.0f);
                 w = fmaf(tx, ty, w);
-                dx += sx;
-                dy += sy;
+                dx += rp.z;
+                dy += rp.w;
             }
             wgt[i] = w;
         }
@@ -561,10 +568,14 @@ __device__ __forceinline__ void bp_tile_fan(const Geom &g, int tile, const Image
     const int tiles_x = (n + kBpTile - 1) / kBpTile;
     const int tx0 = (tile % tiles_x) * kBpTile, ty0 = (tile / tiles_x) * kBpTile;
     const int c = tx0 + (threadIdx.x % kBpTile), r = ty0 + (threadIdx.x / kBpTile);
-    const double qx = (double)c - g.cn, qy = (double)r - g.cn;
+    const float qx = (float)((double)c - g.cn), qy = (float)((double)r - g.cn);
+    const float lx = (float)(c - tx0), ly = (float)(r - ty0);
     const int per_plane = kBpAnglesFan * W;
-    double4 *rays_s = reinterpret_cast<double4 *>(lds + PLANES * per_plane);
-    const double is2 = g.inv_step * g.inv_step;
+    float4 *rays_s = reinterpret_cast<float4 *>(lds + PLANES * per_plane);
+    const float is2 = (float)(g.inv_step * g.inv_step);
+    // tile centre (index coordinates): each staged ray is moved to its lattice point
+    // nearest to it
+    const double tcx = tx0 + 0.5 * (kBpTile - 1), tcy = ty0 + 0.5 * (kBpTile - 1);
 
     float acc[BC];
 #pragma unroll
@@ -599,10 +610,17 @@ __device__ __forceinline__ void bp_tile_fan(const Geom &g, int tile, const Image
         for (int p = threadIdx.x; p < na * W; p += 256) {
             const int al = p / W, j = p - al * W;
             const int d = wlo_s[al] + j;
-            const bool inside = (unsigned)d < (unsigned)D;
             // a bin outside the detector gets a ray far from every pixel (weight 0)
-            rays_s[al * W + j] = inside ? g.rays[(size_t)(a0 + al) * D + d]
-                                        : make_double4(-1e9, -1e9, 0.0, 0.0);
+            float4 v = make_float4(-1e9f, -1e9f, 0.0f, 0.0f);
+            if ((unsigned)d < (unsigned)D) {
+                // the ray's samples are o + k s (index coordinates, FP64): the lattice
+                // point nearest the tile centre, relative to the tile origin, in FP32
+                const double4 rp = g.rays[(size_t)(a0 + al) * D + d];
+                const double k0 = rint(fma(tcx - rp.x, rp.z, (tcy - rp.y) * rp.w) * g.inv_step * g.inv_step);
+                v = make_float4((float)(fma(k0, rp.z, rp.x) - tx0), (float)(fma(k0, rp.w, rp.y) - ty0),
+                                (float)rp.z, (float)rp.w);
+            }
+            rays_s[al * W + j] = v;
         }
         int nb_block = 0;
         for (int al = 0; al < na; ++al) nb_block = max(nb_block, nb_s[al]);
@@ -617,10 +635,10 @@ __device__ __forceinline__ void bp_tile_fan(const Geom &g, int tile, const Image
             for (int i = 0; i < BC; ++i) part[i] = 0.0f;
         }
         if (NB > 4 && nb_block <= 4)
-            fan_angle_block<T, BC, 4, NK>(g, a0, na, W, wlo_s, rays_s, lds, per_plane, qx, qy, c, r,
+            fan_angle_block<T, BC, 4, NK>(g, a0, na, W, wlo_s, rays_s, lds, per_plane, qx, qy, lx, ly,
                                           is2, part);
         else
-            fan_angle_block<T, BC, NB, NK>(g, a0, na, W, wlo_s, rays_s, lds, per_plane, qx, qy, c, r,
+            fan_angle_block<T, BC, NB, NK>(g, a0, na, W, wlo_s, rays_s, lds, per_plane, qx, qy, lx, ly,
                                            is2, part);
         if (kTwoLevel) {
 #pragma unroll

@@ -36,6 +36,8 @@ struct double2 { double x, y; };
 struct double4 { double x, y, z, w; };
 struct float2 { float x, y; };
 inline float2 make_float2(float a, float b) { return {a, b}; }
+struct float4 { float x, y, z, w; };
+inline float4 make_float4(float a, float b, float c, float d) { return {a, b, c, d}; }
 inline unsigned __brev(unsigned v) {
     unsigned r = 0;
     for (int i = 0; i < 32; ++i) r |= ((v >> i) & 1u) << (31 - i);
