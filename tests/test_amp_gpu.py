@@ -46,7 +46,7 @@ def test_autocast_forward_16bit_with_fp32_gradient(dt):
     e_y = rel_l2(y.detach().double().cpu().numpy(), oracle.forward(g, x_np.astype(np.float64)))
     e_g = rel_l2(x.grad.double().cpu().numpy(), oracle.backproject(g, g16.double().cpu().numpy()))
     report(f"autocast_forward_{dt}", rel_l2=e_y, grad_rel_l2=e_g)
-    assert e_y <= (TOL_16 if dt == "f16" else 2 * TOL_16)
+    assert e_y <= TOL_16
     assert e_g <= TOL_F32
 
 
@@ -66,7 +66,7 @@ def test_autocast_backprojection_16bit_with_fp32_gradient(dt):
     assert torch.equal(y.grad, op.forward_raw(w.to(TDT[dt]).float(), scale=0.01))
     e = rel_l2(x.detach().double().cpu().numpy(), oracle.backproject(g, y_np.astype(np.float64), 0.01))
     report(f"autocast_backprojection_{dt}", rel_l2=e)
-    assert e <= (TOL_16 if dt == "f16" else 2 * TOL_16)
+    assert e <= TOL_16
 
 
 def test_types_kept_outside_autocast():

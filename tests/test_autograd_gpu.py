@@ -156,7 +156,7 @@ def test_unrolled_gd_gradient_fd_and_checkpoint(dt):
             an = dot_f64(g, v).item()
             worst = max(worst, abs(fd - an) / abs(fd))
     report("unrolled_gd_fd", worst_rel=worst, alpha=alpha)
-    assert worst <= 1e-4
+    assert worst <= 1e-5
 
 
 def test_unrolled_gd_matches_oracle_iteration():
