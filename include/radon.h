@@ -286,7 +286,10 @@ int radon_release_plans(void);
  * out[4..7] = the same for the backprojection.  variant: 0 = direct kernel, 1 = tiled
  * kernel.  staging: 1 when the tiled kernel first copies the call's input (images,
  * or sinograms for the backprojection) into a zero-bordered, image-interleaved
- * workspace, else 0.  Builds the plan when missing; status codes as radon_forward. */
+ * workspace; 2 (forward, 16-bit storage) when that copy holds pairs of neighbouring
+ * pixels and each pair of bilinear taps is applied by one FP32-accumulating dot2
+ * instruction with the weights rounded to the storage type; else 0.  Builds the plan
+ * when missing; status codes as radon_forward. */
 int radon_plan_info(const radon_geometry_t *geometry, int32_t dtype, int32_t batch,
                     int32_t *out8);
 

@@ -2,7 +2,8 @@
 // batch size class) by timing the candidates on the device with HIP events.
 //
 // Forward candidates: images per lane {8, 4 (FP32 only), 16 (16-bit only)} x slab
-// staging {interleaved copy, caller's images}, and the direct kernel.
+// staging {interleaved copy, caller's images, and for 16-bit storage the tap-pair copy
+// with dot2 arithmetic}, and the direct kernel.
 // Backprojection candidates: images per lane {64, 32, 16, one chunk (batches <= 8)} x
 // angles per LDS block {8, 4}
 // (parallel beam; the fan beam's block is fixed at 4 because its rays are staged
@@ -126,9 +127,10 @@ int autotune(Plan &p, int dtype, int batch, void *ws, size_t ws_bytes, TunedShap
             return launch_forward(p.geom, p.fwd_work, dtype, sh, x, y, batch, 1.0f, ws, ws_bytes, s);
         }, s);
         out.fwd_variant = VARIANT_DIRECT;
+        const std::vector<int> stages = dtype == F32 ? std::vector<int>{1, 0} : std::vector<int>{2, 1, 0};
         for (int im : imgs)
-            for (int st : {1, 0}) {
-                if (st == 1 && p.no_interleave) continue;
+            for (int st : stages) {
+                if (st > 0 && p.no_interleave) continue;
                 LaunchShape sh = p.fwd_shape;
                 sh.images = im;
                 sh.stage = st;

@@ -124,6 +124,50 @@ template <> struct Chunk<bf16_t> {
     }
 };
 
+// ---------------------------------------------------------------- tap-pair chunks
+// 16-bit storage in "tap pairs": a 16-byte chunk holds two horizontally adjacent
+// pixels (x, x+1) of four images, one 32-bit word per image (pixel x in the low
+// half).  One dot2 instruction (v_dot2c_f32_f16 / v_dot2c_f32_bf16: both 16-bit
+// products are exact in FP32 and added to the FP32 accumulator) then applies the two
+// bilinear weights of a row of taps, so a bilinear sample costs two instructions per
+// image instead of four multiply-adds.  The weights are rounded to the storage type
+// (round to nearest even) for that.  Along a ray whose direction is close to an axis
+// the fractional sample positions change slowly, so these rounding errors are
+// correlated from sample to sample and do not average out: the sum carries up to the
+// weights' relative rounding (2^-12 in FP16, 2^-9 in BF16), the same order as the
+// rounding of the stored output.
+typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+template <typename T> struct Pair;
+
+template <> struct Pair<__half> {
+    static constexpr int kImages = 4;
+    // (lo, hi) rounded to FP16 and packed, lo in bits 0..15
+    static __device__ __forceinline__ uint32_t weights(float lo, float hi) {
+        const f16x2_t v = {(_Float16)lo, (_Float16)hi};
+        return __builtin_bit_cast(uint32_t, v);
+    }
+    static __device__ __forceinline__ float dot2(uint32_t taps, uint32_t w, float acc) {
+        return __builtin_amdgcn_fdot2(__builtin_bit_cast(f16x2_t, taps), __builtin_bit_cast(f16x2_t, w),
+                                      acc, false);
+    }
+    static __device__ __forceinline__ uint32_t bits(__half h) { return __half_as_ushort(h); }
+};
+
+template <> struct Pair<bf16_t> {
+    static constexpr int kImages = 4;
+    static __device__ __forceinline__ uint32_t weights(float lo, float hi) {
+        const bf16x2_t v = {(__bf16)lo, (__bf16)hi};
+        return __builtin_bit_cast(uint32_t, v);
+    }
+    static __device__ __forceinline__ float dot2(uint32_t taps, uint32_t w, float acc) {
+        return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, taps),
+                                               __builtin_bit_cast(bf16x2_t, w), acc, false);
+    }
+    static __device__ __forceinline__ uint32_t bits(bf16_t h) { return h.bits; }
+};
+
 // ---------------------------------------------------------------- geometry
 struct Geom {
     int n;               // image side N

@@ -74,8 +74,10 @@ __global__ __launch_bounds__(256) void fwd_direct(Geom g, const T *__restrict__ 
 // caps them, at three blocks (6 waves per SIMD) for items up to ~120 columns wide.
 // The FP32 kernel needs 66 registers then; the BF16 one spills one or two registers
 // and still runs 12% faster than at two blocks.
-template <typename T, int BC>
-constexpr int kFwdMinWaves = (sizeof(T) == 2 || BC == 8) ? 6 : 1;
+// Tap-pair kernels (16-bit, four images per chunk) have FP32's LDS footprint: the
+// 8-image one is held to the same bound; the 16-image one fits one block per CU.
+template <typename T, int BC, bool PAIRS = false>
+constexpr int kFwdMinWaves = PAIRS ? (BC == 8 ? 6 : 2) : ((sizeof(T) == 2 || BC == 8) ? 6 : 1);
 
 // One block = one work item of the plan x BC images (blockIdx.y selects the images).
 template <typename T, int BC>
@@ -91,15 +93,16 @@ __global__ __launch_bounds__(kFwdThreads, (kFwdMinWaves<T, BC>)) void fwd_tiled(
 }
 
 // Same, staging from the interleaved, zero-bordered copies of the batch: xi holds
-// the row-major copy [groups][N+4][N+4] followed by the transposed copy.  PITCH > 0:
-// LDS rows of that many chunks (the plan's windows are at most that wide), fixed at
-// compile time so the tap offsets are immediates.
-template <typename T, int BC, int PITCH>
-__global__ __launch_bounds__(kFwdThreads, (kFwdMinWaves<T, BC>)) void fwd_tiled_il(Geom g, FwdWork work, const uint4 *__restrict__ xi,
+// the row-major copy [groups][N+4][N+4] followed by the transposed copy (PAIRS: copies
+// of tap pairs, four images per chunk).  PITCH > 0: LDS rows of that many chunks (the
+// plan's windows are at most that wide), fixed at compile time so the tap offsets are
+// immediates.
+template <typename T, int BC, int PITCH, bool PAIRS = false>
+__global__ __launch_bounds__(kFwdThreads, (kFwdMinWaves<T, BC, PAIRS>)) void fwd_tiled_il(Geom g, FwdWork work, const uint4 *__restrict__ xi,
                                                     T *__restrict__ y, int batch, float scale_dt,
                                                     int tile_t, int groups) {
     extern __shared__ uint4 lds[];
-    constexpr int CH = Chunk<T>::kImages;
+    constexpr int CH = PAIRS ? 4 : Chunk<T>::kImages;
     const FwdItem it = work.items[blockIdx.x];
     const int b0 = blockIdx.y * BC;
     // only the output side of the image set is used with an interleaved source
@@ -107,8 +110,8 @@ __global__ __launch_bounds__(kFwdThreads, (kFwdMinWaves<T, BC>)) void fwd_tiled_
         y, 0, y, (size_t)g.n_angles * g.det_count, batch, b0, scale_dt);
     const int plane = (g.n + 4) * (g.n + 4);
     const uint4 *first = xi + (size_t)(b0 / CH) * plane;
-    const InterleavedSource<T, BC> src{first, first + (size_t)groups * plane, g.n, plane};
-    fwd_item<T, BC, InterleavedSource<T, BC>, PITCH>(g, it, work.ranges, imgs, src, tile_t, lds);
+    const InterleavedSource<T, BC, PAIRS> src{first, first + (size_t)groups * plane, g.n, plane};
+    fwd_item<T, BC, InterleavedSource<T, BC, PAIRS>, PITCH>(g, it, work.ranges, imgs, src, tile_t, lds);
 }
 
 // Interleave a batch x[B][N][N] into chunks of CH images with a zero border of 2
@@ -149,9 +152,57 @@ __global__ __launch_bounds__(256) void interleave_images(const T *__restrict__ x
     }
 }
 
-size_t interleaved_bytes(int n, int batch, int dtype) {
-    const int ch = dtype == F32 ? 4 : 8;
-    const size_t groups = ((size_t)batch + 15) / 16 * 16 / ch;   // whole 16-image blocks
+// Tap-pair copies of a 16-bit batch: the same chunk grid as interleave_images, chunk
+// (grp, yy, xx) = padded pixels xx and xx + 1 of padded row yy (row-major copy) and
+// chunk (groups + grp, xx, yy) = padded pixels (xx, yy) and (xx, yy + 1) (transposed
+// copy: pairs run along the image's y), word e of a chunk = image 4 grp + e with the
+// first pixel in its low half.  One block = one 16 x 16 chunk tile of one group, read
+// with one pixel of halo into LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void interleave_pairs(const T *__restrict__ x, uint4 *__restrict__ xi,
+                                                        int n, int batch, int groups) {
+    constexpr int CH = Pair<T>::kImages;
+    constexpr int TP = kIlTile + 1;
+    __shared__ uint2 tile[TP][TP + 1];   // 4 images' 16-bit values per padded pixel
+    const int np = n + 4;
+    const int tiles = (np + kIlTile - 1) / kIlTile;
+    const int grp = blockIdx.y;
+    const int ty0 = (blockIdx.x / tiles) * kIlTile, tx0 = (blockIdx.x % tiles) * kIlTile;
+    const size_t plane = (size_t)np * np;
+    for (int t = threadIdx.x; t < TP * TP; t += 256) {
+        const int i = t / TP, j = t - i * TP;
+        const int ix = tx0 + j - 2, iy = ty0 + i - 2;
+        const bool inside = (unsigned)ix < (unsigned)n && (unsigned)iy < (unsigned)n;
+        uint32_t h[CH];
+#pragma unroll
+        for (int e = 0; e < CH; ++e) {
+            const int b = grp * CH + e;
+            h[e] = (inside && b < batch) ? Pair<T>::bits(x[(size_t)b * n * n + (size_t)iy * n + ix]) : 0u;
+        }
+        tile[i][j] = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+    }
+    __syncthreads();
+    // pixels a (low halves) and b (high halves) of the four images
+    auto pair = [](uint2 a, uint2 b) {
+        return make_uint4((a.x & 0xffffu) | (b.x << 16), (a.x >> 16) | (b.x & 0xffff0000u),
+                          (a.y & 0xffffu) | (b.y << 16), (a.y >> 16) | (b.y & 0xffff0000u));
+    };
+    const int tx = threadIdx.x % kIlTile, ty = threadIdx.x / kIlTile;
+    {
+        const int xx = tx0 + tx, yy = ty0 + ty;
+        if (xx < np && yy < np) xi[(size_t)grp * plane + (size_t)yy * np + xx] = pair(tile[ty][tx], tile[ty][tx + 1]);
+    }
+    {
+        const int row = tx0 + ty, col = ty0 + tx;   // padded x, padded y
+        if (row < np && col < np)
+            xi[(size_t)(groups + grp) * plane + (size_t)row * np + col] = pair(tile[tx][ty], tile[tx + 1][ty]);
+    }
+}
+
+// Workspace of the interleaved copies: four images per chunk (FP32, or 16-bit tap
+// pairs; the 16-bit single-pixel copies need half of it) in whole 16-image blocks.
+size_t interleaved_bytes(int n, int batch, int /*dtype*/) {
+    const size_t groups = ((size_t)batch + 15) / 16 * 16 / 4;
     return 2 * groups * (size_t)(n + 4) * (n + 4) * sizeof(uint4);
 }
 
@@ -165,6 +216,30 @@ static hipError_t launch_fwd_direct(const Geom &g, const void *x, void *y, int b
     return hipGetLastError();
 }
 
+// Tiled forward with 16-bit tap pairs (stage 2): pair copies, then the pair kernel.
+template <typename T, int BC>
+static hipError_t launch_fwd_pairs(const Geom &g, const FwdWork &work, const void *x, void *y,
+                                   int batch, float scale_dt, void *ws, hipStream_t s) {
+    constexpr int PLANES = BC / Pair<T>::kImages;
+    const size_t lds = (size_t)PLANES * (kSlabH + 3) * work.tile_t * sizeof(uint4);
+    const size_t lds_fixed = (size_t)PLANES * (kSlabH + 3) * kFwdPitchFixed * sizeof(uint4);
+    dim3 grid(work.n_items, (batch + BC - 1) / BC);
+    const int groups = (batch + BC - 1) / BC * PLANES;
+    const int tiles = (g.n + 4 + kIlTile - 1) / kIlTile;
+    hipLaunchKernelGGL(interleave_pairs<T>, dim3(tiles * tiles, groups), dim3(256), 0, s,
+                       (const T *)x, (uint4 *)ws, g.n, batch, groups);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (work.tile_t <= kFwdPitchFixed)
+        hipLaunchKernelGGL((fwd_tiled_il<T, BC, kFwdPitchFixed, true>), grid, dim3(kFwdThreads),
+                           lds_fixed, s, g, work, (const uint4 *)ws, (T *)y, batch, scale_dt,
+                           kFwdPitchFixed, groups);
+    else
+        hipLaunchKernelGGL((fwd_tiled_il<T, BC, 0, true>), grid, dim3(kFwdThreads), lds, s, g, work,
+                           (const uint4 *)ws, (T *)y, batch, scale_dt, work.tile_t, groups);
+    return hipGetLastError();
+}
+
 template <typename T, int BC>
 static hipError_t launch_fwd_tiled(const Geom &g, const FwdWork &work, const void *x, void *y,
                                    int batch, float scale_dt, int stage, void *ws, size_t ws_bytes,
@@ -175,6 +250,10 @@ static hipError_t launch_fwd_tiled(const Geom &g, const FwdWork &work, const voi
     const size_t lds_fixed = (size_t)PLANES * (kSlabH + 3) * kFwdPitchFixed * sizeof(uint4);
     dim3 grid(work.n_items, (batch + BC - 1) / BC);
     const int dt = sizeof(T) == 4 ? F32 : F16;
+    if constexpr (sizeof(T) == 2) {
+        if (stage == 2 && ws && ws_bytes >= interleaved_bytes(g.n, batch, dt))
+            return launch_fwd_pairs<T, BC>(g, work, x, y, batch, scale_dt, ws, s);
+    }
     if (ws && stage && ws_bytes >= interleaved_bytes(g.n, batch, dt)) {
         // groups of the launch: whole BC-image blocks (<= the groups interleaved_bytes counts)
         const int groups = (batch + BC - 1) / BC * PLANES;

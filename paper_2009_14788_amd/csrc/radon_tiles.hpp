@@ -53,6 +53,7 @@ __device__ __forceinline__ ImageSet<T, BC> contiguous_images(const T *in, size_t
 template <typename T, int BC>
 struct PointerSource {
     static constexpr bool kMarchFrame = false;
+    static constexpr bool kPairs = false;
     const T *const *img;
     int n;
     __device__ __forceinline__ void stage(uint4 *lds, int plane_chunks, int pitch, int ox0, int oy0,
@@ -91,13 +92,16 @@ struct PointerSource {
 // x+2) of the row-major copy [groups][N+4][N+4] holds pixel (x, y) of the group's
 // images, and chunk (group, x+2, y+2) of the transposed copy holds the same pixel,
 // both with a zero border of 2 pixels, so a window inside [-2, N+1]^2 is copied chunk
-// for chunk with no bounds test.  Window rows/columns beyond [-2, N+1] are never
+// for chunk with no bounds test.  PAIRS (16-bit storage): the copies hold tap pairs
+// (Pair<T>) instead, chunk (group, row, col) = frame pixels col and col + 1 of the row,
+// four images per chunk.  Window rows/columns beyond [-2, N+1] are never
 // tapped and are not staged.  Wave w copies window rows w, w+W, w+2W, ... (W waves; a slab has
 // kSlabH + 3 rows) with its lanes along the row (at most kTileTMax = 3 x 64
 // chunks), from wave-uniform row addresses.
-template <typename T, int BC>
+template <typename T, int BC, bool PAIRS = false>
 struct InterleavedSource {
     static constexpr bool kMarchFrame = true;
+    static constexpr bool kPairs = PAIRS;
     const uint4 *base;   // row-major copy: first plane of the block's images
     const uint4 *tbase;  // transposed copy: first plane of the block's images
     int n;
@@ -106,7 +110,7 @@ struct InterleavedSource {
                                           int rows, int cols, int axis) const {
         static_assert(kTileTMax <= 3 * 64, "staging loop bounds");
         constexpr int kRowsPerWave = (kSlabH + 3 + kFwdWaves - 1) / kFwdWaves;
-        constexpr int PLANES = BC / Chunk<T>::kImages;
+        constexpr int PLANES = BC / (PAIRS ? 4 : Chunk<T>::kImages);
         const int np = n + 4;
         const int r_end = min(rows, n + 2 - oy0), c_end = min(cols, n + 2 - ox0);
         if (r_end <= 0 || c_end <= 0) return;
@@ -200,6 +204,46 @@ __device__ __forceinline__ void slab_samples(const uint4 *lane_lds, int pitch, i
     }
 }
 
+// The samples of one lane's ray inside one slab, staged as tap pairs (16-bit storage,
+// four images per chunk): per sample the four bilinear weights are formed in the
+// staging frame exactly as in slab_samples, rounded to the storage type in two pairs
+// (row cy: taps cx, cx+1; row cy+1: the same columns), and each image takes one
+// dot2 per row from one 16-byte read per plane and row.
+template <typename T, int BC, int PITCH>
+__device__ __forceinline__ void slab_samples_pair(const uint4 *lane_lds, int pitch, int plane_chunks,
+                                                  double fxa, double fya, double sx, double sy,
+                                                  int cnt, float *part) {
+    constexpr int CH = Pair<T>::kImages;
+    constexpr int PLANES = BC / CH;
+    if (PITCH > 0) {
+        pitch = PITCH;
+        plane_chunks = (kSlabH + 3) * PITCH;
+    }
+    const char *base = reinterpret_cast<const char *>(lane_lds);
+    const unsigned row_bytes = (unsigned)pitch * 16u, plane_bytes = (unsigned)plane_chunks * 16u;
+    const float end = (float)cnt, fxa32 = (float)fxa, fya32 = (float)fya;
+    const float sx32 = (float)sx, sy32 = (float)sy;
+    for (float jf = 0.0f; jf < end; jf += 1.0f) {
+        const float px = fmaf(jf, sx32, fxa32), py = fmaf(jf, sy32, fya32);
+        const int cx = (int)px, cy = (int)py;                       // px, py >= 1 - 1e-6
+        const float fx = __builtin_amdgcn_fractf(px), fy = __builtin_amdgcn_fractf(py);
+        const float gb = 1.0f - fy;
+        const float w01 = __fmul_rn(fx, gb), w11 = __fmul_rn(fx, fy);
+        const uint32_t wt = Pair<T>::weights(gb - w01, w01), wb = Pair<T>::weights(fy - w11, w11);
+        const char *p0 = base + ((unsigned)__mul24(cy, pitch) + (unsigned)cx) * 16u;
+#pragma unroll
+        for (int q = 0; q < PLANES; ++q) {
+            const uint4 t0 = *reinterpret_cast<const uint4 *>(p0 + q * plane_bytes);
+            const uint4 t1 = *reinterpret_cast<const uint4 *>(p0 + q * plane_bytes + row_bytes);
+            float *aq = part + q * CH;
+            aq[0] = Pair<T>::dot2(t1.x, wb, Pair<T>::dot2(t0.x, wt, aq[0]));
+            aq[1] = Pair<T>::dot2(t1.y, wb, Pair<T>::dot2(t0.y, wt, aq[1]));
+            aq[2] = Pair<T>::dot2(t1.z, wb, Pair<T>::dot2(t0.z, wt, aq[2]));
+            aq[3] = Pair<T>::dot2(t1.w, wb, Pair<T>::dot2(t0.w, wt, aq[3]));
+        }
+    }
+}
+
 // One block processes one work item (up to kFwdWaves angles x 64 bins) x BC images.  The rays march through the image in slabs of
 // kSlabH rows (or columns); per slab the block stages the slab's pixel window
 // into LDS as 16-byte chunks holding Chunk<T>::kImages images each ("planes"),
@@ -282,7 +326,10 @@ __device__ __forceinline__ void fwd_item(const Geom &g, const FwdItem &it, const
         float part[BC];
 #pragma unroll
         for (int i = 0; i < BC; ++i) part[i] = 0.0f;
-        if (swap)
+        if constexpr (Source::kPairs)
+            slab_samples_pair<T, BC, PITCH>(lane_lds, pitch, plane_chunks, px64 - bx, py64 - by,
+                                            r.z, r.w, je - jb, part);
+        else if (swap)
             slab_samples<T, BC, Source::kMarchFrame, PITCH>(lane_lds, pitch, plane_chunks,
                                                             px64 - bx, py64 - by, r.z, r.w,
                                                             je - jb, part);

@@ -31,6 +31,7 @@ struct dim3 {
     dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
 };
 struct uint4 { unsigned x, y, z, w; };
+struct uint2 { unsigned x, y; };
 struct int2 { int x, y; };
 struct double2 { double x, y; };
 struct double4 { double x, y, z, w; };
@@ -44,6 +45,7 @@ inline unsigned __brev(unsigned v) {
     return r;
 }
 inline uint4 make_uint4(unsigned a, unsigned b, unsigned c, unsigned d) { return {a, b, c, d}; }
+inline uint2 make_uint2(unsigned a, unsigned b) { return {a, b}; }
 inline int2 make_int2(int a, int b) { return {a, b}; }
 inline double2 make_double2(double a, double b) { return {a, b}; }
 inline double4 make_double4(double a, double b, double c, double d) { return {a, b, c, d}; }
@@ -64,6 +66,14 @@ inline float emu_fractf(float x) { return x - std::floor(x); }
 #define __builtin_amdgcn_fractf(x) emu_fractf(x)
 #define __builtin_amdgcn_fmed3f(a, b, c) emu_med3(a, b, c)
 #define __builtin_amdgcn_readfirstlane(x) (x)
+// v_dot2c_f32_f16 / v_dot2c_f32_bf16: the two 16-bit products are exact, their sum with
+// the FP32 accumulator is rounded once
+template <class V> inline float emu_fdot2(V a, V b, float c) {
+    return (float)((double)(float)a[0] * (double)(float)b[0] + (double)(float)a[1] * (double)(float)b[1] +
+                   (double)c);
+}
+#define __builtin_amdgcn_fdot2(a, b, c, clamp) emu_fdot2(a, b, c)
+#define __builtin_amdgcn_fdot2_f32_bf16(a, b, c, clamp) emu_fdot2(a, b, c)
 template <class T> inline T atomicAdd(T *p, T v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
 
 typedef int hipError_t;

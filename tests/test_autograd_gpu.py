@@ -144,14 +144,21 @@ def test_unrolled_gd_gradient_fd_and_checkpoint(dt):
         return   # the FD comparison needs FP32 storage; 16-bit runs test the plumbing
     g = grads[0]
     with torch.no_grad():
+        def loss(yy):
+            d = unrolled_gd(op, yy, alpha, iters=10, checkpoint=False) - xt
+            return dot_f64(d, d)
+
+        # x_10 = M y is linear in y (x_0 = 0), so the central difference of the quadratic
+        # loss is exact at any step; the step is sized so that M v is as large as the
+        # residual x_10(y0) - x_true, which keeps the FP32 rounding of x_10 small next
+        # to the difference (with v ~ 0.1 N(0,1), |M v| is ~1e-3 of the residual and
+        # that rounding alone gives ~7e-5)
+        d0 = loss(y0).item() ** 0.5
         worst = 0.0
         for k in range(3):
-            v = _t(inputs.randn(tuple(y0.shape), 50 + k)) * 0.1
-
-            def loss(yy):
-                d = unrolled_gd(op, yy, alpha, iters=10, checkpoint=False) - xt
-                return dot_f64(d, d)
-
+            v = _t(inputs.randn(tuple(y0.shape), 50 + k))
+            mv = unrolled_gd(op, v, alpha, iters=10, checkpoint=False)
+            v = v * (d0 / dot_f64(mv, mv).item() ** 0.5)
             fd = (loss(y0 + v) - loss(y0 - v)).item() / 2.0
             an = dot_f64(g, v).item()
             worst = max(worst, abs(fd - an) / abs(fd))

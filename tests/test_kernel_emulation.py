@@ -112,14 +112,16 @@ def test_emulated_kernels_match_oracle(emu_bin, tmp_path):
     assert rows[2][:2] == (1, 1) and rows[10][:2] == (1, 1), rows
 
 
-@pytest.mark.parametrize("shape", ["8,0,16,4,0", "4,1,32,4,1", "16,1,32,8,0", "8,1,16,8,1", "4,1,64,4,1", "8,0,64,8,0", "8,1,4,8,1", "4,0,4,4,0"])
+@pytest.mark.parametrize("shape", ["8,0,16,4,0", "4,1,32,4,1", "16,1,32,8,0", "8,1,16,8,1", "4,1,64,4,1",
+                                   "8,0,64,8,0", "8,1,4,8,1", "4,0,4,4,0", "8,2,16,4,1", "16,2,32,8,0"])
 def test_emulated_launch_shapes(emu_bin, tmp_path, shape):
-    """Every forced launch shape (images per lane, staging, angle block) stays in
-    bounds and at parity, with a ragged batch of 11 images."""
+    """Every forced launch shape (images per lane, staging -- 2: 16-bit tap pairs --,
+    angle block) stays in bounds and at parity, with a ragged batch of 11 images."""
     U = inputs.uniform_angles
     lines = [_line("par", 40, U(24), 57, batch=11),
              _line("par", 40, U(24), 57, batch=11, dt=1),
-             _line("fan", 40, U(24, 2 * math.pi), 66, 1.5, 250.0, 120.0, batch=11)]
+             _line("fan", 40, U(24, 2 * math.pi), 66, 1.5, 250.0, 120.0, batch=11),
+             _line("fan", 37, U(24, 2 * math.pi), 60, 1.5, 250.0, 120.0, batch=11, dt=2)]
     rows, _ = _run(emu_bin, tmp_path, lines, env={"RADON_FORCE_SHAPE": shape})
     _check_bars(rows, lines)
 
