@@ -59,7 +59,8 @@ enum {
     RADON_ERR_HIP = -4,           /* a HIP runtime call or kernel launch failed */
     RADON_ERR_ALLOC = -5,         /* device or host allocation failed */
     RADON_ERR_NO_DEVICE = -6,     /* no usable GPU */
-    RADON_ERR_NOT_PREPARED = -7   /* plan missing while the stream is capturing */
+    RADON_ERR_NOT_PREPARED = -7,  /* plan missing while the stream is capturing */
+    RADON_ERR_SCRATCH = -8        /* request exceeds a no-allocation entry point's fixed scratch */
 };
 
 enum { RADON_PARALLEL = 0, RADON_FANBEAM = 1 };
@@ -223,6 +224,20 @@ int radon_shearlet_adjoint(const radon_shearlet_t *s, const void *coeffs, void *
  * the capturing stream before capturing). */
 int radon_dot_f64_batched(const void *a, const void *b, int64_t n, int32_t batch, int32_t dtype,
                           double *out, void *stream);
+
+/* For callers that cannot allocate (code under stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc): radon_dot_f64_batched with no allocation at any
+ * call.  Same arguments, layouts, errors and results (the same kernels and reduction
+ * tree, so bit for bit the same values).  The partial sums live in a fixed array of
+ * 65536 doubles (512 KiB) of device memory that every GPU the library runs on holds
+ * until the process ends; a call needs batch * c of them, c = min(64, max(1,
+ * ceil(n / 4096))), and returns RADON_ERR_SCRATCH without launching anything when
+ * that exceeds 65536 (e.g. more than 1024 systems of >= 258048 elements).  Every call
+ * on one GPU uses that GPU's one array: calls that overlap on a GPU (two streams, or
+ * two threads) race and give wrong results, so serialise them.  The first call on a
+ * device looks the array's address up (no allocation). */
+int radon_dot_f64_batched_noalloc(const void *a, const void *b, int64_t n, int32_t batch,
+                                  int32_t dtype, double *out, void *stream);
 
 /* Per-system scaled update of the solvers (Sec. 4.2, 4.3): out[k n + i] = u[k n + i] + c_k v[k n + i] with
  * c_k = c0 * num[k] / den[k] evaluated in FP64 (num or den NULL reads as 1; c_k = 0

@@ -16,7 +16,7 @@ FILTERS = {"ram-lak": 0, "shepp-logan": 1, "cosine": 2, "hamming": 3, "hann": 4}
 STATUS = {
     0: "RADON_OK", -1: "RADON_ERR_INVALID_ARG", -2: "RADON_ERR_ALIGN",
     -3: "RADON_ERR_UNSUPPORTED", -4: "RADON_ERR_HIP", -5: "RADON_ERR_ALLOC",
-    -6: "RADON_ERR_NO_DEVICE", -7: "RADON_ERR_NOT_PREPARED",
+    -6: "RADON_ERR_NO_DEVICE", -7: "RADON_ERR_NOT_PREPARED", -8: "RADON_ERR_SCRATCH",
 }
 
 
@@ -85,6 +85,7 @@ def _load():
         "radon_filter_sinogram": ([G, vp, vp, i32, i32, i32, vp], ctypes.c_int),
         "radon_dot_f64": ([vp, vp, ctypes.c_int64, i32, vp, vp], ctypes.c_int),
         "radon_dot_f64_batched": ([vp, vp, ctypes.c_int64, i32, i32, vp, vp], ctypes.c_int),
+        "radon_dot_f64_batched_noalloc": ([vp, vp, ctypes.c_int64, i32, i32, vp, vp], ctypes.c_int),
         "radon_axpy_ratio": ([vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_int64, i32, i32, vp],
                              ctypes.c_int),
         "radon_solver_workspace_bytes": ([G, i32, i32, i32], ctypes.c_int64),

@@ -914,6 +914,22 @@ int radon_dot_f64_batched(const void *a, const void *b, int64_t n, int32_t batch
     return e == hipSuccess ? RADON_OK : RADON_ERR_HIP;
 }
 
+int radon_dot_f64_batched_noalloc(const void *a, const void *b, int64_t n, int32_t batch,
+                                  int32_t dtype, double *out, void *stream) {
+    int rc = check_dtype(dtype);
+    if (rc != RADON_OK) return rc;
+    if (n < 0 || batch < 0 || batch > 65535 || !out) return RADON_ERR_INVALID_ARG;
+    if (batch == 0) return RADON_OK;
+    if (reinterpret_cast<uintptr_t>(out) % alignof(double)) return RADON_ERR_ALIGN;
+    if (n > 0 && ((rc = check_ptr(a)) != RADON_OK || (rc = check_ptr(b)) != RADON_OK)) return rc;
+    if ((long long)batch * dot_rows_chunks(n) > kStaticDotPartials) return RADON_ERR_SCRATCH;
+    double *partials = nullptr;
+    if (static_dot_partials(&partials) != hipSuccess) return RADON_ERR_HIP;
+    hipError_t e = launch_dot_rows(a, b, (long long)n, batch, dtype, out, partials,
+                                   static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? RADON_OK : RADON_ERR_HIP;
+}
+
 int radon_axpy_ratio(const void *u, const void *v, void *out, const double *num,
                      const double *den, double c0, int64_t n, int32_t batch, int32_t dtype,
                      void *stream) {
@@ -966,6 +982,7 @@ const char *radon_status_string(int status) {
     case RADON_ERR_ALLOC: return "allocation failed";
     case RADON_ERR_NO_DEVICE: return "no usable GPU";
     case RADON_ERR_NOT_PREPARED: return "plan missing while the stream is capturing";
+    case RADON_ERR_SCRATCH: return "request exceeds the fixed scratch of a no-allocation entry point";
     default: return "unknown status";
     }
 }

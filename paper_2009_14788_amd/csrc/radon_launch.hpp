@@ -123,6 +123,12 @@ constexpr int kDotRowChunks = 64;
 int dot_rows_chunks(long long n);
 hipError_t launch_dot_rows(const void *a, const void *b, long long n, int batch, int dtype,
                            double *out, double *partials, hipStream_t s);
+// Fixed per-GPU partials of the no-allocation inner products: kStaticDotPartials
+// doubles (512 KiB) in device memory that the library's code object holds until the
+// process ends.  static_dot_partials returns the current device's address of it (looked
+// up on the first call per device; no allocation).
+constexpr int kStaticDotPartials = 1 << 16;
+hipError_t static_dot_partials(double **out);
 // out_b = u_b + c_b v_b with c_b = c0 * num[b] / den[b] in FP64 (null arrays read as 1,
 // c_b = 0 where den[b] == 0, and then out_b = u_b without reading v).  batch <= 65535.
 hipError_t launch_axpy_ratio(const void *u, const void *v, void *out, const double *num,

@@ -7,6 +7,9 @@
 // Inner products are deterministic: system b is cut into `chunks` contiguous pieces,
 // each block reduces one piece through a fixed tree into partials[b * chunks + c], and
 // one block per system sums its partials in a fixed order.
+#include <map>
+#include <mutex>
+
 #include "radon_common.hpp"
 #include "radon_launch.hpp"
 
@@ -136,6 +139,33 @@ static hipError_t dot_rows_typed(const void *a, const void *b, long long n, int 
     hipLaunchKernelGGL(dot_rows_final, dim3(batch), dim3(kVecThreads), 0, s,
                        (const double *)partials, chunks, out);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- fixed scratch
+// Partials of the no-allocation inner products: one array per GPU, part of the code
+// object, so it exists from module load until the process ends.  In host code the
+// name `scratch` is only a stand-in for the symbol; the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) double scratch[kStaticDotPartials];
+
+static std::mutex g_static_mutex;
+static std::map<int, double *> g_static_ptr;   // device -> address of its `scratch`
+
+hipError_t static_dot_partials(double **out) {
+    int device = 0;
+    hipError_t e = hipGetDevice(&device);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(g_static_mutex);
+    auto it = g_static_ptr.find(device);
+    if (it == g_static_ptr.end()) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        it = g_static_ptr.emplace(device, static_cast<double *>(p)).first;
+    }
+    *out = it->second;
+    return hipSuccess;
 }
 
 hipError_t launch_dot_rows(const void *a, const void *b, long long n, int batch, int dtype,

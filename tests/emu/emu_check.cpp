@@ -268,6 +268,26 @@ static int lifetime_mode(std::vector<Geo> &geos) {
     da.join();
     db.join();
     expect(d[1] == ref && d[2] == ref, "dot_concurrent_replays");
+    // the no-allocation batched inner product: captured from its very first call,
+    // bitwise equal to radon_dot_f64_batched, then a second, smaller call; a request
+    // beyond its fixed scratch is rejected before anything is launched
+    const int64_t m = (int64_t)g0.nx / 2;
+    double *e = (double *)dev_alloc(8 * sizeof(double));
+    hipStream_t C = reinterpret_cast<hipStream_t>(0x3000);
+    emu::begin_capture(C);
+    int rc_n = radon_dot_f64_batched_noalloc(keep[0], keep[0], m, 2, dt, e, C);
+    auto dot_c = emu::end_capture(C);
+    emu::replay_graph(dot_c);
+    rc_n |= radon_dot_f64_batched(keep[0], keep[0], m, 2, dt, e + 2, A);
+    rc_n |= radon_dot_f64_batched_noalloc(keep[0], keep[0], m / 3, 1, dt, e + 4, A);
+    rc_n |= radon_dot_f64_batched(keep[0], keep[0], m / 3, 1, dt, e + 5, A);
+    expect(rc_n == 0 && !dot_c.empty() && e[0] == e[2] && e[1] == e[3] && e[4] == e[5] &&
+               e[0] > 0.0 && e[4] > 0.0,
+           "noalloc_dot_equals_dot");
+    expect(radon_dot_f64_batched_noalloc(keep[0], keep[0], 300000, 1025, dt, e, A) ==
+               RADON_ERR_SCRATCH,
+           "noalloc_dot_rejects_oversize");
+    std::free(e);
     expect(emu::capture().allocs_while_capturing == 0, "no_allocation_under_capture");
     std::printf("summary geometries %zu failures %d\n", geos.size(), fails);
     std::free(d);

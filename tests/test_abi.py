@@ -70,7 +70,7 @@ def test_validate_null():
 
 
 def test_status_strings():
-    for code in range(-7, 1):
+    for code in range(-8, 1):
         s = _lib.string(code)
         assert s and s != "unknown status"
     assert _lib.string(-99) == "unknown status"

@@ -243,7 +243,8 @@ def test_emulated_graph_lifetime_and_streams(emu_bin, tmp_path):
     assert set(checks) >= {"eager_status", "capture_status", "streams_use_own_counters",
                            "replay_after_eviction", "concurrent_replays",
                            "dot_streams_use_own_partials", "dot_concurrent_replays",
-                           "no_allocation_under_capture"}, r.stdout
+                           "no_allocation_under_capture", "noalloc_dot_equals_dot",
+                           "noalloc_dot_rejects_oversize"}, r.stdout
     assert all(v == "ok" for v in checks.values()), r.stdout
 
 
