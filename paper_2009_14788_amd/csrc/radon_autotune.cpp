@@ -7,7 +7,8 @@
 // Backprojection candidates: images per lane {64, 32, 16, one chunk (batches <= 8)} x
 // angles per LDS block {8, 4}
 // (parallel beam; the fan beam's block is fixed at 4 because its rays are staged
-// too) x sinogram staging {interleaved copy, caller's sinograms}, and the direct kernel.  The direct kernels win on tiny problems, where the
+// too) x sinogram staging {interleaved copy, caller's sinograms, and for 16-bit storage
+// the tap-pair copy with dot2 arithmetic}, and the direct kernel.  The direct kernels win on tiny problems, where the
 // tiled kernels' sequential slabs and angle blocks are latency-bound.  Results live in the plan
 // and, when RADON_TUNE_CACHE names a file, in that file (one line per entry:
 // "<key> <fwd variant> <fwd images> <fwd stage> <bp variant> <bp images> <bp angles>
@@ -160,7 +161,7 @@ int autotune(Plan &p, int dtype, int batch, void *ws, size_t ws_bytes, TunedShap
         for (int im : ims)
             if (im >= 16 || batch <= 8)
             for (int ab : abs)
-                for (int st : {1, 0}) {
+                for (int st : (dtype == F32 ? std::vector<int>{1, 0} : std::vector<int>{2, 1, 0})) {
                     LaunchShape sh = p.bp_shape;
                     sh.images = im;
                     sh.angles = ab;

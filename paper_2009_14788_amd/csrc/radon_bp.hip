@@ -109,20 +109,21 @@ __global__ __launch_bounds__(256) void bp_tiled_par(Geom g, const T *__restrict_
     bp_tile_par<T, BC, NB, NK, AB>(g, blockIdx.x, imgs, src, W, lds);
 }
 
-// Same, staging from the interleaved, zero-padded copy yi of the batch's sinograms.
+// Same, staging from the interleaved, zero-padded copy yi of the batch's sinograms
+// (PAIRS: a copy of tap pairs, four images per chunk, applied with dot2).
 // Four resident blocks (four waves per SIMD) cap the registers at 128, so the plane
 // pipeline of the inner loop does not lower the occupancy.
-template <typename T, int BC, int NB, int NK, int AB>
+template <typename T, int BC, int NB, int NK, int AB, bool PAIRS = false>
 __global__ __launch_bounds__(256, 4) void bp_tiled_par_il(Geom g, const uint4 *__restrict__ yi,
                                                        T *__restrict__ x, int batch, float scale_dt,
                                                        int W) {
     extern __shared__ uint4 lds[];
-    constexpr int CH = Chunk<T>::kImages;
+    constexpr int CH = PAIRS ? 4 : Chunk<T>::kImages;
     const int b0 = blockIdx.y * BC;
     // only the output side of the image set is used with an interleaved source
     const ImageSet<T, BC> imgs = contiguous_images<T, BC>(x, 0, x, (size_t)g.n * g.n, batch, b0, scale_dt);
     const int Dp = g.det_count + 2 * W;
-    SinoInterleavedSource<T, BC> src;
+    SinoInterleavedSource<T, BC, PAIRS> src;
     src.plane_stride = g.n_angles * Dp;
     src.base = yi + (size_t)(b0 / CH) * src.plane_stride;
     src.D = g.det_count;
@@ -142,16 +143,16 @@ __global__ __launch_bounds__(256) void bp_tiled_fan(Geom g, const T *__restrict_
     bp_tile_fan<T, BC, NB, NK>(g, blockIdx.x, imgs, src, W, lds);
 }
 
-template <typename T, int BC, int NB, int NK>
+template <typename T, int BC, int NB, int NK, bool PAIRS = false>
 __global__ __launch_bounds__(256) void bp_tiled_fan_il(Geom g, const uint4 *__restrict__ yi,
                                                        T *__restrict__ x, int batch, float scale_dt,
                                                        int W) {
     extern __shared__ uint4 lds[];
-    constexpr int CH = Chunk<T>::kImages;
+    constexpr int CH = PAIRS ? 4 : Chunk<T>::kImages;
     const int b0 = blockIdx.y * BC;
     const ImageSet<T, BC> imgs = contiguous_images<T, BC>(x, 0, x, (size_t)g.n * g.n, batch, b0, scale_dt);
     const int Dp = g.det_count + 2 * W;
-    SinoInterleavedSource<T, BC> src;
+    SinoInterleavedSource<T, BC, PAIRS> src;
     src.plane_stride = g.n_angles * Dp;
     src.base = yi + (size_t)(b0 / CH) * src.plane_stride;
     src.D = g.det_count;
@@ -181,9 +182,35 @@ __global__ __launch_bounds__(256) void interleave_sinograms(const T *__restrict_
     yi[((size_t)grp * A + a) * Dp + p] = Chunk<T>::pack(v);
 }
 
-size_t interleaved_sino_bytes(int n_angles, int det_count, int window, int batch, int dtype) {
-    const int ch = dtype == F32 ? 4 : 8;
-    const size_t groups = ((size_t)batch + 63) / 64 * 64 / ch;   // whole 64-image blocks
+// Tap-pair copy of 16-bit sinograms: chunk p of (grp, a) = bins d = p - W and d + 1
+// of images 4 grp .. 4 grp + 3, one 32-bit word per image with bin d in the low half
+// (zero outside the detector and past the batch).  Grid: (bins, A, groups).
+template <typename T>
+__global__ __launch_bounds__(256) void interleave_sino_pairs(const T *__restrict__ y, uint4 *__restrict__ yi,
+                                                             int A, int D, int W, int batch) {
+    constexpr int CH = Pair<T>::kImages;
+    const int Dp = D + 2 * W;
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= Dp) return;
+    const int a = blockIdx.y, grp = blockIdx.z;
+    const int d = p - W;
+    const bool in0 = (unsigned)d < (unsigned)D, in1 = (unsigned)(d + 1) < (unsigned)D;
+    uint32_t w[CH];
+#pragma unroll
+    for (int e = 0; e < CH; ++e) {
+        const int b = grp * CH + e;
+        const T *row = y + ((size_t)b * A + a) * D;
+        const uint32_t lo = (in0 && b < batch) ? Pair<T>::bits(row[d]) : 0u;
+        const uint32_t hi = (in1 && b < batch) ? Pair<T>::bits(row[d + 1]) : 0u;
+        w[e] = lo | (hi << 16);
+    }
+    yi[((size_t)grp * A + a) * Dp + p] = make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// Workspace of the interleaved copies: four images per chunk (FP32, or 16-bit tap
+// pairs; the 16-bit single-bin copies need half of it) in whole 64-image blocks.
+size_t interleaved_sino_bytes(int n_angles, int det_count, int window, int batch, int /*dtype*/) {
+    const size_t groups = ((size_t)batch + 63) / 64 * 64 / 4;
     return groups * (size_t)n_angles * (size_t)(det_count + 2 * window) * sizeof(uint4);
 }
 
@@ -197,12 +224,63 @@ static hipError_t launch_bp_direct(const Geom &g, const void *y, void *x, int ba
     return hipGetLastError();
 }
 
+// Tiled backprojection from the tap-pair copy (16-bit storage, staging 2).  Returns
+// false (nothing launched) when the window does not fit the staging slots.
+template <typename T, int BC>
+static bool launch_bp_pairs(const Geom &g, const BpWork &work, const LaunchShape &shape,
+                            const void *y, void *x, int batch, float scale_dt, void *ws,
+                            size_t ws_bytes, hipStream_t s, hipError_t *err) {
+    constexpr int PLANES = BC / Pair<T>::kImages;
+    const int W = work.window;
+    const int dt = sizeof(T) == 4 ? F32 : F16;
+    if (!(ws && ws_bytes >= interleaved_sino_bytes(g.n_angles, g.det_count, W, batch, dt) &&
+          PLANES * W <= 256 * SinoInterleavedSource<T, BC, true>::kSlots &&
+          (double)PLANES * g.n_angles * (g.det_count + 2.0 * W) < 2.0e9))
+        return false;
+    const int tiles = ((g.n + kBpTile - 1) / kBpTile) * ((g.n + kBpTile - 1) / kBpTile);
+    dim3 grid(tiles, (batch + BC - 1) / BC);
+    const int groups = (batch + BC - 1) / BC * PLANES;
+    dim3 ig((g.det_count + 2 * W + 255) / 256, g.n_angles, groups);
+    hipLaunchKernelGGL(interleave_sino_pairs<T>, ig, dim3(256), 0, s, (const T *)y, (uint4 *)ws,
+                       g.n_angles, g.det_count, W, batch);
+    *err = hipGetLastError();
+    if (*err != hipSuccess) return true;
+    const uint4 *yi = (const uint4 *)ws;
+    if (!g.fan) {
+        if (shape.angles <= 4)
+            hipLaunchKernelGGL((bp_tiled_par_il<T, BC, 3, 3, 4, true>), grid, dim3(256),
+                               (size_t)PLANES * 4 * kBpWinPar * sizeof(uint4), s, g, yi, (T *)x, batch,
+                               scale_dt, W);
+        else
+            hipLaunchKernelGGL((bp_tiled_par_il<T, BC, 3, 3, kBpAngles, true>), grid, dim3(256),
+                               (size_t)PLANES * kBpAngles * kBpWinPar * sizeof(uint4), s, g, yi, (T *)x,
+                               batch, scale_dt, W);
+    } else {
+        const size_t lds = (size_t)PLANES * kBpAnglesFan * W * sizeof(uint4) +
+                           (size_t)kBpAnglesFan * W * sizeof(float4);
+        if (work.bins <= 4)
+            hipLaunchKernelGGL((bp_tiled_fan_il<T, BC, 4, 3, true>), grid, dim3(256), lds, s, g, yi,
+                               (T *)x, batch, scale_dt, W);
+        else
+            hipLaunchKernelGGL((bp_tiled_fan_il<T, BC, 6, 3, true>), grid, dim3(256), lds, s, g, yi,
+                               (T *)x, batch, scale_dt, W);
+    }
+    *err = hipGetLastError();
+    return true;
+}
+
 template <typename T, int BC>
 static hipError_t launch_bp_tiled(const Geom &g, const BpWork &work, const LaunchShape &shape,
                                   const void *y, void *x, int batch, float scale_dt, void *ws,
                                   size_t ws_bytes, hipStream_t s) {
     constexpr int CH = Chunk<T>::kImages;
     constexpr int PLANES = BC / CH;
+    if constexpr (sizeof(T) == 2) {
+        hipError_t err = hipSuccess;
+        if (shape.stage == 2 &&
+            launch_bp_pairs<T, BC>(g, work, shape, y, x, batch, scale_dt, ws, ws_bytes, s, &err))
+            return err;
+    }
     const int W = work.window;
     const int tiles = ((g.n + kBpTile - 1) / kBpTile) * ((g.n + kBpTile - 1) / kBpTile);
     dim3 grid(tiles, (batch + BC - 1) / BC);

@@ -356,6 +356,7 @@ __device__ __forceinline__ void fwd_item(const Geom &g, const FwdItem &it, const
 // thread, one scalar load per image.
 template <typename T, int BC>
 struct SinoPointerSource {
+    static constexpr bool kPairs = false;
     const T *const *img;
     int D;
     __device__ __forceinline__ void stage(uint4 *lds, int a0, int na, int W, const int *wlo_s,
@@ -385,10 +386,12 @@ struct SinoPointerSource {
 // Chunk<T>::kImages images with W zero bins on either side: one 16-byte copy per
 // chunk.  A window starting below -W or above D lies wholly in the zero region and is
 // read from the nearest padded position instead.  Each thread owns up to kSlots
-// fixed (plane, bin) slots of the window, set up once per block.
-template <typename T, int BC>
+// fixed (plane, bin) slots of the window, set up once per block.  PAIRS (16-bit
+// storage): the copy holds tap pairs, chunk j = bins j and j + 1 of four images.
+template <typename T, int BC, bool PAIRS = false>
 struct SinoInterleavedSource {
     static constexpr int kSlots = 4;
+    static constexpr bool kPairs = PAIRS;
     const uint4 *base;     // first plane of the block's images
     int plane_stride;      // chunks between planes (A * (D + 2W))
     int D, Dp;             // detector bins, padded row length D + 2W
@@ -396,7 +399,7 @@ struct SinoInterleavedSource {
 
     // slot k of this thread: element f = threadIdx + 256 k of the (plane, bin) window
     __device__ __forceinline__ void setup(int W, int per_plane) {
-        constexpr int PLANES = BC / Chunk<T>::kImages;
+        constexpr int PLANES = BC / (PAIRS ? 4 : Chunk<T>::kImages);
         slots = 0;
 #pragma unroll
         for (int k = 0; k < kSlots; ++k) {
@@ -420,6 +423,45 @@ struct SinoInterleavedSource {
     }
 };
 
+// NB candidate-bin weights of one (pixel, angle) applied to the tap-pair chunks of
+// PLANES planes (four images each): chunk i of `row` holds bins lb + i and lb + i + 1,
+// so the chunks at offsets 0, 2, 4, ... cover the candidates two at a time (a missing
+// last partner gets weight 0) and each image takes one dot2 per chunk.  Planes run in
+// a register pipeline as in the single-pixel chunks' loop.  PP: chunks between planes
+// (0: `pp` at run time).
+template <typename T, int PLANES, int NB, int PP>
+__device__ __forceinline__ void bp_apply_pairs(const float *wgt, const uint4 *row, float *part,
+                                               int pp = PP) {
+    constexpr int NP = (NB + 1) / 2;
+    if (PP > 0) pp = PP;
+    uint32_t wp[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) wp[i] = Pair<T>::weights(wgt[2 * i], 2 * i + 1 < NB ? wgt[2 * i + 1] : 0.0f);
+    uint4 cur[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) cur[i] = row[2 * i];
+#pragma unroll
+    for (int qq = 0; qq < PLANES; ++qq) {
+        uint4 nxt[NP];
+        if (qq + 1 < PLANES) {
+#pragma unroll
+            for (int i = 0; i < NP; ++i) nxt[i] = row[(qq + 1) * pp + 2 * i];
+        }
+        float *aq = part + qq * 4;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            aq[0] = Pair<T>::dot2(cur[i].x, wp[i], aq[0]);
+            aq[1] = Pair<T>::dot2(cur[i].y, wp[i], aq[1]);
+            aq[2] = Pair<T>::dot2(cur[i].z, wp[i], aq[2]);
+            aq[3] = Pair<T>::dot2(cur[i].w, wp[i], aq[3]);
+        }
+        if (qq + 1 < PLANES) {
+#pragma unroll
+            for (int i = 0; i < NP; ++i) cur[i] = nxt[i];
+        }
+    }
+}
+
 // Parallel beam.  One block = a 16x16 pixel tile (lane <-> pixel) x BC images.
 // Angles are processed in blocks of AB: for each, the block stages into LDS
 // the window of W bins its tile can touch, as 16-byte chunks of Chunk<T>::kImages
@@ -434,7 +476,7 @@ template <typename T, int BC, int NB, int NK, int AB, class Source>
 __device__ __forceinline__ void bp_tile_par(const Geom &g, int tile, const ImageSet<T, BC> &imgs,
                                             const Source &src, int W, uint4 *lds) {
     __shared__ int wlo_s[AB];
-    constexpr int CH = Chunk<T>::kImages;
+    constexpr int CH = Source::kPairs ? 4 : Chunk<T>::kImages;
     constexpr int PLANES = BC / CH;
     static_assert(BC % CH == 0, "BC must be a multiple of the images per chunk");
     const int n = g.n, A = g.n_angles;
@@ -502,23 +544,27 @@ __device__ __forceinline__ void bp_tile_par(const Geom &g, int tile, const Image
             int lb = (int)db + 1 - wlo_s[al];
             lb = min(max(lb, 0), W - NB);               // memory safety; real pixels are inside
             const uint4 *row = lds + al * W + lb;
-            // planes in a register pipeline: the next plane's NB chunks are read while
-            // the current plane's are applied, so LDS latency overlaps the multiply-adds
-            uint4 cur[NB];
+            if constexpr (Source::kPairs) {
+                bp_apply_pairs<T, PLANES, NB, per_plane>(wgt, row, part);
+            } else {
+                // planes in a register pipeline: the next plane's NB chunks are read while
+                // the current plane's are applied, so LDS latency overlaps the multiply-adds
+                uint4 cur[NB];
 #pragma unroll
-            for (int i = 0; i < NB; ++i) cur[i] = row[i];
+                for (int i = 0; i < NB; ++i) cur[i] = row[i];
 #pragma unroll
-            for (int qq = 0; qq < PLANES; ++qq) {
-                uint4 nxt[NB];
-                if (qq + 1 < PLANES) {
+                for (int qq = 0; qq < PLANES; ++qq) {
+                    uint4 nxt[NB];
+                    if (qq + 1 < PLANES) {
 #pragma unroll
-                    for (int i = 0; i < NB; ++i) nxt[i] = row[(qq + 1) * per_plane + i];
-                }
+                        for (int i = 0; i < NB; ++i) nxt[i] = row[(qq + 1) * per_plane + i];
+                    }
 #pragma unroll
-                for (int i = 0; i < NB; ++i) Chunk<T>::fma(wgt[i], cur[i], part + qq * CH);
-                if (qq + 1 < PLANES) {
+                    for (int i = 0; i < NB; ++i) Chunk<T>::fma(wgt[i], cur[i], part + qq * CH);
+                    if (qq + 1 < PLANES) {
 #pragma unroll
-                    for (int i = 0; i < NB; ++i) cur[i] = nxt[i];
+                        for (int i = 0; i < NB; ++i) cur[i] = nxt[i];
+                    }
                 }
             }
         }
@@ -542,12 +588,12 @@ __device__ __forceinline__ void bp_tile_par(const Geom &g, int tile, const Image
 // tile and its step, in tile coordinates (|values| <= ~50 px), so the offsets of the
 // candidate samples from the pixel carry ~1e-6 pixel of rounding, as in the parallel
 // kernel.
-template <typename T, int BC, int NBX, int NK>
+template <typename T, int BC, int NBX, int NK, bool PAIRS>
 __device__ __forceinline__ void fan_angle_block(const Geom &g, int a0, int na, int W, const int *wlo_s,
                                                 const float4 *rays_s, const uint4 *lds, int per_plane,
                                                 float qx, float qy, float lx, float ly, float is2,
                                                 float *part) {
-    constexpr int CH = Chunk<T>::kImages;
+    constexpr int CH = PAIRS ? 4 : Chunk<T>::kImages;
     constexpr int PLANES = BC / CH;
     const float sd = (float)g.sd, k_sde = (float)(g.sde * g.inv_spacing), hd = (float)g.half_d;
     for (int al = 0; al < na; ++al) {
@@ -585,10 +631,14 @@ __device__ __forceinline__ void fan_angle_block(const Geom &g, int a0, int na, i
             wgt[i] = w;
         }
         const uint4 *row = lds + al * W + lb;
+        if constexpr (PAIRS) {
+            bp_apply_pairs<T, PLANES, NBX, 0>(wgt, row, part, per_plane);
+        } else {
 #pragma unroll
-        for (int qq = 0; qq < PLANES; ++qq) {
+            for (int qq = 0; qq < PLANES; ++qq) {
 #pragma unroll
-            for (int i = 0; i < NBX; ++i) Chunk<T>::fma(wgt[i], row[qq * per_plane + i], part + qq * CH);
+                for (int i = 0; i < NBX; ++i) Chunk<T>::fma(wgt[i], row[qq * per_plane + i], part + qq * CH);
+            }
         }
     }
 }
@@ -608,7 +658,7 @@ __device__ __forceinline__ void bp_tile_fan(const Geom &g, int tile, const Image
                                             const Source &src, int W, uint4 *lds) {
     __shared__ int wlo_s[kBpAnglesFan];
     __shared__ int nb_s[kBpAnglesFan];
-    constexpr int CH = Chunk<T>::kImages;
+    constexpr int CH = Source::kPairs ? 4 : Chunk<T>::kImages;
     constexpr int PLANES = BC / CH;
     static_assert(BC % CH == 0, "BC must be a multiple of the images per chunk");
     const int n = g.n, A = g.n_angles, D = g.det_count;
@@ -682,10 +732,10 @@ __device__ __forceinline__ void bp_tile_fan(const Geom &g, int tile, const Image
             for (int i = 0; i < BC; ++i) part[i] = 0.0f;
         }
         if (NB > 4 && nb_block <= 4)
-            fan_angle_block<T, BC, 4, NK>(g, a0, na, W, wlo_s, rays_s, lds, per_plane, qx, qy, lx, ly,
+            fan_angle_block<T, BC, 4, NK, Source::kPairs>(g, a0, na, W, wlo_s, rays_s, lds, per_plane, qx, qy, lx, ly,
                                           is2, part);
         else
-            fan_angle_block<T, BC, NB, NK>(g, a0, na, W, wlo_s, rays_s, lds, per_plane, qx, qy, lx, ly,
+            fan_angle_block<T, BC, NB, NK, Source::kPairs>(g, a0, na, W, wlo_s, rays_s, lds, per_plane, qx, qy, lx, ly,
                                            is2, part);
         if (kTwoLevel) {
 #pragma unroll

@@ -9,7 +9,9 @@ lane or LDS plane position cannot hide in an average):
   [0, 2 pi)), BF16 / FP16 storage, both directions, all 64 images;
 * the 200-job uneven batch in one persistent launch, FP32 / FP16, eager and
   graph-replayed, every job whole, both directions;
-* the 64-images-per-lane backprojection (single-level FP32 sums) at 2048 angles.
+* the 64-images-per-lane backprojection (single-level FP32 sums) at 2048 angles;
+* the 16-bit tap-pair shapes (dot2 with 16-bit weights) in both directions, forced,
+  at the headline and fan-beam sizes.
 
 Bars: relative L2 <= 1e-5 (FP32) and <= 5e-3 (16-bit storage, against the oracle on
 the original FP32 inputs, storage rounding included) for every image.  Each case
@@ -110,6 +112,53 @@ def test_headline_full(headline, dt):
         assert e <= {"f16": 2.0 ** -11, "bf16": 2.0 ** -8}[dt]
 
 
+class _forced_shape:
+    """RADON_FORCE_SHAPE for the calls inside the block (read at every call)."""
+
+    def __init__(self, shape):
+        self.shape, self.old = shape, None
+
+    def __enter__(self):
+        self.old = os.environ.get("RADON_FORCE_SHAPE")
+        os.environ["RADON_FORCE_SHAPE"] = self.shape
+
+    def __exit__(self, *exc):
+        if self.old is None:
+            os.environ.pop("RADON_FORCE_SHAPE", None)
+        else:
+            os.environ["RADON_FORCE_SHAPE"] = self.old
+
+
+def _pairs_case(tag, op, og, x, ys, y_ref, xb_ref, dt, shape):
+    """Both directions in tap-pair staging (16-bit weights, dot2), whatever the
+    autotuner picks: every image against the oracle on the FP32 inputs, and the
+    kernel arithmetic alone (the oracle on the 16-bit-rounded inputs) at every lane
+    and plane position."""
+    with _forced_shape(shape):
+        _announce(f"{tag} tap pairs {dt} shape {shape}")
+        xd = torch.from_numpy(x).cuda().to(TDT[dt])
+        y_gpu = _host(op.forward(xd))
+        _compare(f"{tag}_fwd_pairs_{dt}", y_gpu, y_ref, TOL[dt], shape=shape)
+        sel = [p for p in POSITIONS if p < x.shape[0]]
+        e = rel_l2(y_gpu[sel], oracle.forward(og, _host(xd[sel])))
+        report(f"{tag}_fwd_pairs_{dt}_rounded_inputs", rel_l2=e, images=len(sel))
+        assert e <= {"f16": 2.0 ** -11, "bf16": 2.0 ** -8}[dt]
+        del y_gpu, xd
+        yd = torch.from_numpy(ys).cuda().to(TDT[dt])
+        xb_gpu = _host(op.backprojection(yd))
+        _compare(f"{tag}_bp_pairs_{dt}", xb_gpu, xb_ref, TOL[dt], shape=shape)
+        e = rel_l2(xb_gpu[sel], oracle.backproject(og, _host(yd[sel])))
+        report(f"{tag}_bp_pairs_{dt}_rounded_inputs", rel_l2=e, images=len(sel))
+        assert e <= {"f16": 2.0 ** -11, "bf16": 2.0 ** -8}[dt]
+
+
+@pytest.mark.parametrize("shape", ["8,2,64,4,2", "16,2,32,8,2"])
+@pytest.mark.parametrize("dt", ["f16", "bf16"])
+def test_headline_tap_pairs(headline, dt, shape):
+    case, og, x, ys, y_ref, xb_ref = headline
+    _pairs_case("headline", case.library(), og, x, ys, y_ref, xb_ref, dt, shape)
+
+
 # ------------------------------------------------------------------ fan beam 64 x 512^2
 @pytest.fixture(scope="module")
 def fan():
@@ -138,6 +187,13 @@ def test_fan_full(fan, dt):
     _announce(f"fan backprojection {dt} batch {B}")
     xb_gpu = _host(op.backprojection(torch.from_numpy(ys).cuda().to(TDT[dt])))
     _compare(f"fan_bp_{dt}", xb_gpu, xb_ref, TOL[dt], shape=shapes["backprojection"])
+
+
+@pytest.mark.parametrize("shape", ["16,2,64,4,2", "8,2,32,4,2"])
+@pytest.mark.parametrize("dt", ["bf16", "f16"])
+def test_fan_tap_pairs(fan, dt, shape):
+    case, og, x, ys, y_ref, xb_ref = fan
+    _pairs_case("fan", case.library(), og, x, ys, y_ref, xb_ref, dt, shape)
 
 
 # ------------------------------------------------------------------ 200 uneven jobs

@@ -113,10 +113,12 @@ def test_emulated_kernels_match_oracle(emu_bin, tmp_path):
 
 
 @pytest.mark.parametrize("shape", ["8,0,16,4,0", "4,1,32,4,1", "16,1,32,8,0", "8,1,16,8,1", "4,1,64,4,1",
-                                   "8,0,64,8,0", "8,1,4,8,1", "4,0,4,4,0", "8,2,16,4,1", "16,2,32,8,0"])
+                                   "8,0,64,8,0", "8,1,4,8,1", "4,0,4,4,0", "8,2,16,4,2", "16,2,32,8,0",
+                                   "8,1,64,8,2", "16,2,8,4,2"])
 def test_emulated_launch_shapes(emu_bin, tmp_path, shape):
-    """Every forced launch shape (images per lane, staging -- 2: 16-bit tap pairs --,
-    angle block) stays in bounds and at parity, with a ragged batch of 11 images."""
+    """Every forced launch shape (images per lane, staging -- 2: 16-bit tap pairs with
+    dot2, forward or backprojection --, angle block) stays in bounds and at parity, with
+    a ragged batch of 11 images."""
     U = inputs.uniform_angles
     lines = [_line("par", 40, U(24), 57, batch=11),
              _line("par", 40, U(24), 57, batch=11, dt=1),
@@ -124,6 +126,19 @@ def test_emulated_launch_shapes(emu_bin, tmp_path, shape):
              _line("fan", 37, U(24, 2 * math.pi), 60, 1.5, 250.0, 120.0, batch=11, dt=2)]
     rows, _ = _run(emu_bin, tmp_path, lines, env={"RADON_FORCE_SHAPE": shape})
     _check_bars(rows, lines)
+
+
+@pytest.mark.parametrize("shape", ["8,2,16,4,2", "16,2,64,4,2"])
+def test_emulated_tap_pairs_wide_windows(emu_bin, tmp_path, shape):
+    """16-bit tap pairs where the forward's slab windows are wider than the fixed LDS
+    pitch (bins 2 pixels apart at the isocentre, so 64 bins span ~130 columns and the
+    run-time pitch is used), FP16 and BF16, ragged batch of 5."""
+    U = inputs.uniform_angles
+    lines = [_line("fan", 160, U(6, 2 * math.pi), 100, 3.0, 400.0, 200.0, batch=5, dt=1),
+             _line("fan", 160, U(6, 2 * math.pi), 100, 3.0, 400.0, 200.0, batch=5, dt=2)]
+    rows, _ = _run(emu_bin, tmp_path, lines, env={"RADON_FORCE_SHAPE": shape})
+    _check_bars(rows, lines)
+    assert all(r[0] == 1 for r in rows), rows
 
 
 def test_emulated_uneven_batch_groups(emu_bin, tmp_path):
