@@ -32,7 +32,9 @@ COUNTER_RECORD = os.path.join(ROOT, "profiles", "cache_hit_rates_batch128_512_f3
 # the sources that define the forward and backprojection kernels, their launches and
 # their work plans: the HBM traffic record is valid while these are unchanged
 PROJECTOR_SOURCES = ("radon_abi.cpp", "radon_bp.hip", "radon_common.hpp", "radon_fwd.hip",
-                     "radon_launch.hpp", "radon_plan.hpp", "radon_planner.cpp", "radon_tiles.hpp")
+                     "radon_fwd_tiled.hpp", "radon_fwd_t0.hip", "radon_fwd_t1.hip", "radon_fwd_t2.hip",
+                     "radon_fwd_t3.hip", "radon_launch.hpp", "radon_plan.hpp", "radon_planner.cpp",
+                     "radon_tiles.hpp")
 
 
 def kernel_sources_sha256():
@@ -60,6 +62,13 @@ def _record_fields(path, tag):
     if not m or m.group(1) != kernel_sources_sha256():
         return None
     return dict(kv.split("=", 1) for kv in m.group(2).split())
+
+
+def shape_key(info):
+    """Launch shape of one direction as the counter records key it: variant, images
+    per lane, angles per item or block, staging, and the forward's slab rows."""
+    key = f"{info['variant']},{info['images']},{info['angles']},{info['staging']}"
+    return key + (f",{info['rows']}" if "rows" in info else "")
 
 
 def recorded_traffic(direction, shape):
@@ -262,7 +271,7 @@ def main():
     dom_ms = max(fwd_ms, bp_ms)
     achieved = flop / (dom_ms * 1e-3) / 1e12
     info = op.plan_info(torch.float32, B)[dom]
-    shape = f"{info['variant']},{info['images']},{info['angles']},{info['staging']}"
+    shape = shape_key(info)
     kernels = {("forward", 1, 1): "interleave_images + fwd_tiled_il", ("forward", 1, 0): "fwd_tiled",
                ("backprojection", 1, 1): "interleave_sinograms + bp_tiled_par_il",
                ("backprojection", 1, 0): "bp_tiled_par"}.get(
@@ -298,9 +307,7 @@ def main():
     directions = {"forward": direction(fwd_ms, 4.0 * samples, 16.0 * samples),
                   "backprojection": direction(bp_ms, 3.0 * triples, 12.0 * triples)}
     for d in directions:
-        di = op.plan_info(torch.float32, B)[d]
-        directions[d]["counters"] = recorded_cache_counters(
-            d, f"{di['variant']},{di['images']},{di['angles']},{di['staging']}")
+        directions[d]["counters"] = recorded_cache_counters(d, shape_key(op.plan_info(torch.float32, B)[d]))
     peaks = {"fma_per_s": fma_peak, "lds_bytes_per_s": lds_peak,
              "method": "radon_measure_peaks: v_fmac_f32 chains (packed FP32 off) and conflict-free "
                        "ds_read_b128 streams on this GPU, best of 3 runs"}

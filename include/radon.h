@@ -297,16 +297,17 @@ int radon_release_plans(void);
 
 /* Library utility (no operation of the paper): launch shape chosen for a
  * geometry/dtype/batch (after radon_prepare):
- * out[0..3] = forward {images per thread, angles per block, staging, variant},
- * out[4..7] = the same for the backprojection.  variant: 0 = direct kernel, 1 = tiled
+ * out[0..4] = forward {images per thread, angles per work item, staging, variant,
+ * slab rows}, out[5..9] = backprojection {images per thread, angles per LDS block,
+ * staging, variant, tile side in pixels}.  variant: 0 = direct kernel, 1 = tiled
  * kernel.  staging: 1 when the tiled kernel first copies the call's input (images,
  * or sinograms for the backprojection) into a zero-bordered, image-interleaved
- * workspace; 2 (forward, 16-bit storage) when that copy holds pairs of neighbouring
- * pixels and each pair of bilinear taps is applied by one FP32-accumulating dot2
- * instruction with the weights rounded to the storage type; else 0.  Builds the plan
- * when missing; status codes as radon_forward. */
+ * workspace; 2 (16-bit storage) when that copy holds pairs of neighbouring pixels
+ * (bins) and each pair of taps is applied by one FP32-accumulating dot2 instruction
+ * with the weights rounded to the storage type; else 0.  Builds the plan when
+ * missing; status codes as radon_forward. */
 int radon_plan_info(const radon_geometry_t *geometry, int32_t dtype, int32_t batch,
-                    int32_t *out8);
+                    int32_t *out10);
 
 /* Library utility (no operation of the paper): static description of a status code. */
 const char *radon_status_string(int status);

@@ -11,7 +11,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libradon.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["radon_abi.cpp", "radon_planner.cpp", "radon_autotune.cpp", "radon_fwd.hip", "radon_bp.hip", "radon_dot.hip", "radon_batched.hip", "radon_filter.hip", "radon_vec.hip", "radon_solvers.cpp", "radon_peaks.hip", "radon_shearlet.hip", "radon_shearlet_host.cpp"]
+SOURCES = ["radon_abi.cpp", "radon_planner.cpp", "radon_autotune.cpp", "radon_fwd.hip", "radon_fwd_t0.hip", "radon_fwd_t1.hip", "radon_fwd_t2.hip", "radon_fwd_t3.hip", "radon_bp.hip", "radon_dot.hip", "radon_batched.hip", "radon_filter.hip", "radon_vec.hip", "radon_solvers.cpp", "radon_peaks.hip", "radon_shearlet.hip", "radon_shearlet_host.cpp"]
 
 # Packed FP32 instructions are switched off for all device code.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall", "-Wno-unused-function",

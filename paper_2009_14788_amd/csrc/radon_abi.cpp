@@ -107,8 +107,10 @@ Plan::~Plan() {
     if (trig) (void)hipFree(trig);
     if (rays) (void)hipFree(rays);
     if (bpa) (void)hipFree(bpa);
-    if (fwd_items) (void)hipFree(fwd_items);
-    if (fwd_ranges) (void)hipFree(fwd_ranges);
+    for (int t = 0; t < kFwdTilings; ++t) {
+        if (fwd_items[t]) (void)hipFree(fwd_items[t]);
+        if (fwd_ranges[t]) (void)hipFree(fwd_ranges[t]);
+    }
 }
 
 static std::mutex g_mutex;
@@ -227,9 +229,15 @@ static int build_plan(const radon_geometry_t *g, int device, std::unique_ptr<Pla
     int tile_t = 0;
     const char *force = std::getenv("RADON_VARIANT");
     const bool want_direct = force && std::strcmp(force, "direct") == 0;
-    if (!want_direct &&
-        plan_forward_tiles(g->image_size, g->n_angles, g->det_count, rays, items, ranges, tile_t) &&
-        !items.empty()) {
+    // tiled forward: one plan per tiling (tiling 0 decides whether the tiled kernels
+    // apply at all; another tiling that does not fit keeps n_items = 0)
+    for (int t = 0; t < kFwdTilings && !want_direct; ++t) {
+        if (!plan_forward_tiles(g->image_size, g->n_angles, g->det_count, rays, kFwdTiling[t].slab_h,
+                                kFwdTiling[t].waves, items, ranges, tile_t) ||
+            items.empty()) {
+            if (t == 0) break;
+            continue;
+        }
         // longest items first (slabs the item's rays cross): blocks are dispatched in
         // index order, so the short items fill the tail of the launch
         std::vector<int> slabs(items.size(), 0);
@@ -243,23 +251,25 @@ static int build_plan(const radon_geometry_t *g, int device, std::unique_ptr<Pla
         std::vector<FwdItem> sorted(items.size());
         for (size_t i = 0; i < order.size(); ++i) sorted[i] = items[order[i]];
         items.swap(sorted);
-        if (hipMalloc(&p->fwd_items, items.size() * sizeof(FwdItem)) != hipSuccess)
+        if (hipMalloc(&p->fwd_items[t], items.size() * sizeof(FwdItem)) != hipSuccess)
             return RADON_ERR_ALLOC;
-        if (hipMemcpy(p->fwd_items, items.data(), items.size() * sizeof(FwdItem),
+        if (hipMemcpy(p->fwd_items[t], items.data(), items.size() * sizeof(FwdItem),
                       hipMemcpyHostToDevice) != hipSuccess)
             return RADON_ERR_HIP;
         const size_t nr = std::max<size_t>(ranges.size(), 1);
-        if (hipMalloc(&p->fwd_ranges, nr * sizeof(int2)) != hipSuccess) return RADON_ERR_ALLOC;
-        if (!ranges.empty() && hipMemcpy(p->fwd_ranges, ranges.data(), ranges.size() * sizeof(int2),
+        if (hipMalloc(&p->fwd_ranges[t], nr * sizeof(int2)) != hipSuccess) return RADON_ERR_ALLOC;
+        if (!ranges.empty() && hipMemcpy(p->fwd_ranges[t], ranges.data(), ranges.size() * sizeof(int2),
                                          hipMemcpyHostToDevice) != hipSuccess)
             return RADON_ERR_HIP;
-        p->fwd_items_host = items;
-        p->fwd_work.items = p->fwd_items;
-        p->fwd_work.ranges = p->fwd_ranges;
-        p->fwd_work.n_items = (int)items.size();
+        FwdWork &w = p->fwd_work[t];
+        w.items = p->fwd_items[t];
+        w.ranges = p->fwd_ranges[t];
+        w.n_items = (int)items.size();
         // LDS row pitch: 8 more than a multiple of 16 chunks, so the taps of lanes
         // whose samples sit in neighbouring rows land half a bank cycle apart
-        p->fwd_work.tile_t = (tile_t + 15 - kFwdPitchMod) / 16 * 16 + kFwdPitchMod;
+        w.tile_t = (tile_t + 15 - kFwdPitchMod) / 16 * 16 + kFwdPitchMod;
+        if (t > 0) continue;
+        p->fwd_items_host = items;
         p->fwd_shape.variant = VARIANT_TILED;
         const char *il = std::getenv("RADON_FWD_INTERLEAVE");
         p->no_interleave = il && std::strcmp(il, "0") == 0;
@@ -267,6 +277,7 @@ static int build_plan(const radon_geometry_t *g, int device, std::unique_ptr<Pla
         p->fwd_shape.images = (imgs && std::atoi(imgs) >= 16) ? 16 : 8;
         p->fwd_shape.angles = kFwdWaves;
         p->fwd_shape.rays = kFwdLanes;
+        p->fwd_shape.tiling = 0;
     }
     // tiled backprojection
     if (!want_direct) {
@@ -527,7 +538,7 @@ static int build_batch_table(const std::vector<Plan *> &plans, const radon_job_t
         Plan *p = plans[i];
         if (jobs[i].batch == 0) continue;
         const bool tiled = direction == 0
-                               ? (p->fwd_shape.variant == VARIANT_TILED && p->fwd_work.n_items > 0)
+                               ? (p->fwd_shape.variant == VARIANT_TILED && p->fwd_work[0].n_items > 0)
                                : (p->bp_shape.variant == VARIANT_TILED && p->bp_work.window > 0);
         if (!tiled) {
             t->fallback.push_back(i);
@@ -552,9 +563,9 @@ static int build_batch_table(const std::vector<Plan *> &plans, const radon_job_t
         const std::vector<Img> &v = pool[p];
         BatchJob j{};
         j.g = p->geom;
-        j.items = p->fwd_work.items;
-        j.ranges = p->fwd_work.ranges;
-        j.tile_t = p->fwd_work.tile_t;
+        j.items = p->fwd_work[0].items;
+        j.ranges = p->fwd_work[0].ranges;
+        j.tile_t = p->fwd_work[0].tile_t;
         j.window = p->bp_work.window;
         j.bins = p->bp_work.bins;
         const int jid = (int)bj.size();
@@ -692,7 +703,7 @@ static int run_batched(const radon_job_t *jobs, int32_t n, int32_t dtype, int di
     for (int i : t->fallback) {
         const Plan *p = plans[i];
         hipError_t e = direction == 0
-            ? launch_forward(p->geom, p->fwd_work, dtype, p->fwd_shape, jobs[i].input,
+            ? launch_forward(p->geom, p->fwd_work[0], dtype, p->fwd_shape, jobs[i].input,
                              jobs[i].output, jobs[i].batch, jobs[i].scale, nullptr, 0, s)
             : launch_backproject(p->geom, p->bp_work, dtype, p->bp_shape, jobs[i].input,
                                  jobs[i].output, jobs[i].batch, jobs[i].scale, nullptr, 0, s);
@@ -726,19 +737,26 @@ static int release_all() {
     return RADON_OK;
 }
 
+// The forward tiling t if its plan exists, else tiling 0.
+static void use_tiling(const Plan *p, LaunchShape &fwd, int t) {
+    fwd.tiling = (t >= 0 && t < kFwdTilings && p->fwd_work[t].n_items > 0) ? t : 0;
+    fwd.angles = kFwdTiling[fwd.tiling].waves;
+}
+
 // Launch shapes for a call: the autotuned ones for this storage type and batch class
 // when radon_prepare has tuned them, else the plan's defaults.
-// RADON_FORCE_SHAPE="fi,fs,bi,ba[,bs]" overrides both (used to test every variant).
+// RADON_FORCE_SHAPE="fi,fs,bi,ba[,bs[,ft]]" overrides both (used to test every variant).
 static void call_shapes(Plan *p, int dtype, int batch, LaunchShape &fwd, LaunchShape &bp) {
     fwd = p->fwd_shape;
     bp = p->bp_shape;
-    // test hook: "fwd images, fwd staging, bp images, bp angles[, bp staging]"
+    // test hook: "fwd images, fwd staging, bp images, bp angles[, bp staging[, fwd tiling]]"
     if (const char *f = std::getenv("RADON_FORCE_SHAPE")) {
-        int fi, fs, bi, ba, bs = 1;
-        const int k = std::sscanf(f, "%d,%d,%d,%d,%d", &fi, &fs, &bi, &ba, &bs);
+        int fi, fs, bi, ba, bs = 1, ft = 0;
+        const int k = std::sscanf(f, "%d,%d,%d,%d,%d,%d", &fi, &fs, &bi, &ba, &bs, &ft);
         if (k >= 4) {
             fwd.images = fi;
             fwd.stage = fs;
+            use_tiling(p, fwd, ft);
             bp.images = bi;
             if (!p->geom.fan) bp.angles = ba;
             bp.stage = bs;
@@ -760,6 +778,7 @@ static void call_shapes(Plan *p, int dtype, int batch, LaunchShape &fwd, LaunchS
     bp.variant = it->second.bp_variant;
     fwd.images = it->second.fwd_images;
     fwd.stage = it->second.fwd_stage;
+    use_tiling(p, fwd, it->second.fwd_tiling);
     bp.images = it->second.bp_images;
     bp.angles = it->second.bp_angles;
     bp.stage = it->second.bp_stage;
@@ -821,9 +840,9 @@ int radon_forward(const radon_geometry_t *geometry, const void *x, void *y, int3
     call_shapes(p, dtype, batch, fwd, bp);
     void *ws = nullptr;
     size_t ws_bytes = 0;
-    if (fwd.variant == VARIANT_TILED && fwd.stage && p->fwd_work.n_items > 0 && !p->no_interleave)
+    if (fwd.variant == VARIANT_TILED && fwd.stage && p->fwd_work[fwd.tiling].n_items > 0 && !p->no_interleave)
         ws = stream_workspace(s, interleaved_bytes(geometry->image_size, batch, dtype), &ws_bytes);
-    hipError_t e = launch_forward(p->geom, p->fwd_work, dtype, fwd, x, y, batch, scale, ws,
+    hipError_t e = launch_forward(p->geom, p->fwd_work[fwd.tiling], dtype, fwd, x, y, batch, scale, ws,
                                   ws_bytes, s);
     return e == hipSuccess ? RADON_OK : RADON_ERR_HIP;
 }
@@ -951,11 +970,11 @@ int radon_axpy_ratio(const void *u, const void *v, void *out, const double *num,
 int radon_release_plans(void) { return release_all(); }
 
 int radon_plan_info(const radon_geometry_t *geometry, int32_t dtype, int32_t batch,
-                    int32_t *out8) {
+                    int32_t *out10) {
     int rc = validate(geometry);
     if (rc != RADON_OK) return rc;
     if ((rc = check_dtype(dtype)) != RADON_OK) return rc;
-    if (!out8 || batch < 0) return RADON_ERR_INVALID_ARG;
+    if (!out10 || batch < 0) return RADON_ERR_INVALID_ARG;
     Plan *p = nullptr;
     if ((rc = get_plan(geometry, nullptr, &p)) != RADON_OK) return rc;
     LaunchShape fwd, bp;
@@ -964,11 +983,13 @@ int radon_plan_info(const radon_geometry_t *geometry, int32_t dtype, int32_t bat
     if (fwd.variant != VARIANT_TILED || p->no_interleave) fwd.stage = 0;
     const LaunchShape *sh[2] = {&fwd, &bp};
     for (int i = 0; i < 2; ++i) {
-        out8[4 * i + 0] = sh[i]->images;
-        out8[4 * i + 1] = sh[i]->angles;
-        out8[4 * i + 2] = sh[i]->stage;
-        out8[4 * i + 3] = sh[i]->variant;
+        out10[5 * i + 0] = sh[i]->images;
+        out10[5 * i + 1] = sh[i]->angles;
+        out10[5 * i + 2] = sh[i]->stage;
+        out10[5 * i + 3] = sh[i]->variant;
     }
+    out10[4] = kFwdTiling[fwd.tiling].slab_h;
+    out10[9] = kBpTile;
     return RADON_OK;
 }
 

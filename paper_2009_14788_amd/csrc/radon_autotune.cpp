@@ -3,7 +3,8 @@
 //
 // Forward candidates: images per lane {8, 4 (FP32 only), 16 (16-bit only)} x slab
 // staging {interleaved copy, caller's images, and for 16-bit storage the tap-pair copy
-// with dot2 arithmetic}, and the direct kernel.
+// with dot2 arithmetic} x tiling (kFwdTiling: slab rows {11, 7, 15} with 8 angles per
+// work item, and 11 rows with 4 angles), and the direct kernel.
 // Backprojection candidates: images per lane {64, 32, 16, one chunk (batches <= 8)} x
 // angles per LDS block {8, 4}
 // (parallel beam; the fan beam's block is fixed at 4 because its rays are staged
@@ -12,7 +13,7 @@
 // tiled kernels' sequential slabs and angle blocks are latency-bound.  Results live in the plan
 // and, when RADON_TUNE_CACHE names a file, in that file (one line per entry:
 // "<key> <fwd variant> <fwd images> <fwd stage> <bp variant> <bp images> <bp angles>
-// <bp stage>"),
+// <bp stage> <fwd tiling>"),
 // so later processes skip the timing.
 #include <hip/hip_runtime.h>
 
@@ -49,8 +50,9 @@ static bool cache_lookup(const std::string &key, TunedShapes &out) {
     while (std::getline(f, line)) {
         std::istringstream ls(line);
         std::string k;
-        int fv, fi, fs, bv, bi, ba, bs;
+        int fv, fi, fs, bv, bi, ba, bs, ft = 0;
         if (!(ls >> k >> fv >> fi >> fs >> bv >> bi >> ba >> bs) || k != key) continue;
+        if (!(ls >> ft) || ft < 0 || ft >= kFwdTilings) ft = 0;   // lines of older versions: tiling 0
         out.fwd_variant = fv;
         out.bp_variant = bv;
         out.fwd_images = fi;
@@ -58,6 +60,7 @@ static bool cache_lookup(const std::string &key, TunedShapes &out) {
         out.bp_images = bi;
         out.bp_angles = ba;
         out.bp_stage = bs;
+        out.fwd_tiling = ft;
         return true;
     }
     return false;
@@ -68,7 +71,8 @@ static void cache_store(const std::string &key, const TunedShapes &t) {
     if (!path || !*path) return;
     std::ofstream f(path, std::ios::app);
     f << key << " " << t.fwd_variant << " " << t.fwd_images << " " << t.fwd_stage << " "
-      << t.bp_variant << " " << t.bp_images << " " << t.bp_angles << " " << t.bp_stage << "\n";
+      << t.bp_variant << " " << t.bp_images << " " << t.bp_angles << " " << t.bp_stage << " "
+      << t.fwd_tiling << "\n";
 }
 
 // Average milliseconds of `reps` launches after one warm-up; a negative value when
@@ -125,27 +129,32 @@ int autotune(Plan &p, int dtype, int batch, void *ws, size_t ws_bytes, TunedShap
         float best = time_launches([&] {
             LaunchShape sh = p.fwd_shape;
             sh.variant = VARIANT_DIRECT;
-            return launch_forward(p.geom, p.fwd_work, dtype, sh, x, y, batch, 1.0f, ws, ws_bytes, s);
+            return launch_forward(p.geom, p.fwd_work[0], dtype, sh, x, y, batch, 1.0f, ws, ws_bytes, s);
         }, s);
         out.fwd_variant = VARIANT_DIRECT;
         const std::vector<int> stages = dtype == F32 ? std::vector<int>{1, 0} : std::vector<int>{2, 1, 0};
-        for (int im : imgs)
-            for (int st : stages) {
-                if (st > 0 && p.no_interleave) continue;
-                LaunchShape sh = p.fwd_shape;
-                sh.images = im;
-                sh.stage = st;
-                const float ms = time_launches([&] {
-                    return launch_forward(p.geom, p.fwd_work, dtype, sh, x, y, batch, 1.0f, ws,
-                                          ws_bytes, s);
-                }, s);
-                if (ms > 0.0f && (best < 0.0f || ms < best)) {
-                    best = ms;
-                    out.fwd_variant = VARIANT_TILED;
-                    out.fwd_images = im;
-                    out.fwd_stage = st;
+        for (int t = 0; t < kFwdTilings; ++t) {
+            if (p.fwd_work[t].n_items == 0) continue;
+            for (int im : imgs)
+                for (int st : stages) {
+                    if (st > 0 && p.no_interleave) continue;
+                    LaunchShape sh = p.fwd_shape;
+                    sh.images = im;
+                    sh.stage = st;
+                    sh.tiling = t;
+                    const float ms = time_launches([&] {
+                        return launch_forward(p.geom, p.fwd_work[t], dtype, sh, x, y, batch, 1.0f, ws,
+                                              ws_bytes, s);
+                    }, s);
+                    if (ms > 0.0f && (best < 0.0f || ms < best)) {
+                        best = ms;
+                        out.fwd_variant = VARIANT_TILED;
+                        out.fwd_images = im;
+                        out.fwd_stage = st;
+                        out.fwd_tiling = t;
+                    }
                 }
-            }
+        }
     }
     if (p.bp_shape.variant == VARIANT_TILED) {
         float best = time_launches([&] {

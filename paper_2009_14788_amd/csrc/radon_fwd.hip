@@ -7,7 +7,7 @@
 
 #include "radon_common.hpp"
 #include "radon_launch.hpp"
-#include "radon_tiles.hpp"
+#include "radon_fwd_tiled.hpp"
 
 namespace radon {
 
@@ -66,52 +66,6 @@ __global__ __launch_bounds__(256) void fwd_direct(Geom g, const T *__restrict__ 
             Store<T>::store(y + ((size_t)(b0 + i) * g.n_angles + a) * g.det_count + d,
                             acc[i] * scale_dt);
     }
-}
-
-// ------------------------------------------------------------------ tiled variant
-// Waves per SIMD the tiled kernels are compiled for: two-plane kernels (FP32 with 8
-// images, 16-bit with 16) are held to <= 80 registers, so that LDS, not registers,
-// caps them, at three blocks (6 waves per SIMD) for items up to ~120 columns wide.
-// The FP32 kernel needs 66 registers then; the BF16 one spills one or two registers
-// and still runs 12% faster than at two blocks.
-// Tap-pair kernels (16-bit, four images per chunk) have FP32's LDS footprint: the
-// 8-image one is held to the same bound; the 16-image one fits one block per CU.
-template <typename T, int BC, bool PAIRS = false>
-constexpr int kFwdMinWaves = PAIRS ? (BC == 8 ? 6 : 2) : ((sizeof(T) == 2 || BC == 8) ? 6 : 1);
-
-// One block = one work item of the plan x BC images (blockIdx.y selects the images).
-template <typename T, int BC>
-__global__ __launch_bounds__(kFwdThreads, (kFwdMinWaves<T, BC>)) void fwd_tiled(Geom g, FwdWork work, const T *__restrict__ x,
-                                                 T *__restrict__ y, int batch, float scale_dt,
-                                                 int tile_t) {
-    extern __shared__ uint4 lds[];
-    const FwdItem it = work.items[blockIdx.x];
-    const ImageSet<T, BC> imgs = contiguous_images<T, BC>(
-        x, (size_t)g.n * g.n, y, (size_t)g.n_angles * g.det_count, batch, blockIdx.y * BC, scale_dt);
-    const PointerSource<T, BC> src{imgs.in, g.n};
-    fwd_item<T, BC>(g, it, work.ranges, imgs, src, tile_t, lds);
-}
-
-// Same, staging from the interleaved, zero-bordered copies of the batch: xi holds
-// the row-major copy [groups][N+4][N+4] followed by the transposed copy (PAIRS: copies
-// of tap pairs, four images per chunk).  PITCH > 0: LDS rows of that many chunks (the
-// plan's windows are at most that wide), fixed at compile time so the tap offsets are
-// immediates.
-template <typename T, int BC, int PITCH, bool PAIRS = false>
-__global__ __launch_bounds__(kFwdThreads, (kFwdMinWaves<T, BC, PAIRS>)) void fwd_tiled_il(Geom g, FwdWork work, const uint4 *__restrict__ xi,
-                                                    T *__restrict__ y, int batch, float scale_dt,
-                                                    int tile_t, int groups) {
-    extern __shared__ uint4 lds[];
-    constexpr int CH = PAIRS ? 4 : Chunk<T>::kImages;
-    const FwdItem it = work.items[blockIdx.x];
-    const int b0 = blockIdx.y * BC;
-    // only the output side of the image set is used with an interleaved source
-    const ImageSet<T, BC> imgs = contiguous_images<T, BC>(
-        y, 0, y, (size_t)g.n_angles * g.det_count, batch, b0, scale_dt);
-    const int plane = (g.n + 4) * (g.n + 4);
-    const uint4 *first = xi + (size_t)(b0 / CH) * plane;
-    const InterleavedSource<T, BC, PAIRS> src{first, first + (size_t)groups * plane, g.n, plane};
-    fwd_item<T, BC, InterleavedSource<T, BC, PAIRS>, PITCH>(g, it, work.ranges, imgs, src, tile_t, lds);
 }
 
 // Interleave a batch x[B][N][N] into chunks of CH images with a zero border of 2
@@ -216,62 +170,34 @@ static hipError_t launch_fwd_direct(const Geom &g, const void *x, void *y, int b
     return hipGetLastError();
 }
 
-// Tiled forward with 16-bit tap pairs (stage 2): pair copies, then the pair kernel.
-template <typename T, int BC>
-static hipError_t launch_fwd_pairs(const Geom &g, const FwdWork &work, const void *x, void *y,
-                                   int batch, float scale_dt, void *ws, hipStream_t s) {
-    constexpr int PLANES = BC / Pair<T>::kImages;
-    const size_t lds = (size_t)PLANES * (kSlabH + 3) * work.tile_t * sizeof(uint4);
-    const size_t lds_fixed = (size_t)PLANES * (kSlabH + 3) * kFwdPitchFixed * sizeof(uint4);
-    dim3 grid(work.n_items, (batch + BC - 1) / BC);
-    const int groups = (batch + BC - 1) / BC * PLANES;
-    const int tiles = (g.n + 4 + kIlTile - 1) / kIlTile;
-    hipLaunchKernelGGL(interleave_pairs<T>, dim3(tiles * tiles, groups), dim3(256), 0, s,
-                       (const T *)x, (uint4 *)ws, g.n, batch, groups);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (work.tile_t <= kFwdPitchFixed)
-        hipLaunchKernelGGL((fwd_tiled_il<T, BC, kFwdPitchFixed, true>), grid, dim3(kFwdThreads),
-                           lds_fixed, s, g, work, (const uint4 *)ws, (T *)y, batch, scale_dt,
-                           kFwdPitchFixed, groups);
-    else
-        hipLaunchKernelGGL((fwd_tiled_il<T, BC, 0, true>), grid, dim3(kFwdThreads), lds, s, g, work,
-                           (const uint4 *)ws, (T *)y, batch, scale_dt, work.tile_t, groups);
-    return hipGetLastError();
-}
-
-template <typename T, int BC>
-static hipError_t launch_fwd_tiled(const Geom &g, const FwdWork &work, const void *x, void *y,
-                                   int batch, float scale_dt, int stage, void *ws, size_t ws_bytes,
-                                   hipStream_t s) {
-    constexpr int CH = Chunk<T>::kImages;
-    constexpr int PLANES = BC / CH;
-    const size_t lds = (size_t)PLANES * (kSlabH + 3) * work.tile_t * sizeof(uint4);
-    const size_t lds_fixed = (size_t)PLANES * (kSlabH + 3) * kFwdPitchFixed * sizeof(uint4);
-    dim3 grid(work.n_items, (batch + BC - 1) / BC);
-    const int dt = sizeof(T) == 4 ? F32 : F16;
-    if constexpr (sizeof(T) == 2) {
-        if (stage == 2 && ws && ws_bytes >= interleaved_bytes(g.n, batch, dt))
-            return launch_fwd_pairs<T, BC>(g, work, x, y, batch, scale_dt, ws, s);
-    }
-    if (ws && stage && ws_bytes >= interleaved_bytes(g.n, batch, dt)) {
-        // groups of the launch: whole BC-image blocks (<= the groups interleaved_bytes counts)
-        const int groups = (batch + BC - 1) / BC * PLANES;
-        const int tiles = (g.n + 4 + kIlTile - 1) / kIlTile;
-        hipLaunchKernelGGL(interleave_images<T>, dim3(tiles * tiles, groups), dim3(256), 0, s,
-                           (const T *)x, (uint4 *)ws, g.n, batch, groups);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        if (work.tile_t <= kFwdPitchFixed)
-            hipLaunchKernelGGL((fwd_tiled_il<T, BC, kFwdPitchFixed>), grid, dim3(kFwdThreads),
-                               lds_fixed, s, g, work, (const uint4 *)ws, (T *)y, batch, scale_dt,
-                               kFwdPitchFixed, groups);
-        else
-            hipLaunchKernelGGL((fwd_tiled_il<T, BC, 0>), grid, dim3(kFwdThreads), lds, s, g, work,
-                               (const uint4 *)ws, (T *)y, batch, scale_dt, work.tile_t, groups);
-    } else {
-        hipLaunchKernelGGL((fwd_tiled<T, BC>), grid, dim3(kFwdThreads), lds, s, g, work, (const T *)x,
-                           (T *)y, batch, scale_dt, work.tile_t);
+// Interleaved copies of the call's images for the tiled kernels (tiling independent):
+// `groups` groups of four images (tap pairs) or of Chunk<T>::kImages images.
+hipError_t launch_interleave(int dtype, bool pairs, const void *x, void *ws, int n, int batch,
+                             int groups, hipStream_t s) {
+    const int tiles = (n + 4 + kIlTile - 1) / kIlTile;
+    const dim3 grid(tiles * tiles, groups);
+    switch (dtype * 2 + (pairs ? 1 : 0)) {
+    case F32 * 2:
+        hipLaunchKernelGGL(interleave_images<float>, grid, dim3(256), 0, s, (const float *)x, (uint4 *)ws,
+                           n, batch, groups);
+        break;
+    case F16 * 2:
+        hipLaunchKernelGGL(interleave_images<__half>, grid, dim3(256), 0, s, (const __half *)x, (uint4 *)ws,
+                           n, batch, groups);
+        break;
+    case F16 * 2 + 1:
+        hipLaunchKernelGGL(interleave_pairs<__half>, grid, dim3(256), 0, s, (const __half *)x, (uint4 *)ws,
+                           n, batch, groups);
+        break;
+    case BF16 * 2:
+        hipLaunchKernelGGL(interleave_images<bf16_t>, grid, dim3(256), 0, s, (const bf16_t *)x, (uint4 *)ws,
+                           n, batch, groups);
+        break;
+    case BF16 * 2 + 1:
+        hipLaunchKernelGGL(interleave_pairs<bf16_t>, grid, dim3(256), 0, s, (const bf16_t *)x, (uint4 *)ws,
+                           n, batch, groups);
+        break;
+    default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
@@ -281,20 +207,11 @@ hipError_t launch_forward(const Geom &g, const FwdWork &work, int dtype, const L
                           size_t ws_bytes, hipStream_t s) {
     const float scale_dt = (float)(scale * g.step);
     if (shape.variant == VARIANT_TILED && work.n_items > 0) {
-        const int st = shape.stage;
-        switch (dtype) {
-        case F32:
-            if (shape.images <= 4)
-                return launch_fwd_tiled<float, 4>(g, work, x, y, batch, scale_dt, st, ws, ws_bytes, s);
-            return launch_fwd_tiled<float, 8>(g, work, x, y, batch, scale_dt, st, ws, ws_bytes, s);
-        case F16:
-            if (shape.images >= 16)
-                return launch_fwd_tiled<__half, 16>(g, work, x, y, batch, scale_dt, st, ws, ws_bytes, s);
-            return launch_fwd_tiled<__half, 8>(g, work, x, y, batch, scale_dt, st, ws, ws_bytes, s);
-        case BF16:
-            if (shape.images >= 16)
-                return launch_fwd_tiled<bf16_t, 16>(g, work, x, y, batch, scale_dt, st, ws, ws_bytes, s);
-            return launch_fwd_tiled<bf16_t, 8>(g, work, x, y, batch, scale_dt, st, ws, ws_bytes, s);
+        switch (shape.tiling) {
+        case 0: return launch_forward_tiling0(g, work, dtype, shape, x, y, batch, scale_dt, ws, ws_bytes, s);
+        case 1: return launch_forward_tiling1(g, work, dtype, shape, x, y, batch, scale_dt, ws, ws_bytes, s);
+        case 2: return launch_forward_tiling2(g, work, dtype, shape, x, y, batch, scale_dt, ws, ws_bytes, s);
+        case 3: return launch_forward_tiling3(g, work, dtype, shape, x, y, batch, scale_dt, ws, ws_bytes, s);
         default: return hipErrorInvalidValue;
         }
     }

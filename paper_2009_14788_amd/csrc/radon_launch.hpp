@@ -18,16 +18,18 @@ struct LaunchShape {
     int images = 4;       // images per thread (accumulators per lane)
     int angles = 1;       // angles per block (forward: waves; backprojection: LDS angle block)
     int rays = 256;       // forward: bins per block; backprojection: pixels per block
-    int stage = 1;        // tiled staging: 1 = interleaved workspace copy, 0 = caller's buffers
+    int stage = 1;        // tiled staging: 1 = interleaved workspace copy, 0 = caller's buffers,
+                          // 2 = 16-bit tap-pair copy
+    int tiling = 0;       // forward: index into kFwdTiling (slab rows, angles per item)
 };
 
 // ------------------------------------------------------------------ tiled forward work
-// One work item of the tiled forward projector: up to kFwdWaves angles x up to 64
+// One work item of the tiled forward projector: up to W angles x up to 64
 // consecutive bins (one lane per ray), marched through the image in slabs of
-// kSlabH pixel rows (axis 0) or columns (axis 1).  For every slab the item stages
-// into LDS the pixel rows/columns [m_lo-1, m_lo+kSlabH+1] along the march axis and
-// the transverse index range ranges[range + s - slab0] (inclusive, clamped to
-// [-2, N+1]), where m_lo = -1 + s*kSlabH.
+// H pixel rows (axis 0) or columns (axis 1), (H, W) the plan's tiling.  For every
+// slab the item stages into LDS the pixel rows/columns [m_lo-1, m_lo+H+1] along the
+// march axis and the transverse index range ranges[range + s - slab0] (inclusive,
+// clamped to [-2, N+1]), where m_lo = -1 + s*H.
 struct FwdItem {
     int a0, na;
     int d0, nd;
@@ -36,23 +38,35 @@ struct FwdItem {
     int range;
 };
 
-#ifndef RADON_SLAB_H
-#define RADON_SLAB_H 11
-#endif
-// pixel rows (columns) per slab.  11 keeps the FP32 8-image slab of a 512^2 item
-// under 53 KB, so three 512-thread blocks share a compute unit's 160 KB of LDS;
-// on the MI355X that beat 12 (two blocks), 10, 8 and 7 (with four blocks)
-constexpr int kSlabH = RADON_SLAB_H;
-#ifndef RADON_FWD_WAVES
-#define RADON_FWD_WAVES 8
-#endif
-constexpr int kFwdWaves = RADON_FWD_WAVES;   // angles (waves) per forward work item
-constexpr int kFwdThreads = 64 * kFwdWaves;  // threads per forward block
-#ifndef RADON_FWD_QBINS
-#define RADON_FWD_QBINS 2
-#endif
-constexpr int kFwdQBins = RADON_FWD_QBINS;        // bins per 16-lane quarter wave
-constexpr int kFwdQAngles = 16 / kFwdQBins;       // angles per quarter wave
+// Tilings of the tiled forward, chosen per plan by the autotuner: slab rows H, angles
+// (waves of 64 lanes) per item W, and bins per 16-lane quarter wave Q (a quarter takes
+// Q neighbouring bins x 16/Q neighbouring angles, so its taps fall on nearby columns).
+// Tiling 0 (11-row slabs, 8 angles) keeps the FP32 8-image slab of a 512^2 item under
+// 53 KB, so three 512-thread blocks share a compute unit's 160 KB of LDS; shorter
+// slabs fit more blocks, longer ones stage fewer overlapping rows per sample, and
+// 4-angle items suit few-angle geometries.
+template <int H, int W, int Q>
+struct FwdCfg {
+    static constexpr int kSlabH = H;
+    static constexpr int kWaves = W;
+    static constexpr int kThreads = 64 * W;
+    static constexpr int kQBins = Q;
+    static constexpr int kQAngles = 16 / Q;
+    static_assert(Q * kQAngles == 16 && W % kQAngles == 0, "lane mapping");
+};
+struct FwdTiling {
+    int slab_h, waves, qbins;
+};
+constexpr int kFwdTilings = 4;
+constexpr FwdTiling kFwdTiling[kFwdTilings] = {{11, 8, 2}, {7, 8, 2}, {15, 8, 2}, {11, 4, 4}};
+using FwdCfg0 = FwdCfg<11, 8, 2>;
+using FwdCfg1 = FwdCfg<7, 8, 2>;
+using FwdCfg2 = FwdCfg<15, 8, 2>;
+using FwdCfg3 = FwdCfg<11, 4, 4>;
+// tiling 0, used by the uneven-batch kernels
+constexpr int kSlabH = FwdCfg0::kSlabH;
+constexpr int kFwdWaves = FwdCfg0::kWaves;
+constexpr int kFwdThreads = FwdCfg0::kThreads;
 #ifndef RADON_FWD_PITCH_MOD
 #define RADON_FWD_PITCH_MOD 8
 #endif
@@ -73,10 +87,12 @@ struct FwdWork {
 };
 
 // Host planning of the tiled forward projector from FP64 ray parameters
-// (rays[a*D+d] = (ox, oy, sx, sy) in index coordinates).  Returns false when some
-// block of rays does not fit the tiled kernel; the direct kernel is used then.
+// (rays[a*D+d] = (ox, oy, sx, sy) in index coordinates) for slabs of slab_h rows and
+// up to `angles` angles per item.  Returns false when some block of rays does not fit
+// the tiled kernel; the direct kernel is used then.
 bool plan_forward_tiles(int n, int n_angles, int det_count, const std::vector<double4> &rays,
-                        std::vector<FwdItem> &items, std::vector<int2> &ranges, int &tile_t);
+                        int slab_h, int angles, std::vector<FwdItem> &items,
+                        std::vector<int2> &ranges, int &tile_t);
 
 // ws: optional workspace for the interleaved copy of the input batch (used by the
 // tiled kernel when ws_bytes >= interleaved_bytes(n, batch, dtype)).
@@ -84,6 +100,20 @@ hipError_t launch_forward(const Geom &g, const FwdWork &work, int dtype, const L
                           const void *x, void *y, int batch, float scale, void *ws,
                           size_t ws_bytes, hipStream_t s);
 size_t interleaved_bytes(int n, int batch, int dtype);
+// The tiled forward's interleaved copies of a batch (pairs: 16-bit tap pairs) into ws,
+// `groups` groups of images (both orientations).
+hipError_t launch_interleave(int dtype, bool pairs, const void *x, void *ws, int n, int batch,
+                             int groups, hipStream_t s);
+// Tiled forward of one tiling (radon_fwd_t<k>.hip); scale_dt = scale * step.
+#define RADON_FWD_TILING_DECL(k)                                                                   \
+    hipError_t launch_forward_tiling##k(const Geom &g, const FwdWork &work, int dtype,             \
+                                        const LaunchShape &shape, const void *x, void *y, int batch, \
+                                        float scale_dt, void *ws, size_t ws_bytes, hipStream_t s);
+RADON_FWD_TILING_DECL(0)
+RADON_FWD_TILING_DECL(1)
+RADON_FWD_TILING_DECL(2)
+RADON_FWD_TILING_DECL(3)
+#undef RADON_FWD_TILING_DECL
 // ------------------------------------------------------------------ tiled backprojection
 constexpr int kBpTile = 16;        // pixels per tile side (one lane per pixel)
 constexpr int kBpAngles = 8;       // angles per LDS block (parallel beam)

@@ -31,7 +31,7 @@ struct PlanKeyHash {
 struct TunedShapes {
     bool valid = false;
     int fwd_variant = VARIANT_TILED, bp_variant = VARIANT_TILED;
-    int fwd_images = 8, fwd_stage = 1;
+    int fwd_images = 8, fwd_stage = 1, fwd_tiling = 0;
     int bp_images = 32, bp_angles = 8, bp_stage = 1;
 };
 
@@ -41,10 +41,11 @@ struct Plan {
     double2 *trig = nullptr;  // device [A]
     double4 *rays = nullptr;  // device [A*D], fan beam only
     BpAngle *bpa = nullptr;   // device [A], parallel beam only
-    FwdItem *fwd_items = nullptr;  // device, tiled forward work items
-    int2 *fwd_ranges = nullptr;    // device, per item and slab transverse ranges
-    FwdWork fwd_work;
-    std::vector<FwdItem> fwd_items_host;   // host copy (work-unit costs of uneven batches)
+    // tiled forward work per tiling (kFwdTiling[t]); n_items = 0 where it does not apply
+    FwdItem *fwd_items[kFwdTilings] = {};  // device, tiled forward work items
+    int2 *fwd_ranges[kFwdTilings] = {};    // device, per item and slab transverse ranges
+    FwdWork fwd_work[kFwdTilings];
+    std::vector<FwdItem> fwd_items_host;   // host copy of tiling 0 (work-unit costs of uneven batches)
     BpWork bp_work;
     bool no_interleave = false;            // stage the forward from the caller's images
     LaunchShape fwd_shape, bp_shape;       // defaults

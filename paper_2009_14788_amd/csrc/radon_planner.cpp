@@ -1,7 +1,8 @@
 // Host planning of the tiled forward projector (FP64, once per geometry).
 //
-// The rays of a work item (up to 4 angles x 64 bins) march through the image in
-// slabs of kSlabH pixel rows (or columns, whichever axis the rays are closer to).
+// The rays of a work item (up to W angles x 64 bins) march through the image in
+// slabs of H pixel rows (or columns, whichever axis the rays are closer to), (H, W)
+// one of the forward's tilings.
 // For each slab the planner computes the transverse pixel range every ray of the
 // item can touch there, so the kernel stages exactly that window into LDS.
 #include <algorithm>
@@ -29,8 +30,8 @@ Span ray_span(const double4 &r, int axis, double m0, double m1) {
     return {(int)std::floor(lo) - 1, (int)std::floor(hi) + 2};
 }
 
-bool plan_item(int n, int det_count, const std::vector<double4> &rays, int a0, int na, int d0,
-               int nd, std::vector<FwdItem> &items, std::vector<int2> &ranges, int &tile_t) {
+bool plan_item(int n, int det_count, const std::vector<double4> &rays, int slab_h, int a0, int na,
+               int d0, int nd, std::vector<FwdItem> &items, std::vector<int2> &ranges, int &tile_t) {
     const double4 &mid = rays[(size_t)(a0 + na / 2) * det_count + d0 + nd / 2];
     const int axis = std::fabs(mid.w) >= std::fabs(mid.z) ? 0 : 1;
     // every ray must advance along the march axis by at least half a step per sample
@@ -40,15 +41,15 @@ bool plan_item(int n, int det_count, const std::vector<double4> &rays, int a0, i
             const double sm = axis ? r.z : r.w;
             if (std::fabs(sm) < 0.5 * std::hypot(r.z, r.w)) return false;
         }
-    const int nslabs = (n + 1 + kSlabH - 1) / kSlabH;
+    const int nslabs = (n + 1 + slab_h - 1) / slab_h;
     std::vector<int2> local(nslabs);
     int first = -1, last = -1, width = 0;
     for (int s = 0; s < nslabs; ++s) {
-        const double m_lo = -1.0 + (double)s * kSlabH;
+        const double m_lo = -1.0 + (double)s * slab_h;
         int lo = 1 << 30, hi = -(1 << 30);
         for (int a = a0; a < a0 + na; ++a)
             for (int d : {d0, d0 + nd - 1}) {
-                const Span sp = ray_span(rays[(size_t)a * det_count + d], axis, m_lo, m_lo + kSlabH);
+                const Span sp = ray_span(rays[(size_t)a * det_count + d], axis, m_lo, m_lo + slab_h);
                 lo = std::min(lo, sp.lo);
                 hi = std::max(hi, sp.hi);
             }
@@ -90,21 +91,22 @@ bool plan_item(int n, int det_count, const std::vector<double4> &rays, int a0, i
 }  // namespace
 
 bool plan_forward_tiles(int n, int n_angles, int det_count, const std::vector<double4> &rays,
-                        std::vector<FwdItem> &items, std::vector<int2> &ranges, int &tile_t) {
+                        int slab_h, int angles, std::vector<FwdItem> &items,
+                        std::vector<int2> &ranges, int &tile_t) {
     items.clear();
     ranges.clear();
     tile_t = 0;
-    for (int a0 = 0; a0 < n_angles; a0 += kFwdWaves) {
-        const int na = std::min(kFwdWaves, n_angles - a0);
+    for (int a0 = 0; a0 < n_angles; a0 += angles) {
+        const int na = std::min(angles, n_angles - a0);
         for (int d0 = 0; d0 < det_count; d0 += kFwdLanes) {
             const int nd = std::min(kFwdLanes, det_count - d0);
-            if (plan_item(n, det_count, rays, a0, na, d0, nd, items, ranges, tile_t)) continue;
+            if (plan_item(n, det_count, rays, slab_h, a0, na, d0, nd, items, ranges, tile_t)) continue;
             // split: one angle per item, then fewer bins per item
             for (int a = a0; a < a0 + na; ++a) {
                 int step = nd;
                 for (int d = d0; d < d0 + nd;) {
                     const int cnt = std::min(step, d0 + nd - d);
-                    if (plan_item(n, det_count, rays, a, 1, d, cnt, items, ranges, tile_t)) {
+                    if (plan_item(n, det_count, rays, slab_h, a, 1, d, cnt, items, ranges, tile_t)) {
                         d += cnt;
                     } else if (step > 8) {
                         step /= 2;

@@ -1,7 +1,7 @@
 // Per-work-item device functions of the tiled projectors, shared by the per-call
 // kernels and the persistent uneven-batch kernels.  Every function is called by all
-// threads of a block (kFwdThreads for the forward, 256 for the backprojection) with
-// block-uniform arguments (they contain barriers).
+// threads of a block (the tiling's C::kThreads for the forward, 256 for the
+// backprojection) with block-uniform arguments (they contain barriers).
 #pragma once
 
 #include "radon_common.hpp"
@@ -44,14 +44,16 @@ __device__ __forceinline__ ImageSet<T, BC> contiguous_images(const T *in, size_t
 // chunks (Chunk<T>::kImages images per chunk, zero outside the image), rows `pitch`
 // chunks apart and planes `plane_chunks` apart.  A source with kMarchFrame stages in
 // the march frame: for items that march along x (axis 1) the frame is the transposed
-// image, so every slab is a band of rows; otherwise the frame is the image.
+// image, so every slab is a band of rows; otherwise the frame is the image.  Cfg: the
+// forward tiling (block size, slab rows) the source serves.
 
 // From the callers' images (any layout of BC image pointers), in the image frame:
 // image base pointers are uniform per plane and image, loads use 32-bit pixel
 // offsets, the (row, col) walk is incremental, and pixels outside the image read a
 // valid address and are replaced by 0.
-template <typename T, int BC>
+template <typename T, int BC, class C = FwdCfg0>
 struct PointerSource {
+    using Cfg = C;
     static constexpr bool kMarchFrame = false;
     static constexpr bool kPairs = false;
     const T *const *img;
@@ -61,12 +63,12 @@ struct PointerSource {
         constexpr int CH = Chunk<T>::kImages;
         constexpr int PLANES = BC / CH;
         const int total = rows * cols;
-        const int step_i = kFwdThreads / cols, step_j = kFwdThreads - step_i * cols;
+        const int step_i = C::kThreads / cols, step_j = C::kThreads - step_i * cols;
         const int i0 = threadIdx.x / cols, j0 = threadIdx.x - i0 * cols;
 #pragma unroll
         for (int q = 0; q < PLANES; ++q) {
             int i = i0, jj = j0;
-            for (int idx = threadIdx.x; idx < total; idx += kFwdThreads) {
+            for (int idx = threadIdx.x; idx < total; idx += C::kThreads) {
                 const int gx = ox0 + jj, gy = oy0 + i;
                 const bool inside = (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n;
                 const unsigned off = inside ? (unsigned)(gy * n + gx) : 0u;
@@ -95,11 +97,12 @@ struct PointerSource {
 // for chunk with no bounds test.  PAIRS (16-bit storage): the copies hold tap pairs
 // (Pair<T>) instead, chunk (group, row, col) = frame pixels col and col + 1 of the row,
 // four images per chunk.  Window rows/columns beyond [-2, N+1] are never
-// tapped and are not staged.  Wave w copies window rows w, w+W, w+2W, ... (W waves; a slab has
-// kSlabH + 3 rows) with its lanes along the row (at most kTileTMax = 3 x 64
+// tapped and are not staged.  Wave w copies window rows w, w+W, w+2W, ... (W waves; a
+// slab has H + 3 rows) with its lanes along the row (at most kTileTMax = 3 x 64
 // chunks), from wave-uniform row addresses.
-template <typename T, int BC, bool PAIRS = false>
+template <typename T, int BC, bool PAIRS = false, class C = FwdCfg0>
 struct InterleavedSource {
+    using Cfg = C;
     static constexpr bool kMarchFrame = true;
     static constexpr bool kPairs = PAIRS;
     const uint4 *base;   // row-major copy: first plane of the block's images
@@ -109,7 +112,7 @@ struct InterleavedSource {
     __device__ __forceinline__ void stage(uint4 *lds, int plane_chunks, int pitch, int ox0, int oy0,
                                           int rows, int cols, int axis) const {
         static_assert(kTileTMax <= 3 * 64, "staging loop bounds");
-        constexpr int kRowsPerWave = (kSlabH + 3 + kFwdWaves - 1) / kFwdWaves;
+        constexpr int kRowsPerWave = (C::kSlabH + 3 + C::kWaves - 1) / C::kWaves;
         constexpr int PLANES = BC / (PAIRS ? 4 : Chunk<T>::kImages);
         const int np = n + 4;
         const int r_end = min(rows, n + 2 - oy0), c_end = min(cols, n + 2 - ox0);
@@ -126,7 +129,7 @@ struct InterleavedSource {
             uint4 *dst = lds + q * plane_chunks;
 #pragma unroll
             for (int i = 0; i < kRowsPerWave; ++i) {
-                const int row = wave + kFwdWaves * i;
+                const int row = wave + C::kWaves * i;
                 if (row >= r_end) break;
                 const uint4 *srow = src + row * np;
                 uint4 *drow = dst + row * pitch;
@@ -152,9 +155,9 @@ struct InterleavedSource {
 // and the two FP64 conversions per sample are saved.  SWAP: the frame is the
 // transposed image; the two middle taps are then taken in the image frame's order,
 // so both frames give bitwise identical sums.  PITCH > 0: the row pitch is that
-// compile-time number of chunks (planes of kSlabH + 3 rows), so every tap offset is an
+// compile-time number of chunks (planes of SH + 3 rows), so every tap offset is an
 // immediate of the LDS read instead of a per-sample address add.
-template <typename T, int BC, bool SWAP, int PITCH>
+template <typename T, int BC, bool SWAP, int PITCH, int SH>
 __device__ __forceinline__ void slab_samples(const uint4 *lane_lds, int pitch, int plane_chunks,
                                              double fxa, double fya, double sx, double sy, int cnt,
                                              float *part) {
@@ -162,7 +165,7 @@ __device__ __forceinline__ void slab_samples(const uint4 *lane_lds, int pitch, i
     constexpr int PLANES = BC / CH;
     if (PITCH > 0) {
         pitch = PITCH;
-        plane_chunks = (kSlabH + 3) * PITCH;
+        plane_chunks = (SH + 3) * PITCH;
     }
     // byte addressing: one multiply-add and one shift-add per sample, the tap
     // offsets (+16 bytes, +pitch, +plane) are loop invariants
@@ -209,7 +212,7 @@ __device__ __forceinline__ void slab_samples(const uint4 *lane_lds, int pitch, i
 // staging frame exactly as in slab_samples, rounded to the storage type in two pairs
 // (row cy: taps cx, cx+1; row cy+1: the same columns), and each image takes one
 // dot2 per row from one 16-byte read per plane and row.
-template <typename T, int BC, int PITCH>
+template <typename T, int BC, int PITCH, int SH>
 __device__ __forceinline__ void slab_samples_pair(const uint4 *lane_lds, int pitch, int plane_chunks,
                                                   double fxa, double fya, double sx, double sy,
                                                   int cnt, float *part) {
@@ -217,7 +220,7 @@ __device__ __forceinline__ void slab_samples_pair(const uint4 *lane_lds, int pit
     constexpr int PLANES = BC / CH;
     if (PITCH > 0) {
         pitch = PITCH;
-        plane_chunks = (kSlabH + 3) * PITCH;
+        plane_chunks = (SH + 3) * PITCH;
     }
     const char *base = reinterpret_cast<const char *>(lane_lds);
     const unsigned row_bytes = (unsigned)pitch * 16u, plane_bytes = (unsigned)plane_chunks * 16u;
@@ -244,8 +247,9 @@ __device__ __forceinline__ void slab_samples_pair(const uint4 *lane_lds, int pit
     }
 }
 
-// One block processes one work item (up to kFwdWaves angles x 64 bins) x BC images.  The rays march through the image in slabs of
-// kSlabH rows (or columns); per slab the block stages the slab's pixel window
+// One block processes one work item (up to C::kWaves angles x 64 bins) x BC images,
+// C = Source::Cfg the tiling.  The rays march through the image in slabs of
+// C::kSlabH rows (or columns); per slab the block stages the slab's pixel window
 // into LDS as 16-byte chunks holding Chunk<T>::kImages images each ("planes"),
 // then every lane walks its ray's samples inside the slab.  A sample costs one
 // address and weight computation shared by the BC images and four 16-byte LDS
@@ -258,20 +262,21 @@ template <typename T, int BC, class Source, int PITCH = 0>
 __device__ __forceinline__ void fwd_item(const Geom &g, const FwdItem &it, const int2 *__restrict__ ranges,
                                          const ImageSet<T, BC> &imgs, const Source &src, int tile_t,
                                          uint4 *lds) {
+    using C = typename Source::Cfg;
+    constexpr int SH = C::kSlabH;
     static_assert(PITCH == 0 || Source::kMarchFrame, "a fixed pitch needs the march frame");
     if (PITCH > 0) tile_t = PITCH;
-    const int plane_chunks = (kSlabH + 3) * tile_t;
+    const int plane_chunks = (SH + 3) * tile_t;
 
-    // rays of the item -> lanes: each 16-lane quarter of a wave takes kFwdQBins
-    // neighbouring bins x kFwdQAngles neighbouring angles (4 x 4), so the quarter's taps
-    // fall on nearby columns (distinct LDS banks) and its rays have similar lengths; a
-    // wave is 4 quarters along the bins, 64 / (4 kFwdQBins) waves cover the 64 bins
-    static_assert(kFwdQBins * kFwdQAngles == 16 && kFwdWaves % kFwdQAngles == 0, "lane mapping");
-    constexpr int kWavesPerGroup = 16 / kFwdQBins;
+    // rays of the item -> lanes: each 16-lane quarter of a wave takes C::kQBins
+    // neighbouring bins x C::kQAngles neighbouring angles, so the quarter's taps fall on
+    // nearby columns (distinct LDS banks) and its rays have similar lengths; a wave is 4
+    // quarters along the bins, 64 / (4 C::kQBins) waves cover the 64 bins
+    constexpr int kWavesPerGroup = 16 / C::kQBins;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int q16 = lane & 15;
-    const int ai = kFwdQAngles * (wave / kWavesPerGroup) + q16 / kFwdQBins;
-    const int di = 4 * kFwdQBins * (wave % kWavesPerGroup) + kFwdQBins * (lane >> 4) + q16 % kFwdQBins;
+    const int ai = C::kQAngles * (wave / kWavesPerGroup) + q16 / C::kQBins;
+    const int di = 4 * C::kQBins * (wave % kWavesPerGroup) + C::kQBins * (lane >> 4) + q16 % C::kQBins;
     const bool active = ai < it.na && di < it.nd;
     const int a = it.a0 + min(ai, it.na - 1), d = it.d0 + min(di, it.nd - 1);
     const int n = g.n;
@@ -288,7 +293,7 @@ __device__ __forceinline__ void fwd_item(const Geom &g, const FwdItem &it, const
     if (swap) r = make_double4(r.y, r.x, r.w, r.z);
     const int faxis = Source::kMarchFrame ? 0 : it.axis;
     const double om = faxis ? r.x : r.y;
-    const int pitch = faxis ? (kSlabH + 3) : tile_t;
+    const int pitch = faxis ? (SH + 3) : tile_t;
 
     float acc[BC];
 #pragma unroll
@@ -297,20 +302,20 @@ __device__ __forceinline__ void fwd_item(const Geom &g, const FwdItem &it, const
     for (int si = 0; si < it.nslab; ++si) {
         const int2 tr = ranges[it.range + si];
         if (tr.x > tr.y) continue;                      // uniform over the block
-        const int m_lo = -1 + (it.slab0 + si) * kSlabH;
+        const int m_lo = -1 + (it.slab0 + si) * SH;
         // tile element (0, 0) sits at frame pixel (ox0, oy0); tile is rows x cols pixels
         const int ox0 = faxis ? m_lo - 1 : tr.x;
         const int oy0 = faxis ? tr.x : m_lo - 1;
-        const int cols = faxis ? kSlabH + 3 : tr.y - tr.x + 1;
-        const int rows = faxis ? tr.y - tr.x + 1 : kSlabH + 3;
+        const int cols = faxis ? SH + 3 : tr.y - tr.x + 1;
+        const int rows = faxis ? tr.y - tr.x + 1 : SH + 3;
 
         __syncthreads();                                // previous slab fully consumed
         src.stage(lds, plane_chunks, pitch, ox0, oy0, rows, cols, it.axis);
         __syncthreads();
 
-        // samples of this ray whose march coordinate lies in [m_lo, m_lo + kSlabH)
+        // samples of this ray whose march coordinate lies in [m_lo, m_lo + SH)
         const int jb = max(jlo, (int)ceil(((double)m_lo - om) * inv_sm));
-        const int je = min(jhi + 1, (int)ceil(((double)(m_lo + kSlabH) - om) * inv_sm));
+        const int je = min(jhi + 1, (int)ceil(((double)(m_lo + SH) - om) * inv_sm));
         if (jb >= je) continue;
         // anchor: one cell below the lowest cell over the slab's samples, so that every
         // sample offset is >= 1 in FP64 (>= 1 - 2e-6 once stepped in FP32, so
@@ -327,14 +332,14 @@ __device__ __forceinline__ void fwd_item(const Geom &g, const FwdItem &it, const
 #pragma unroll
         for (int i = 0; i < BC; ++i) part[i] = 0.0f;
         if constexpr (Source::kPairs)
-            slab_samples_pair<T, BC, PITCH>(lane_lds, pitch, plane_chunks, px64 - bx, py64 - by,
+            slab_samples_pair<T, BC, PITCH, SH>(lane_lds, pitch, plane_chunks, px64 - bx, py64 - by,
                                             r.z, r.w, je - jb, part);
         else if (swap)
-            slab_samples<T, BC, Source::kMarchFrame, PITCH>(lane_lds, pitch, plane_chunks,
+            slab_samples<T, BC, Source::kMarchFrame, PITCH, SH>(lane_lds, pitch, plane_chunks,
                                                             px64 - bx, py64 - by, r.z, r.w,
                                                             je - jb, part);
         else
-            slab_samples<T, BC, false, PITCH>(lane_lds, pitch, plane_chunks, px64 - bx, py64 - by,
+            slab_samples<T, BC, false, PITCH, SH>(lane_lds, pitch, plane_chunks, px64 - bx, py64 - by,
                                               r.z, r.w, je - jb, part);
 #pragma unroll
         for (int i = 0; i < BC; ++i) acc[i] += part[i];

@@ -176,13 +176,15 @@ class _Base:
 
     def plan_info(self, dtype=torch.float32, batch: int = 1):
         """Launch shapes used for this storage type and batch size, per direction:
-        images per lane, angles per block, staging (1 = interleaved workspace copy),
-        variant (1 = tiled kernel, 0 = direct kernel)."""
-        out = (ctypes.c_int32 * 8)()
+        images per lane, angles per block, staging (1 = interleaved workspace copy,
+        2 = 16-bit tap pairs), variant (1 = tiled kernel, 0 = direct kernel), and the
+        forward's slab rows / the backprojection's tile side."""
+        out = (ctypes.c_int32 * 10)()
         _lib.check("radon_plan_info", _lib.lib.radon_plan_info(
             ctypes.byref(self._geom), dtype_code(dtype), int(batch), out))
         keys = ("images", "angles", "staging", "variant")
-        return {"forward": dict(zip(keys, out[0:4])), "backprojection": dict(zip(keys, out[4:8]))}
+        return {"forward": dict(zip(keys + ("rows",), out[0:5])),
+                "backprojection": dict(zip(keys + ("tile",), out[5:10]))}
 
 
 class Radon(_Base):

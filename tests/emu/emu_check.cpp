@@ -408,7 +408,7 @@ int main(int argc, char **argv) {
         void *fd = dev_alloc(g.ny * es), *bd = dev_alloc(g.nx * es);
         int rc = radon_forward(&g.g, xin, g.fx, g.batch, g.dt, 1.0f, nullptr);
         if (!rc) rc = radon_backproject(&g.g, yin, g.bx, g.batch, g.dt, 1.0f, nullptr);
-        int info[8] = {0};
+        int info[10] = {0};
         if (!rc) rc = radon_plan_info(&g.g, g.dt, g.batch, info);
         // direct kernels: plans rebuilt with the tiled planners switched off
         if (!rc) {
@@ -436,7 +436,7 @@ int main(int argc, char **argv) {
         const double df = rel_l2(fd, g.dt, of.data(), g.ny), db = rel_l2(bd, g.dt, ob.data(), g.nx);
         std::printf("geometry %zu fwd_variant %d bp_variant %d forward %.3e backprojection %.3e "
                     "direct_forward %.3e direct_backprojection %.3e\n",
-                    k, info[3], info[7], ef, eb, df, db);
+                    k, info[3], info[8], ef, eb, df, db);
         std::free(xin);
         std::free(yin);
         std::free(fd);

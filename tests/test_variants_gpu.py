@@ -3,6 +3,7 @@ with 4/8/16 images per lane and either slab staging (bitwise identical), and
 backprojection with 16/32 images per lane and 4/8-angle LDS blocks (identical up to
 the grouping of the FP32 partial sums).  Also checks that autotuning runs and keeps
 results within the parity bar."""
+import json
 import math
 import os
 import subprocess
@@ -86,7 +87,10 @@ np.save(sys.argv[2], op.forward_raw(x).cpu().numpy())
     assert r.returncode == 0, r.stderr[-2000:]
     print(r.stdout)
     lines = cache.read_text().strip().splitlines()
-    assert len(lines) == 1 and len(lines[0].split()) == 8
+    # key, fwd variant/images/staging, bp variant/images/angles/staging, fwd tiling
+    assert len(lines) == 1 and len(lines[0].split()) == 9
+    assert lines[0].split()[0].endswith("_t0_b16")             # FP32, batch class 16
+    assert 0 <= int(lines[0].split()[8]) < 4
     y = np.load(tmp_path / "y.npy")
     og = oracle.Geometry(128, inputs.uniform_angles(90), 182, 1.0)
     ref = oracle.forward(og, inputs.phantom_batch(9, 12, 128)[:2].astype(np.float64))
@@ -99,6 +103,46 @@ np.save(sys.argv[2], op.forward_raw(x).cpu().numpy())
     assert r2.returncode == 0, r2.stderr[-2000:]
     assert len(cache.read_text().strip().splitlines()) == 1
     assert np.array_equal(np.load(tmp_path / "y2.npy"), y)
+
+
+@pytest.mark.parametrize("tiling,rows,angles", [(1, 7, 8), (2, 15, 8), (3, 11, 4)])
+def test_tune_cache_selects_forward_tiling(tmp_path, tiling, rows, angles):
+    """A tune-cache line naming a forward tiling (slab rows, angles per item) is what
+    the next process uses: plan_info reports it, and the result stays at parity with
+    the oracle."""
+    script = r"""
+import sys, json, numpy as np, torch
+sys.path.insert(0, sys.argv[1])
+from paper_2009_14788_amd import inputs
+from paper_2009_14788_amd.radon import Radon
+op = Radon(128, inputs.uniform_angles(90), 182)
+op.prepare(torch.float32, 12)
+print(json.dumps(op.plan_info(torch.float32, 12)))
+x = torch.from_numpy(inputs.phantom_batch(9, 12, 128)).cuda()
+np.save(sys.argv[2], op.forward_raw(x).cpu().numpy())
+"""
+    cache = tmp_path / "tune.txt"
+    env = dict(os.environ, RADON_TUNE_CACHE=str(cache))
+    # learn the key from a first tuning run, then rewrite its line with the tiling
+    r = subprocess.run([sys.executable, "-c", script, ROOT, str(tmp_path / "y0.npy")], env=env,
+                       capture_output=True, text=True, timeout=240)
+    assert r.returncode == 0, r.stderr[-2000:]
+    f = cache.read_text().split()
+    f[1:4] = ["1", "8", "1"]                                    # tiled forward, 8 images, staged
+    f[8] = str(tiling)
+    cache.write_text(" ".join(f) + "\n")
+    print(f"[gpu-step] tune cache forcing tiling {tiling}", flush=True)
+    r = subprocess.run([sys.executable, "-c", script, ROOT, str(tmp_path / "y.npy")], env=env,
+                       capture_output=True, text=True, timeout=240)
+    assert r.returncode == 0, r.stderr[-2000:]
+    info = json.loads(r.stdout.strip().splitlines()[-1])["forward"]
+    assert (info["rows"], info["angles"], info["images"]) == (rows, angles, 8), info
+    y = np.load(tmp_path / "y.npy")
+    og = oracle.Geometry(128, inputs.uniform_angles(90), 182, 1.0)
+    ref = oracle.forward(og, inputs.phantom_batch(9, 12, 128)[[0, 11]].astype(np.float64))
+    e = rel_l2(y[[0, 11]], ref)
+    report(f"tiling{tiling}_forward", rel_l2=e, rows=rows, angles=angles)
+    assert e <= TOL_F32
 
 
 def test_measure_peaks_plausible():
