@@ -522,9 +522,11 @@ static int upload(V **dst, const std::vector<V> &src) {
     return RADON_OK;
 }
 
-// Images of all jobs that share a plan are pooled and cut into image groups (8 for
-// the forward; for the backprojection 32 while at least 14 remain, else 8), so
-// single-image jobs of one geometry share lanes.  Units are sorted longest first.
+// Images of all jobs that share a plan are pooled and cut into image groups, so
+// single-image jobs of one geometry share lanes: forward, one 16-byte chunk of images
+// per lane (4 FP32 / 8 16-bit);
+// backprojection, the narrowest of 8, 16 and 32 images that holds the images left (32
+// while more remain).  Units are sorted longest first.
 static int build_batch_table(const std::vector<Plan *> &plans, const radon_job_t *jobs, int n,
                              int dtype, int direction, int device, std::unique_ptr<BatchTable> &out) {
     std::unique_ptr<BatchTable> t(new (std::nothrow) BatchTable());
@@ -572,7 +574,10 @@ static int build_batch_table(const std::vector<Plan *> &plans, const radon_job_t
         bj.push_back(j);
         for (size_t k = 0; k < v.size();) {
             const size_t left = v.size() - k;
-            const int cap = direction == 0 ? ch : (left >= 14 ? kBatchBpWide : kBatchBpNarrow);
+            const int cap = direction == 0 ? ch
+                                           : (left > (size_t)kBatchBpMid    ? kBatchBpWide
+                                              : left > (size_t)kBatchBpNarrow ? kBatchBpMid
+                                                                              : kBatchBpNarrow);
             const int cnt = (int)std::min<size_t>(left, (size_t)cap);
             ImageGroup gr{};
             for (int e = 0; e < kBatchBpWide; ++e) {
@@ -592,8 +597,8 @@ static int build_batch_table(const std::vector<Plan *> &plans, const radon_job_t
                     units.push_back({{jid, (int)it, gid, 0}, (double)(f.nslab + 1) * f.na * f.nd});
                 }
             } else {
-                const bool wide = cap == kBatchBpWide;
-                const int planes = (wide ? kBatchBpWide : kBatchBpNarrow) / ch;
+                const int wide = cap == kBatchBpWide ? 1 : (cap == kBatchBpMid ? 2 : 0);
+                const int planes = cap / ch;
                 const int nimg = p->geom.n;
                 const int tiles = ((nimg + kBpTile - 1) / kBpTile) * ((nimg + kBpTile - 1) / kBpTile);
                 const size_t need = !p->geom.fan
@@ -603,9 +608,9 @@ static int build_batch_table(const std::vector<Plan *> &plans, const radon_job_t
                 lds = std::max(lds, need);
                 // instruction estimate per (pixel, angle): candidate search + 3 or NB FMAs per image
                 const int nb = p->geom.fan ? j.bins : 3;
-                const double cost = (double)p->geom.n_angles * (30.0 * nb + (wide ? 32 : 8) * nb);
+                const double cost = (double)p->geom.n_angles * (30.0 * nb + cap * nb);
                 for (int tile = 0; tile < tiles; ++tile)
-                    units.push_back({{jid, tile, gid, wide ? 1 : 0}, cost});
+                    units.push_back({{jid, tile, gid, wide}, cost});
             }
         }
     }

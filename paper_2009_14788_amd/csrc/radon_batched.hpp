@@ -9,6 +9,7 @@
 namespace radon {
 
 constexpr int kBatchBpNarrow = 8;      // images per lane in small backprojection units
+constexpr int kBatchBpMid = 16;        // images per lane in medium backprojection units
 constexpr int kBatchBpWide = 32;       // images per lane in large backprojection units
 
 // One geometry of an uneven batch as the device sees it (shared by every job of
@@ -35,7 +36,8 @@ struct ImageGroup {
 };
 
 // One unit of work: forward (geometry, plan item, image group); backprojection
-// (geometry, pixel tile, image group); `wide` selects 32-image backprojection lanes.
+// (geometry, pixel tile, image group).  `wide` (backprojection): 0 = kBatchBpNarrow,
+// 1 = kBatchBpWide, 2 = kBatchBpMid images per lane; 0 for the forward.
 struct WorkUnit {
     int job, unit, group, wide;
 };

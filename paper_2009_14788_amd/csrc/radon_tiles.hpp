@@ -597,7 +597,7 @@ template <typename T, int BC, int NBX, int NK, bool PAIRS>
 __device__ __forceinline__ void fan_angle_block(const Geom &g, int a0, int na, int W, const int *wlo_s,
                                                 const float4 *rays_s, const uint4 *lds, int per_plane,
                                                 float qx, float qy, float lx, float ly, float is2,
-                                                float *part) {
+                                                float *part, int skip = 0) {
     constexpr int CH = PAIRS ? 4 : Chunk<T>::kImages;
     constexpr int PLANES = BC / CH;
     const float sd = (float)g.sd, k_sde = (float)(g.sde * g.inv_spacing), hd = (float)g.half_d;
@@ -612,7 +612,7 @@ __device__ __forceinline__ void fan_angle_block(const Geom &g, int a0, int na, i
         const float k2 = k_sde * den * den;
         const float gsx = k2 * fmaf(cx, near, pu * sy), gsy = k2 * fmaf(sy, near, -pu * cx);
         const float hb = fabsf(gsx) + fabsf(gsy);
-        const int dfirst = (int)ceilf(sb - hb * 1.01f - 0.05f);
+        const int dfirst = (int)ceilf(sb - hb * 1.01f - 0.05f) + skip;
         int lb = dfirst - wlo_s[al];
         lb = min(max(lb, 0), W - NBX);              // memory safety; real pixels are inside
         float wgt[NBX];
@@ -639,25 +639,42 @@ __device__ __forceinline__ void fan_angle_block(const Geom &g, int a0, int na, i
         if constexpr (PAIRS) {
             bp_apply_pairs<T, PLANES, NBX, 0>(wgt, row, part, per_plane);
         } else {
+            // planes in a register pipeline (the next plane's NBX chunks are read while
+            // the current plane's are applied): with few waves per SIMD the LDS latency
+            // is otherwise exposed once per plane
+            uint4 cur[NBX];
+#pragma unroll
+            for (int i = 0; i < NBX; ++i) cur[i] = row[i];
 #pragma unroll
             for (int qq = 0; qq < PLANES; ++qq) {
+                uint4 nxt[NBX];
+                if (qq + 1 < PLANES) {
 #pragma unroll
-                for (int i = 0; i < NBX; ++i) Chunk<T>::fma(wgt[i], row[qq * per_plane + i], part + qq * CH);
+                    for (int i = 0; i < NBX; ++i) nxt[i] = row[(qq + 1) * per_plane + i];
+                }
+#pragma unroll
+                for (int i = 0; i < NBX; ++i) Chunk<T>::fma(wgt[i], cur[i], part + qq * CH);
+                if (qq + 1 < PLANES) {
+#pragma unroll
+                    for (int i = 0; i < NBX; ++i) cur[i] = nxt[i];
+                }
             }
         }
     }
 }
 
 // Fan beam.  Same tiling as the parallel kernel; every bin has its own ray, so the
-// block also stages the rays (FP64 foot point and step) of its bin window.  Per
-// (pixel, angle) the candidate bins are those within the projected half-width of
-// the pixel's footprint around the projection of its centre (first-order bound
-// plus a margin far larger than the footprint's curvature); per bin, the NK
-// candidate samples around the pixel's position along that ray are evaluated with
-// FP64 anchors and FP32 offsets, exactly as in the parallel kernel.  The plan's NB
-// bins cover the worst magnification in the image; per block of angles the tile's
-// own bound (its footprint's smallest distance to the source and largest lateral
-// offset) often needs only 4, and then the 4-bin loop runs.
+// block also stages the rays of its bin window (each as its lattice point nearest the
+// tile, relative to the tile, and its step, in FP32).  Per (pixel, angle) the
+// candidate bins are those within the projected half-width of the pixel's footprint
+// around the projection of its centre (first-order bound plus a margin far larger
+// than the footprint's curvature); per bin, the NK candidate samples around the
+// pixel's position along that ray are evaluated from small FP32 offsets, as in the
+// parallel kernel.  The plan's NB bins cover the worst magnification in the image;
+// per block of angles the tile's own bound (its footprint's smallest distance to the
+// source and largest lateral offset) usually needs only 4 (96% of the blocks of a
+// 512^2 image at S = 1000, E = 500, 1.5-pixel bins), and only the other blocks run a
+// second pass over the next 2.
 template <typename T, int BC, int NB, int NK, class Source>
 __device__ __forceinline__ void bp_tile_fan(const Geom &g, int tile, const ImageSet<T, BC> &imgs,
                                             const Source &src, int W, uint4 *lds) {
@@ -736,12 +753,14 @@ __device__ __forceinline__ void bp_tile_fan(const Geom &g, int tile, const Image
 #pragma unroll
             for (int i = 0; i < BC; ++i) part[i] = 0.0f;
         }
-        if (NB > 4 && nb_block <= 4)
-            fan_angle_block<T, BC, 4, NK, Source::kPairs>(g, a0, na, W, wlo_s, rays_s, lds, per_plane, qx, qy, lx, ly,
-                                          is2, part);
-        else
-            fan_angle_block<T, BC, NB, NK, Source::kPairs>(g, a0, na, W, wlo_s, rays_s, lds, per_plane, qx, qy, lx, ly,
-                                           is2, part);
+        // candidate bins: four, and for the angle blocks whose bound needs more, two
+        // more in a second pass (one 4-bin body keeps the registers of the wide lanes
+        // at three waves per SIMD, where a 6-bin body needed two)
+        fan_angle_block<T, BC, 4, NK, Source::kPairs>(g, a0, na, W, wlo_s, rays_s, lds, per_plane, qx, qy,
+                                                      lx, ly, is2, part);
+        if (NB > 4 && nb_block > 4)
+            fan_angle_block<T, BC, 2, NK, Source::kPairs>(g, a0, na, W, wlo_s, rays_s, lds, per_plane, qx,
+                                                          qy, lx, ly, is2, part, 4);
         if (kTwoLevel) {
 #pragma unroll
             for (int i = 0; i < BC; ++i) acc[i] += part[i];

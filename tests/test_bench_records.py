@@ -15,18 +15,19 @@ def _fields(name, tag):
 
 def test_traffic_record_parses():
     f = _fields("hbm_traffic_batch128_512.md", "traffic-record")
-    assert "forward:1,8,8,1" in f and "backprojection:1,64,4,1" in f
+    assert "forward:1,8,8,1,11" in f and "backprojection:1,64,4,1" in f
     for k, v in f.items():
         direction, shape = k.split(":")
         assert direction in ("forward", "backprojection")
-        assert len(shape.split(",")) == 4
+        # variant, images, angles, staging, and for the forward the slab rows
+        assert len(shape.split(",")) == (5 if direction == "forward" else 4)
         # at least the algorithmic bytes of one direction (0.40 GB) move per launch
         assert int(v) > 4.0e8
 
 
 def test_counter_record_parses():
     f = _fields("cache_hit_rates_batch128_512_f32.md", "counter-record")
-    assert "forward:1,8,8,1" in f and "backprojection:1,64,4,1" in f
+    assert "forward:1,8,8,1,11" in f and "backprojection:1,64,4,1" in f
     for v in f.values():
         c = {k: float(x) for k, x in (kv.split(":") for kv in v.split(","))}
         assert set(c) == {"l2_hit", "l1_hit", "lds_conflict"}

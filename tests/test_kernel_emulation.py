@@ -124,7 +124,9 @@ def test_emulated_launch_shapes(emu_bin, tmp_path, shape):
     lines = [_line("par", 40, U(24), 57, batch=11),
              _line("par", 40, U(24), 57, batch=11, dt=1),
              _line("fan", 40, U(24, 2 * math.pi), 66, 1.5, 250.0, 120.0, batch=11),
-             _line("fan", 37, U(24, 2 * math.pi), 60, 1.5, 250.0, 120.0, batch=11, dt=2)]
+             _line("fan", 37, U(24, 2 * math.pi), 60, 1.5, 250.0, 120.0, batch=11, dt=2),
+             # source close enough that some tiles need 5-6 candidate bins (second pass)
+             _line("fan", 40, U(16, 2 * math.pi), 80, 1.0, 130.0, 40.0, batch=11, dt=1)]
     rows, _ = _run(emu_bin, tmp_path, lines, env={"RADON_FORCE_SHAPE": shape})
     _check_bars(rows, lines)
 
