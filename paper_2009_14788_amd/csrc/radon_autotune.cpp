@@ -1,7 +1,7 @@
 // Autotuner: picks the launch shape of each direction for a (plan, storage type,
 // batch size class) by timing the candidates on the device with HIP events.
 //
-// Forward candidates: images per lane {8, 4 (FP32 only), 16 (16-bit only)} x slab
+// Forward candidates: images per lane {8, 16, 4 (FP32 only)} x slab
 // staging {interleaved copy, caller's images, and for 16-bit storage the tap-pair copy
 // with dot2 arithmetic} x tiling (kFwdTiling: slab rows {11, 7, 15} with 8 angles per
 // work item, and 11 rows with 4 angles), and the direct kernel.
@@ -125,7 +125,7 @@ int autotune(Plan &p, int dtype, int batch, void *ws, size_t ws_bytes, TunedShap
     }
 
     if (p.fwd_shape.variant == VARIANT_TILED) {
-        std::vector<int> imgs = dtype == F32 ? std::vector<int>{8, 4} : std::vector<int>{8, 16};
+        std::vector<int> imgs = dtype == F32 ? std::vector<int>{8, 4, 16} : std::vector<int>{8, 16};
         float best = time_launches([&] {
             LaunchShape sh = p.fwd_shape;
             sh.variant = VARIANT_DIRECT;

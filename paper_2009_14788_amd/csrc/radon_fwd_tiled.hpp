@@ -117,8 +117,8 @@ static hipError_t launch_fwd_tiled(const Geom &g, const FwdWork &work, const voi
     return hipGetLastError();
 }
 
-// All storage types and lane widths of tiling C (shape.images: FP32 4 or 8, 16-bit 8
-// or 16 images per lane).
+// All storage types and lane widths of tiling C (shape.images: FP32 4, 8 or 16, 16-bit
+// 8 or 16 images per lane).
 template <class C>
 hipError_t launch_forward_tiled(const Geom &g, const FwdWork &work, int dtype, const LaunchShape &shape,
                                 const void *x, void *y, int batch, float scale_dt, void *ws,
@@ -128,6 +128,8 @@ hipError_t launch_forward_tiled(const Geom &g, const FwdWork &work, int dtype, c
     case F32:
         if (shape.images <= 4)
             return launch_fwd_tiled<float, 4, C>(g, work, x, y, batch, scale_dt, st, ws, ws_bytes, s);
+        if (shape.images >= 16)
+            return launch_fwd_tiled<float, 16, C>(g, work, x, y, batch, scale_dt, st, ws, ws_bytes, s);
         return launch_fwd_tiled<float, 8, C>(g, work, x, y, batch, scale_dt, st, ws, ws_bytes, s);
     case F16:
         if (shape.images >= 16)

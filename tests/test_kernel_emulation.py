@@ -115,7 +115,8 @@ def test_emulated_kernels_match_oracle(emu_bin, tmp_path):
 @pytest.mark.parametrize("shape", ["8,0,16,4,0", "4,1,32,4,1", "16,1,32,8,0", "8,1,16,8,1", "4,1,64,4,1",
                                    "8,0,64,8,0", "8,1,4,8,1", "4,0,4,4,0", "8,2,16,4,2", "16,2,32,8,0",
                                    "8,1,64,8,2", "16,2,8,4,2", "8,1,32,4,1,1", "4,0,16,8,0,2",
-                                   "16,2,64,4,2,3", "8,1,64,8,1,3", "16,1,32,4,1,2"])
+                                   "16,2,64,4,2,3", "8,1,64,8,1,3", "16,1,32,4,1,2", "16,1,64,4,1,1",
+                                   "16,0,16,8,0,0"])
 def test_emulated_launch_shapes(emu_bin, tmp_path, shape):
     """Every forced launch shape (images per lane, staging -- 2: 16-bit tap pairs with
     dot2, forward or backprojection --, angle block, forward tiling: slab rows and
