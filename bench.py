@@ -33,7 +33,8 @@ COUNTER_RECORD = os.path.join(ROOT, "profiles", "cache_hit_rates_batch128_512_f3
 # their work plans: the HBM traffic record is valid while these are unchanged
 PROJECTOR_SOURCES = ("radon_abi.cpp", "radon_bp.hip", "radon_common.hpp", "radon_fwd.hip",
                      "radon_fwd_tiled.hpp", "radon_fwd_t0.hip", "radon_fwd_t1.hip", "radon_fwd_t2.hip",
-                     "radon_fwd_t3.hip", "radon_launch.hpp", "radon_plan.hpp", "radon_planner.cpp",
+                     "radon_fwd_t3.hip", "radon_launch.hpp", "radon_lds_dma.hpp", "radon_plan.hpp",
+                     "radon_planner.cpp",
                      "radon_tiles.hpp")
 
 

@@ -763,7 +763,7 @@ static void call_shapes(Plan *p, int dtype, int batch, LaunchShape &fwd, LaunchS
             fwd.stage = fs;
             use_tiling(p, fwd, ft);
             bp.images = bi;
-            if (!p->geom.fan) bp.angles = ba;
+            bp.angles = p->geom.fan ? (ba == 2 ? 2 : kBpAnglesFan) : ba;
             bp.stage = bs;
             return;
         }

@@ -6,9 +6,9 @@
 // with dot2 arithmetic} x tiling (kFwdTiling: slab rows {11, 7, 15} with 8 angles per
 // work item, and 11 rows with 4 angles), and the direct kernel.
 // Backprojection candidates: images per lane {64, 32, 16, one chunk (batches <= 8)} x
-// angles per LDS block {8, 4}
-// (parallel beam; the fan beam's block is fixed at 4 because its rays are staged
-// too) x sinogram staging {interleaved copy, caller's sinograms, and for 16-bit storage
+// angles per LDS block (with the interleaved copies, whose next block is copied
+// asynchronously into a second buffer, {4, 2}; from the caller's sinograms {8, 4}
+// parallel, 4 fan) x sinogram staging {interleaved copy, caller's sinograms, and for 16-bit storage
 // the tap-pair copy with dot2 arithmetic}, and the direct kernel.  The direct kernels win on tiny problems, where the
 // tiled kernels' sequential slabs and angle blocks are latency-bound.  Results live in the plan
 // and, when RADON_TUNE_CACHE names a file, in that file (one line per entry:
@@ -163,14 +163,19 @@ int autotune(Plan &p, int dtype, int batch, void *ws, size_t ws_bytes, TunedShap
             return launch_backproject(p.geom, p.bp_work, dtype, sh, y, x, batch, 1.0f, ws, ws_bytes, s);
         }, s);
         out.bp_variant = VARIANT_DIRECT;
-        const std::vector<int> abs = p.geom.fan ? std::vector<int>{kBpAnglesFan}
-                                                : std::vector<int>{kBpAngles, 4};
+        // angles per LDS block: the double-buffered kernels on the interleaved copies
+        // (stages 1, 2) take {4, 2}, the caller's sinograms (stage 0) the parallel
+        // beam's {8, 4} and the fan beam's 4
+        auto abs = [&](int st) {
+            if (st > 0) return std::vector<int>{4, 2};
+            return p.geom.fan ? std::vector<int>{kBpAnglesFan} : std::vector<int>{kBpAngles, 4};
+        };
         // one chunk per lane (4 FP32 or 8 16-bit images) only pays for small batches
         const std::vector<int> ims{64, 32, 16, 4};
         for (int im : ims)
             if (im >= 16 || batch <= 8)
-            for (int ab : abs)
-                for (int st : (dtype == F32 ? std::vector<int>{1, 0} : std::vector<int>{2, 1, 0})) {
+            for (int st : (dtype == F32 ? std::vector<int>{1, 0} : std::vector<int>{2, 1, 0}))
+                for (int ab : abs(st)) {
                     LaunchShape sh = p.bp_shape;
                     sh.images = im;
                     sh.angles = ab;

@@ -76,9 +76,9 @@ __device__ __forceinline__ void bp_unit(const BatchJob &j, const WorkUnit &u,
     if (!j.g.fan)
         bp_tile_par<T, BC, 3, 3, kBpAngles>(j.g, u.unit, imgs, src, j.window, lds);
     else if (j.bins <= 4)
-        bp_tile_fan<T, BC, 4, 3>(j.g, u.unit, imgs, src, j.window, lds);
+        bp_tile_fan<T, BC, 4, 3, kBpAnglesFan>(j.g, u.unit, imgs, src, j.window, lds);
     else
-        bp_tile_fan<T, BC, 6, 3>(j.g, u.unit, imgs, src, j.window, lds);
+        bp_tile_fan<T, BC, 6, 3, kBpAnglesFan>(j.g, u.unit, imgs, src, j.window, lds);
 }
 
 template <typename T>

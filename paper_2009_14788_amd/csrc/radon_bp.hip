@@ -110,9 +110,10 @@ __global__ __launch_bounds__(256) void bp_tiled_par(Geom g, const T *__restrict_
 }
 
 // Same, staging from the interleaved, zero-padded copy yi of the batch's sinograms
-// (PAIRS: a copy of tap pairs, four images per chunk, applied with dot2).
-// Four resident blocks (four waves per SIMD) cap the registers at 128, so the plane
-// pipeline of the inner loop does not lower the occupancy.
+// (PAIRS: a copy of tap pairs, four images per chunk, applied with dot2), double-
+// buffered with asynchronous copies (bp_tile_par_async).  Four resident blocks (four
+// waves per SIMD) cap the registers at 128, so the plane pipeline of the inner loop
+// does not lower the occupancy.
 template <typename T, int BC, int NB, int NK, int AB, bool PAIRS = false>
 __global__ __launch_bounds__(256, 4) void bp_tiled_par_il(Geom g, const uint4 *__restrict__ yi,
                                                        T *__restrict__ x, int batch, float scale_dt,
@@ -128,8 +129,7 @@ __global__ __launch_bounds__(256, 4) void bp_tiled_par_il(Geom g, const uint4 *_
     src.base = yi + (size_t)(b0 / CH) * src.plane_stride;
     src.D = g.det_count;
     src.Dp = Dp;
-    src.setup(W, AB * kBpWinPar);
-    bp_tile_par<T, BC, NB, NK, AB>(g, blockIdx.x, imgs, src, W, lds);
+    bp_tile_par_async<T, BC, NB, NK, AB, PAIRS>(g, blockIdx.x, imgs, src, W, lds);
 }
 
 template <typename T, int BC, int NB, int NK>
@@ -140,10 +140,10 @@ __global__ __launch_bounds__(256) void bp_tiled_fan(Geom g, const T *__restrict_
     const ImageSet<T, BC> imgs = contiguous_images<T, BC>(
         y, (size_t)g.n_angles * g.det_count, x, (size_t)g.n * g.n, batch, blockIdx.y * BC, scale_dt);
     const SinoPointerSource<T, BC> src{imgs.in, g.det_count};
-    bp_tile_fan<T, BC, NB, NK>(g, blockIdx.x, imgs, src, W, lds);
+    bp_tile_fan<T, BC, NB, NK, kBpAnglesFan>(g, blockIdx.x, imgs, src, W, lds);
 }
 
-template <typename T, int BC, int NB, int NK, bool PAIRS = false>
+template <typename T, int BC, int NB, int NK, int AB, bool PAIRS = false>
 __global__ __launch_bounds__(256) void bp_tiled_fan_il(Geom g, const uint4 *__restrict__ yi,
                                                        T *__restrict__ x, int batch, float scale_dt,
                                                        int W) {
@@ -157,8 +157,8 @@ __global__ __launch_bounds__(256) void bp_tiled_fan_il(Geom g, const uint4 *__re
     src.base = yi + (size_t)(b0 / CH) * src.plane_stride;
     src.D = g.det_count;
     src.Dp = Dp;
-    src.setup(W, kBpAnglesFan * W);
-    bp_tile_fan<T, BC, NB, NK>(g, blockIdx.x, imgs, src, W, lds);
+    src.setup(W, AB * W);
+    bp_tile_fan_async<T, BC, NB, NK, AB, PAIRS>(g, blockIdx.x, imgs, src, W, lds);
 }
 
 // Interleave sinograms y[B][A][D] into yi[groups][A][D + 2W] chunks of CH images with
@@ -226,6 +226,24 @@ static hipError_t launch_bp_direct(const Geom &g, const void *y, void *x, int ba
 
 // Tiled backprojection from the tap-pair copy (16-bit storage, staging 2).  Returns
 // false (nothing launched) when the window does not fit the staging slots.
+// Angles per LDS block of the fan kernels on the interleaved copy: 2 when the shape
+// asks for it, else kBpAnglesFan.
+static int fan_block_angles(const LaunchShape &shape) { return shape.angles == 2 ? 2 : kBpAnglesFan; }
+
+// Angles per LDS block of the parallel kernels on the interleaved copy (double-
+// buffered): 2 when the shape asks for at most 2, else 4.
+static int par_async_angles(const LaunchShape &shape) { return shape.angles <= 2 ? 2 : 4; }
+
+// LDS of the double-buffered parallel kernels: two windows of ab angles, planes at the
+// fixed pitch.
+static size_t par_async_lds(int planes, int ab) { return 2 * (size_t)planes * ab * kBpWinPar * sizeof(uint4); }
+
+// LDS of the double-buffered fan kernels: two sinogram windows and two ray windows of
+// ab angles.
+static size_t fan_async_lds(int planes, int ab, int W) {
+    return 2 * ((size_t)planes * ab * W * sizeof(uint4) + (size_t)ab * W * sizeof(float4));
+}
+
 template <typename T, int BC>
 static bool launch_bp_pairs(const Geom &g, const BpWork &work, const LaunchShape &shape,
                             const void *y, void *x, int batch, float scale_dt, void *ws,
@@ -247,23 +265,32 @@ static bool launch_bp_pairs(const Geom &g, const BpWork &work, const LaunchShape
     if (*err != hipSuccess) return true;
     const uint4 *yi = (const uint4 *)ws;
     if (!g.fan) {
-        if (shape.angles <= 4)
-            hipLaunchKernelGGL((bp_tiled_par_il<T, BC, 3, 3, 4, true>), grid, dim3(256),
-                               (size_t)PLANES * 4 * kBpWinPar * sizeof(uint4), s, g, yi, (T *)x, batch,
-                               scale_dt, W);
+        const int ab = par_async_angles(shape);
+        const size_t lds = par_async_lds(PLANES, ab);
+        if (ab == 2)
+            hipLaunchKernelGGL((bp_tiled_par_il<T, BC, 3, 3, 2, true>), grid, dim3(256), lds, s, g, yi, (T *)x,
+                               batch, scale_dt, W);
         else
-            hipLaunchKernelGGL((bp_tiled_par_il<T, BC, 3, 3, kBpAngles, true>), grid, dim3(256),
-                               (size_t)PLANES * kBpAngles * kBpWinPar * sizeof(uint4), s, g, yi, (T *)x,
+            hipLaunchKernelGGL((bp_tiled_par_il<T, BC, 3, 3, 4, true>), grid, dim3(256), lds, s, g, yi, (T *)x,
                                batch, scale_dt, W);
     } else {
-        const size_t lds = (size_t)PLANES * kBpAnglesFan * W * sizeof(uint4) +
-                           (size_t)kBpAnglesFan * W * sizeof(float4);
-        if (work.bins <= 4)
-            hipLaunchKernelGGL((bp_tiled_fan_il<T, BC, 4, 3, true>), grid, dim3(256), lds, s, g, yi,
-                               (T *)x, batch, scale_dt, W);
-        else
-            hipLaunchKernelGGL((bp_tiled_fan_il<T, BC, 6, 3, true>), grid, dim3(256), lds, s, g, yi,
-                               (T *)x, batch, scale_dt, W);
+        const int ab = fan_block_angles(shape);
+        const size_t lds = fan_async_lds(PLANES, ab, W);
+        if (work.bins <= 4) {
+            if (ab == 2)
+                hipLaunchKernelGGL((bp_tiled_fan_il<T, BC, 4, 3, 2, true>), grid, dim3(256), lds, s, g, yi,
+                                   (T *)x, batch, scale_dt, W);
+            else
+                hipLaunchKernelGGL((bp_tiled_fan_il<T, BC, 4, 3, kBpAnglesFan, true>), grid, dim3(256), lds,
+                                   s, g, yi, (T *)x, batch, scale_dt, W);
+        } else {
+            if (ab == 2)
+                hipLaunchKernelGGL((bp_tiled_fan_il<T, BC, 6, 3, 2, true>), grid, dim3(256), lds, s, g, yi,
+                                   (T *)x, batch, scale_dt, W);
+            else
+                hipLaunchKernelGGL((bp_tiled_fan_il<T, BC, 6, 3, kBpAnglesFan, true>), grid, dim3(256), lds,
+                                   s, g, yi, (T *)x, batch, scale_dt, W);
+        }
     }
     *err = hipGetLastError();
     return true;
@@ -300,37 +327,47 @@ static hipError_t launch_bp_tiled(const Geom &g, const BpWork &work, const Launc
     }
     const uint4 *yi = (const uint4 *)ws;
     if (!g.fan) {
-        if (shape.angles <= 4) {
-            const size_t lds = (size_t)PLANES * 4 * kBpWinPar * sizeof(uint4);
-            if (il)
+        if (il) {
+            const int ab = par_async_angles(shape);
+            const size_t lds = par_async_lds(PLANES, ab);
+            if (ab == 2)
+                hipLaunchKernelGGL((bp_tiled_par_il<T, BC, 3, 3, 2>), grid, dim3(256), lds, s, g, yi,
+                                   (T *)x, batch, scale_dt, W);
+            else
                 hipLaunchKernelGGL((bp_tiled_par_il<T, BC, 3, 3, 4>), grid, dim3(256), lds, s, g, yi,
                                    (T *)x, batch, scale_dt, W);
-            else
-                hipLaunchKernelGGL((bp_tiled_par<T, BC, 3, 3, 4>), grid, dim3(256), lds, s, g,
-                                   (const T *)y, (T *)x, batch, scale_dt, W);
+        } else if (shape.angles <= 4) {
+            const size_t lds = (size_t)PLANES * 4 * kBpWinPar * sizeof(uint4);
+            hipLaunchKernelGGL((bp_tiled_par<T, BC, 3, 3, 4>), grid, dim3(256), lds, s, g,
+                               (const T *)y, (T *)x, batch, scale_dt, W);
         } else {
             const size_t lds = (size_t)PLANES * kBpAngles * kBpWinPar * sizeof(uint4);
-            if (il)
-                hipLaunchKernelGGL((bp_tiled_par_il<T, BC, 3, 3, kBpAngles>), grid, dim3(256), lds, s,
-                                   g, yi, (T *)x, batch, scale_dt, W);
-            else
-                hipLaunchKernelGGL((bp_tiled_par<T, BC, 3, 3, kBpAngles>), grid, dim3(256), lds, s, g,
-                                   (const T *)y, (T *)x, batch, scale_dt, W);
+            hipLaunchKernelGGL((bp_tiled_par<T, BC, 3, 3, kBpAngles>), grid, dim3(256), lds, s, g,
+                               (const T *)y, (T *)x, batch, scale_dt, W);
         }
     } else {
-        const size_t lds = (size_t)PLANES * kBpAnglesFan * W * sizeof(uint4) +
-                           (size_t)kBpAnglesFan * W * sizeof(float4);
+        // the caller's sinograms: kBpAnglesFan angles per block; the interleaved copy:
+        // the shape's (2 or kBpAnglesFan)
+        const int ab = il ? fan_block_angles(shape) : kBpAnglesFan;
+        const size_t lds = il ? fan_async_lds(PLANES, ab, W)
+                              : (size_t)PLANES * ab * W * sizeof(uint4) + (size_t)ab * W * sizeof(float4);
         if (work.bins <= 4) {
-            if (il)
-                hipLaunchKernelGGL((bp_tiled_fan_il<T, BC, 4, 3>), grid, dim3(256), lds, s, g, yi,
+            if (il && ab == 2)
+                hipLaunchKernelGGL((bp_tiled_fan_il<T, BC, 4, 3, 2>), grid, dim3(256), lds, s, g, yi,
                                    (T *)x, batch, scale_dt, W);
+            else if (il)
+                hipLaunchKernelGGL((bp_tiled_fan_il<T, BC, 4, 3, kBpAnglesFan>), grid, dim3(256), lds, s, g,
+                                   yi, (T *)x, batch, scale_dt, W);
             else
                 hipLaunchKernelGGL((bp_tiled_fan<T, BC, 4, 3>), grid, dim3(256), lds, s, g,
                                    (const T *)y, (T *)x, batch, scale_dt, W);
         } else {
-            if (il)
-                hipLaunchKernelGGL((bp_tiled_fan_il<T, BC, 6, 3>), grid, dim3(256), lds, s, g, yi,
+            if (il && ab == 2)
+                hipLaunchKernelGGL((bp_tiled_fan_il<T, BC, 6, 3, 2>), grid, dim3(256), lds, s, g, yi,
                                    (T *)x, batch, scale_dt, W);
+            else if (il)
+                hipLaunchKernelGGL((bp_tiled_fan_il<T, BC, 6, 3, kBpAnglesFan>), grid, dim3(256), lds, s, g,
+                                   yi, (T *)x, batch, scale_dt, W);
             else
                 hipLaunchKernelGGL((bp_tiled_fan<T, BC, 6, 3>), grid, dim3(256), lds, s, g,
                                    (const T *)y, (T *)x, batch, scale_dt, W);

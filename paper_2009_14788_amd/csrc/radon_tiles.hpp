@@ -6,6 +6,7 @@
 
 #include "radon_common.hpp"
 #include "radon_launch.hpp"
+#include "radon_lds_dma.hpp"
 
 namespace radon {
 
@@ -426,6 +427,47 @@ struct SinoInterleavedSource {
                 if (k < slots) drow[lds_off[k]] = row[src_off[k]];
         }
     }
+    // Asynchronous staging of the windows of na angles (lds_copy16_async: 16 bytes per
+    // lane straight into LDS at a wave-uniform base + 16 * lane): angle-major layout
+    // dst[al][plane][bin], angle stride PLANES * W, so element f = threadIdx + 256 k of
+    // an angle is the lane's slot of a contiguous wave row.  Lanes past the window
+    // (f >= PLANES * W) are masked off.
+    __device__ __forceinline__ void issue(uint4 *dst, int a0, int na, int W, const int *wlo) const {
+        constexpr int PLANES = BC / (PAIRS ? 4 : Chunk<T>::kImages);
+        const int pw = PLANES * W;
+        const int wave = (int)threadIdx.x & ~63;
+        for (int al = 0; al < na; ++al) {
+            const int w0 = min(max(wlo[al], -W), D);
+            const uint4 *row = base + (size_t)(a0 + al) * Dp + w0;
+#pragma unroll
+            for (int k = 0; k < kSlots; ++k)
+                if (k < slots) lds_copy16_async(row + src_off[k], dst + al * pw + 256 * k + wave);
+        }
+    }
+    // Same with the planes P chunks apart (P >= W, a compile-time pitch): element
+    // f = q * P + j (plane q, bin j < W) of angle al at dst[al * PLANES * P + f]; the
+    // slots j >= W are left as they are (never read).
+    template <int P>
+    __device__ __forceinline__ void issue_pitched(uint4 *dst, int a0, int na, int W, const int *wlo) const {
+        constexpr int PLANES = BC / (PAIRS ? 4 : Chunk<T>::kImages);
+        constexpr int NS = (PLANES * P + 255) / 256;
+        const int wave = (int)threadIdx.x & ~63;
+        int off[NS];
+        bool on[NS];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            const int f = (int)threadIdx.x + 256 * k, q = f / P, j = f - q * P;
+            on[k] = q < PLANES && j < W;
+            off[k] = q * plane_stride + W + j;
+        }
+        for (int al = 0; al < na; ++al) {
+            const int w0 = min(max(wlo[al], -W), D);
+            const uint4 *row = base + (size_t)(a0 + al) * Dp + w0;
+#pragma unroll
+            for (int k = 0; k < NS; ++k)
+                if (on[k]) lds_copy16_async(row + off[k], dst + al * PLANES * P + 256 * k + wave);
+        }
+    }
 };
 
 // NB candidate-bin weights of one (pixel, angle) applied to the tap-pair chunks of
@@ -467,16 +509,73 @@ __device__ __forceinline__ void bp_apply_pairs(const float *wgt, const uint4 *ro
     }
 }
 
+// Parallel beam, one (pixel, angle): the NB x NK lattice samples (bin d, step k)
+// whose bilinear footprint can cover the pixel.  The pixel's continuous lattice
+// coordinates (u*, v*) are formed in FP64 from the angle's constants; candidates
+// d = floor(u* - hu) + 1 + i, k = floor(v* - hv) + 1 + j; their offsets from the pixel
+// are small FP32 numbers, so the tent weights are accurate to FP32 rounding.  Returns
+// the first candidate bin, wgt[i] the summed weight of bin d + i.
+template <int NB, int NK>
+__device__ __forceinline__ int par_candidates(const Geom &g, const BpAngle &ba, double qx, double qy, float sp,
+                                              float dt, float *wgt) {
+    // continuous bin (u) and step (v) coordinates of the pixel centre
+    const double u = fma(qx, ba.cu, fma(qy, ba.su, g.half_d));
+    const double v = fma(qy, ba.cv, -qx * ba.sv);
+    const double db = floor(u - ba.hu), kb = floor(v - ba.hv);
+    // offset of candidate (d = db+1+i, k = kb+1+j) from the pixel, along u and v
+    const float e0 = (float)(db + 1.0 - u) * sp, t0 = (float)(kb + 1.0 - v) * dt;
+    float dx_i = fmaf(e0, ba.cf, -t0 * ba.sf), dy_i = fmaf(e0, ba.sf, t0 * ba.cf);
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        float dx = dx_i, dy = dy_i, w = 0.0f;
+#pragma unroll
+        for (int jj = 0; jj < NK; ++jj) {
+            const float tx = __builtin_amdgcn_fmed3f(1.0f - fabsf(dx), 0.0f, 1.0f);
+            const float ty = __builtin_amdgcn_fmed3f(1.0f - fabsf(dy), 0.0f, 1.0f);
+            w = fmaf(tx, ty, w);
+            dx += ba.vx;
+            dy += ba.vy;
+        }
+        wgt[i] = w;
+        dx_i += ba.ux;
+        dy_i += ba.uy;
+    }
+    return (int)db + 1;
+}
+
+// NB candidate-bin weights applied to the 16-byte chunks (Chunk<T>::kImages images
+// each) of PLANES planes PP chunks apart, bins lb .. lb + NB - 1 at row[0 .. NB - 1]:
+// planes in a register pipeline, the next plane's NB chunks read while the current
+// plane's are applied, so LDS latency overlaps the multiply-adds.
+template <typename T, int PLANES, int NB, int PP>
+__device__ __forceinline__ void bp_apply_chunks(const float *wgt, const uint4 *row, float *part) {
+    constexpr int CH = Chunk<T>::kImages;
+    uint4 cur[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) cur[i] = row[i];
+#pragma unroll
+    for (int qq = 0; qq < PLANES; ++qq) {
+        uint4 nxt[NB];
+        if (qq + 1 < PLANES) {
+#pragma unroll
+            for (int i = 0; i < NB; ++i) nxt[i] = row[(qq + 1) * PP + i];
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) Chunk<T>::fma(wgt[i], cur[i], part + qq * CH);
+        if (qq + 1 < PLANES) {
+#pragma unroll
+            for (int i = 0; i < NB; ++i) cur[i] = nxt[i];
+        }
+    }
+}
+
 // Parallel beam.  One block = a 16x16 pixel tile (lane <-> pixel) x BC images.
 // Angles are processed in blocks of AB: for each, the block stages into LDS
 // the window of W bins its tile can touch, as 16-byte chunks of Chunk<T>::kImages
-// images ("planes").  Each pixel then finds, per angle, the lattice samples
-// (bin d, step k) whose bilinear footprint covers it: the pixel's continuous
-// lattice coordinates (u*, v*) are formed in FP64 from per-angle constants, the
-// NB x NK candidates d = floor(u* - hu) + 1 + i, k = floor(v* - hv) + 1 + j cover
-// every sample within the footprint, and their offsets from the pixel are small FP32
-// numbers, so the tent weights are accurate to FP32 rounding.  The NB bin weights are
-// then applied to BC images with 16-byte LDS reads.  No atomics.
+// images ("planes").  Each pixel then finds, per angle, the lattice samples whose
+// bilinear footprint covers it (par_candidates) and applies the NB bin weights to BC
+// images with 16-byte LDS reads.  No atomics.  This form stages each block between
+// barriers (the caller's sinograms, and the uneven batches).
 template <typename T, int BC, int NB, int NK, int AB, class Source>
 __device__ __forceinline__ void bp_tile_par(const Geom &g, int tile, const ImageSet<T, BC> &imgs,
                                             const Source &src, int W, uint4 *lds) {
@@ -522,56 +621,93 @@ __device__ __forceinline__ void bp_tile_par(const Geom &g, int tile, const Image
             for (int i = 0; i < BC; ++i) part[i] = 0.0f;
         }
         for (int al = 0; al < na; ++al) {
-            const BpAngle ba = g.bpa[a0 + al];
-            // continuous bin (u) and step (v) coordinates of the pixel centre
-            const double u = fma(qx, ba.cu, fma(qy, ba.su, g.half_d));
-            const double v = fma(qy, ba.cv, -qx * ba.sv);
-            const double db = floor(u - ba.hu), kb = floor(v - ba.hv);
-            // offset of candidate (d = db+1+i, k = kb+1+j) from the pixel, along u and v
-            const float e0 = (float)(db + 1.0 - u) * sp, t0 = (float)(kb + 1.0 - v) * dt;
-            float dx_i = fmaf(e0, ba.cf, -t0 * ba.sf), dy_i = fmaf(e0, ba.sf, t0 * ba.cf);
             float wgt[NB];
-#pragma unroll
-            for (int i = 0; i < NB; ++i) {
-                float dx = dx_i, dy = dy_i, w = 0.0f;
-#pragma unroll
-                for (int jj = 0; jj < NK; ++jj) {
-                    const float tx = __builtin_amdgcn_fmed3f(1.0f - fabsf(dx), 0.0f, 1.0f);
-                    const float ty = __builtin_amdgcn_fmed3f(1.0f - fabsf(dy), 0.0f, 1.0f);
-                    w = fmaf(tx, ty, w);
-                    dx += ba.vx;
-                    dy += ba.vy;
-                }
-                wgt[i] = w;
-                dx_i += ba.ux;
-                dy_i += ba.uy;
-            }
-            int lb = (int)db + 1 - wlo_s[al];
+            int lb = par_candidates<NB, NK>(g, g.bpa[a0 + al], qx, qy, sp, dt, wgt) - wlo_s[al];
             lb = min(max(lb, 0), W - NB);               // memory safety; real pixels are inside
             const uint4 *row = lds + al * W + lb;
-            if constexpr (Source::kPairs) {
+            if constexpr (Source::kPairs)
                 bp_apply_pairs<T, PLANES, NB, per_plane>(wgt, row, part);
-            } else {
-                // planes in a register pipeline: the next plane's NB chunks are read while
-                // the current plane's are applied, so LDS latency overlaps the multiply-adds
-                uint4 cur[NB];
+            else
+                bp_apply_chunks<T, PLANES, NB, per_plane>(wgt, row, part);
+        }
+        if (kTwoLevel) {
 #pragma unroll
-                for (int i = 0; i < NB; ++i) cur[i] = row[i];
+            for (int i = 0; i < BC; ++i) acc[i] += part[i];
+        }
+    }
+    if (c >= n || r >= n) return;
 #pragma unroll
-                for (int qq = 0; qq < PLANES; ++qq) {
-                    uint4 nxt[NB];
-                    if (qq + 1 < PLANES) {
+    for (int i = 0; i < BC; ++i)
+        if (i < imgs.count)
+            Store<T>::store(imgs.out[i] + (size_t)r * n + c, acc[i] * imgs.scale[i]);
+}
+
+// Parallel beam from the interleaved copy, with the sinogram windows double-buffered
+// as in bp_tile_fan_async: the next block's copies (lds_copy16_async) run while this
+// block is applied.  Windows at a fixed plane pitch of kBpWinPar chunks, angle stride
+// PLANES * kBpWinPar (both immediates in the reads).  Same arithmetic and summation
+// order as bp_tile_par.  The blocks' angle constants are read from LDS: after the
+// asm-issued copies the compiler no longer reads uniform global tables with scalar loads.
+template <typename T, int BC, int NB, int NK, int AB, bool PAIRS>
+__device__ __forceinline__ void bp_tile_par_async(const Geom &g, int tile, const ImageSet<T, BC> &imgs,
+                                                  const SinoInterleavedSource<T, BC, PAIRS> &src, int W,
+                                                  uint4 *lds) {
+    __shared__ int wlo_s[3][AB];
+    __shared__ BpAngle bpa_s[3][AB];
+    constexpr int CH = PAIRS ? 4 : Chunk<T>::kImages;
+    constexpr int PLANES = BC / CH;
+    static_assert(BC % CH == 0, "BC must be a multiple of the images per chunk");
+    constexpr int AS = PLANES * kBpWinPar;             // chunks per staged angle
+    const int n = g.n, A = g.n_angles;
+    const int tiles_x = (n + kBpTile - 1) / kBpTile;
+    const int tx0 = (tile % tiles_x) * kBpTile, ty0 = (tile / tiles_x) * kBpTile;
+    const int c = tx0 + (threadIdx.x % kBpTile), r = ty0 + (threadIdx.x / kBpTile);
+    const double qx = (double)c - g.cn, qy = (double)r - g.cn;
+    const double tcx = tx0 + 0.5 * (kBpTile - 1) - g.cn, tcy = ty0 + 0.5 * (kBpTile - 1) - g.cn;
+    const float dt = (float)g.step, sp = (float)g.spacing;
+    // angle a's constants and the first bin of the tile's window there, into slot t
+    auto bounds = [&](int a, int slot, int t) {
+        const BpAngle ba = g.bpa[a];
+        bpa_s[slot][t] = ba;
+        const double uc = fma(tcx, ba.cu, fma(tcy, ba.su, g.half_d));
+        wlo_s[slot][t] = (int)floor(uc - (0.5 * (kBpTile - 1) + 1.0) * ba.hu) - 1;
+    };
+
+    float acc[BC];
 #pragma unroll
-                        for (int i = 0; i < NB; ++i) nxt[i] = row[(qq + 1) * per_plane + i];
-                    }
+    for (int i = 0; i < BC; ++i) acc[i] = 0.0f;
+
+    const int nblk = (A + AB - 1) / AB;
+    if ((int)threadIdx.x < min(AB, A)) bounds(threadIdx.x, 0, threadIdx.x);
+    __syncthreads();
+    src.template issue_pitched<kBpWinPar>(lds, 0, min(AB, A), W, wlo_s[0]);
+    for (int b = 0; b < nblk; ++b) {
+        const int a0 = b * AB, na = min(AB, A - a0), nn = min(AB, A - a0 - AB);
+        const int cur = b & 1, tb = b % 3, tn = (b + 1) % 3;
+        const uint4 *sino_cur = lds + cur * AB * AS;
+        uint4 *sino_next = lds + (cur ^ 1) * AB * AS;
+        if ((int)threadIdx.x < nn) bounds(a0 + AB + threadIdx.x, tn, threadIdx.x);
+        __builtin_amdgcn_s_waitcnt(0);                 // this wave's copies of block b have landed
+        __syncthreads();                               // ... and everyone's; next bounds written
+        // the next block's copies run while this block is applied
+        if (nn > 0) src.template issue_pitched<kBpWinPar>(sino_next, a0 + AB, nn, W, wlo_s[tn]);
+
+        constexpr bool kTwoLevel = BC <= 32;
+        float part_buf[kTwoLevel ? BC : 1];
+        float *part = kTwoLevel ? part_buf : acc;
+        if (kTwoLevel) {
 #pragma unroll
-                    for (int i = 0; i < NB; ++i) Chunk<T>::fma(wgt[i], cur[i], part + qq * CH);
-                    if (qq + 1 < PLANES) {
-#pragma unroll
-                        for (int i = 0; i < NB; ++i) cur[i] = nxt[i];
-                    }
-                }
-            }
+            for (int i = 0; i < BC; ++i) part[i] = 0.0f;
+        }
+        for (int al = 0; al < na; ++al) {
+            float wgt[NB];
+            int lb = par_candidates<NB, NK>(g, bpa_s[tb][al], qx, qy, sp, dt, wgt) - wlo_s[tb][al];
+            lb = min(max(lb, 0), W - NB);               // memory safety; real pixels are inside
+            const uint4 *row = sino_cur + al * AS + lb;
+            if constexpr (PAIRS)
+                bp_apply_pairs<T, PLANES, NB, kBpWinPar>(wgt, row, part);
+            else
+                bp_apply_chunks<T, PLANES, NB, kBpWinPar>(wgt, row, part);
         }
         if (kTwoLevel) {
 #pragma unroll
@@ -594,20 +730,22 @@ __device__ __forceinline__ void bp_tile_par(const Geom &g, int tile, const Image
 // candidate samples from the pixel carry ~1e-6 pixel of rounding, as in the parallel
 // kernel.
 template <typename T, int BC, int NBX, int NK, bool PAIRS>
-__device__ __forceinline__ void fan_angle_block(const Geom &g, int a0, int na, int W, const int *wlo_s,
+__device__ __forceinline__ void fan_angle_block(const Geom &g, const double2 *trig, int na, int W, const int *wlo_s,
                                                 const float4 *rays_s, const uint4 *lds, int per_plane,
-                                                float qx, float qy, float lx, float ly, float is2,
+                                                int as, float qx, float qy, float lx, float ly, float is2,
                                                 float *part, int skip = 0) {
     constexpr int CH = PAIRS ? 4 : Chunk<T>::kImages;
     constexpr int PLANES = BC / CH;
     const float sd = (float)g.sd, k_sde = (float)(g.sde * g.inv_spacing), hd = (float)g.half_d;
     for (int al = 0; al < na; ++al) {
-        const double2 cs64 = g.trig[a0 + al];
+        const double2 cs64 = trig[al];
         const float cx = (float)cs64.x, sy = (float)cs64.y;
         // detector coordinate of the pixel centre and its gradient (bins per pixel)
         const float pu = fmaf(qx, cx, qy * sy), pv = fmaf(-qx, sy, qy * cx);
         const float near = sd + pv;
-        const float den = 1.0f / near;
+        // hardware reciprocal (1 ulp): den only places the candidate bins, whose
+        // margin is ~1e5 times larger than its error
+        const float den = __builtin_amdgcn_rcpf(near);
         const float sb = fmaf(k_sde * pu, den, hd);
         const float k2 = k_sde * den * den;
         const float gsx = k2 * fmaf(cx, near, pu * sy), gsy = k2 * fmaf(sy, near, -pu * cx);
@@ -635,7 +773,7 @@ __device__ __forceinline__ void fan_angle_block(const Geom &g, int a0, int na, i
             }
             wgt[i] = w;
         }
-        const uint4 *row = lds + al * W + lb;
+        const uint4 *row = lds + al * as + lb;
         if constexpr (PAIRS) {
             bp_apply_pairs<T, PLANES, NBX, 0>(wgt, row, part, per_plane);
         } else {
@@ -663,6 +801,52 @@ __device__ __forceinline__ void fan_angle_block(const Geom &g, int a0, int na, i
     }
 }
 
+// Bin window start of a 16x16 tile at angle a (the projections of the corners of its
+// footprint) and the candidate bins a footprint can need there:
+// |grad s| <= SE/(S+v) sqrt(1 + (u/(S+v))^2) with v the smallest and |u| the largest
+// over the corners (both linear).  FP64, one thread per angle.
+template <int NB>
+__device__ __forceinline__ void fan_tile_bounds(const Geom &g, int tx0, int ty0, int a, int *wlo, int *nb) {
+    const double2 cs = g.trig[a];
+    double lo = 1e30, vmin = 1e30, umax = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double px = tx0 - 1.0 + ((k & 1) ? kBpTile + 1.0 : 0.0) - g.cn;
+        const double py = ty0 - 1.0 + ((k & 2) ? kBpTile + 1.0 : 0.0) - g.cn;
+        const double pu = fma(px, cs.x, py * cs.y), pv = fma(-px, cs.y, py * cs.x);
+        lo = fmin(lo, g.sde * pu / (g.sd + pv) * g.inv_spacing + g.half_d);
+        vmin = fmin(vmin, pv);
+        umax = fmax(umax, fabs(pu));
+    }
+    *wlo = (int)floor(lo) - 1;
+    const double near = g.sd + vmin, ratio = umax / near;
+    const double grad = g.sde / near * sqrt(1.0 + ratio * ratio);
+    const double span = 2.0 * 1.4142135623730951 * grad * g.inv_spacing * 1.01 + 0.1;
+    *nb = near > 0.0 ? (int)floor(span) + 1 : NB;
+}
+
+// The rays of the bin windows of na angles into rays_s[al * W + j]: each ray's samples
+// are o + k s (index coordinates, FP64); staged is its lattice point nearest the tile
+// centre, relative to the tile origin, and its step, in FP32.  A bin outside the
+// detector gets a ray far from every pixel (weight 0).
+__device__ __forceinline__ void fan_stage_rays(const Geom &g, int a0, int na, int W, const int *wlo_s,
+                                               int tx0, int ty0, float4 *rays_s) {
+    const int D = g.det_count;
+    const double tcx = tx0 + 0.5 * (kBpTile - 1), tcy = ty0 + 0.5 * (kBpTile - 1);
+    for (int p = threadIdx.x; p < na * W; p += 256) {
+        const int al = p / W, j = p - al * W;
+        const int d = wlo_s[al] + j;
+        float4 v = make_float4(-1e9f, -1e9f, 0.0f, 0.0f);
+        if ((unsigned)d < (unsigned)D) {
+            const double4 rp = g.rays[(size_t)(a0 + al) * D + d];
+            const double k0 = rint(fma(tcx - rp.x, rp.z, (tcy - rp.y) * rp.w) * g.inv_step * g.inv_step);
+            v = make_float4((float)(fma(k0, rp.z, rp.x) - tx0), (float)(fma(k0, rp.w, rp.y) - ty0),
+                            (float)rp.z, (float)rp.w);
+        }
+        rays_s[al * W + j] = v;
+    }
+}
+
 // Fan beam.  Same tiling as the parallel kernel; every bin has its own ray, so the
 // block also stages the rays of its bin window (each as its lattice point nearest the
 // tile, relative to the tile, and its step, in FP32).  Per (pixel, angle) the
@@ -674,73 +858,37 @@ __device__ __forceinline__ void fan_angle_block(const Geom &g, int a0, int na, i
 // per block of angles the tile's own bound (its footprint's smallest distance to the
 // source and largest lateral offset) usually needs only 4 (96% of the blocks of a
 // 512^2 image at S = 1000, E = 500, 1.5-pixel bins), and only the other blocks run a
-// second pass over the next 2.
-template <typename T, int BC, int NB, int NK, class Source>
+// second pass over the next 2.  This form stages each block of AB angles between
+// barriers (the caller's sinograms, and the uneven batches).
+template <typename T, int BC, int NB, int NK, int AB, class Source>
 __device__ __forceinline__ void bp_tile_fan(const Geom &g, int tile, const ImageSet<T, BC> &imgs,
                                             const Source &src, int W, uint4 *lds) {
-    __shared__ int wlo_s[kBpAnglesFan];
-    __shared__ int nb_s[kBpAnglesFan];
+    __shared__ int wlo_s[AB];
+    __shared__ int nb_s[AB];
     constexpr int CH = Source::kPairs ? 4 : Chunk<T>::kImages;
     constexpr int PLANES = BC / CH;
     static_assert(BC % CH == 0, "BC must be a multiple of the images per chunk");
-    const int n = g.n, A = g.n_angles, D = g.det_count;
+    const int n = g.n, A = g.n_angles;
     const int tiles_x = (n + kBpTile - 1) / kBpTile;
     const int tx0 = (tile % tiles_x) * kBpTile, ty0 = (tile / tiles_x) * kBpTile;
     const int c = tx0 + (threadIdx.x % kBpTile), r = ty0 + (threadIdx.x / kBpTile);
     const float qx = (float)((double)c - g.cn), qy = (float)((double)r - g.cn);
     const float lx = (float)(c - tx0), ly = (float)(r - ty0);
-    const int per_plane = kBpAnglesFan * W;
+    const int per_plane = AB * W;
     float4 *rays_s = reinterpret_cast<float4 *>(lds + PLANES * per_plane);
     const float is2 = (float)(g.inv_step * g.inv_step);
-    // tile centre (index coordinates): each staged ray is moved to its lattice point
-    // nearest to it
-    const double tcx = tx0 + 0.5 * (kBpTile - 1), tcy = ty0 + 0.5 * (kBpTile - 1);
 
     float acc[BC];
 #pragma unroll
     for (int i = 0; i < BC; ++i) acc[i] = 0.0f;
 
-    for (int a0 = 0; a0 < A; a0 += kBpAnglesFan) {
-        const int na = min(kBpAnglesFan, A - a0);
+    for (int a0 = 0; a0 < A; a0 += AB) {
+        const int na = min(AB, A - a0);
         __syncthreads();
-        if (threadIdx.x < na) {
-            // bin window of the tile: projections of the corners of its footprint; and
-            // the bins a footprint can need there: |grad s| <= SE/(S+v) sqrt(1 + (u/(S+v))^2)
-            // with v the smallest and |u| the largest over the corners (both linear)
-            const double2 cs = g.trig[a0 + threadIdx.x];
-            double lo = 1e30, vmin = 1e30, umax = 0.0;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const double px = tx0 - 1.0 + ((k & 1) ? kBpTile + 1.0 : 0.0) - g.cn;
-                const double py = ty0 - 1.0 + ((k & 2) ? kBpTile + 1.0 : 0.0) - g.cn;
-                const double pu = fma(px, cs.x, py * cs.y), pv = fma(-px, cs.y, py * cs.x);
-                lo = fmin(lo, g.sde * pu / (g.sd + pv) * g.inv_spacing + g.half_d);
-                vmin = fmin(vmin, pv);
-                umax = fmax(umax, fabs(pu));
-            }
-            wlo_s[threadIdx.x] = (int)floor(lo) - 1;
-            const double near = g.sd + vmin, ratio = umax / near;
-            const double grad = g.sde / near * sqrt(1.0 + ratio * ratio);
-            const double span = 2.0 * 1.4142135623730951 * grad * g.inv_spacing * 1.01 + 0.1;
-            nb_s[threadIdx.x] = near > 0.0 ? (int)floor(span) + 1 : NB;
-        }
+        if (threadIdx.x < na) fan_tile_bounds<NB>(g, tx0, ty0, a0 + threadIdx.x, &wlo_s[threadIdx.x], &nb_s[threadIdx.x]);
         __syncthreads();
         src.stage(lds, a0, na, W, wlo_s, per_plane);
-        for (int p = threadIdx.x; p < na * W; p += 256) {
-            const int al = p / W, j = p - al * W;
-            const int d = wlo_s[al] + j;
-            // a bin outside the detector gets a ray far from every pixel (weight 0)
-            float4 v = make_float4(-1e9f, -1e9f, 0.0f, 0.0f);
-            if ((unsigned)d < (unsigned)D) {
-                // the ray's samples are o + k s (index coordinates, FP64): the lattice
-                // point nearest the tile centre, relative to the tile origin, in FP32
-                const double4 rp = g.rays[(size_t)(a0 + al) * D + d];
-                const double k0 = rint(fma(tcx - rp.x, rp.z, (tcy - rp.y) * rp.w) * g.inv_step * g.inv_step);
-                v = make_float4((float)(fma(k0, rp.z, rp.x) - tx0), (float)(fma(k0, rp.w, rp.y) - ty0),
-                                (float)rp.z, (float)rp.w);
-            }
-            rays_s[al * W + j] = v;
-        }
+        fan_stage_rays(g, a0, na, W, wlo_s, tx0, ty0, rays_s);
         int nb_block = 0;
         for (int al = 0; al < na; ++al) nb_block = max(nb_block, nb_s[al]);
         __syncthreads();
@@ -756,11 +904,94 @@ __device__ __forceinline__ void bp_tile_fan(const Geom &g, int tile, const Image
         // candidate bins: four, and for the angle blocks whose bound needs more, two
         // more in a second pass (one 4-bin body keeps the registers of the wide lanes
         // at three waves per SIMD, where a 6-bin body needed two)
-        fan_angle_block<T, BC, 4, NK, Source::kPairs>(g, a0, na, W, wlo_s, rays_s, lds, per_plane, qx, qy,
-                                                      lx, ly, is2, part);
+        fan_angle_block<T, BC, 4, NK, Source::kPairs>(g, g.trig + a0, na, W, wlo_s, rays_s, lds, per_plane, W, qx,
+                                                      qy, lx, ly, is2, part);
         if (NB > 4 && nb_block > 4)
-            fan_angle_block<T, BC, 2, NK, Source::kPairs>(g, a0, na, W, wlo_s, rays_s, lds, per_plane, qx,
+            fan_angle_block<T, BC, 2, NK, Source::kPairs>(g, g.trig + a0, na, W, wlo_s, rays_s, lds, per_plane, W, qx,
                                                           qy, lx, ly, is2, part, 4);
+        if (kTwoLevel) {
+#pragma unroll
+            for (int i = 0; i < BC; ++i) acc[i] += part[i];
+        }
+    }
+    if (c >= n || r >= n) return;
+#pragma unroll
+    for (int i = 0; i < BC; ++i)
+        if (i < imgs.count)
+            Store<T>::store(imgs.out[i] + (size_t)r * n + c, acc[i] * imgs.scale[i]);
+}
+
+// Fan beam from the interleaved copy, with the sinogram windows double-buffered: the
+// copy of the next block of AB angles goes straight from global memory into the other
+// LDS buffer (asynchronous, see SinoInterleavedSource::issue) while this block is
+// applied, so the block stalls on staging only when the copy outlasts the arithmetic.
+// Same arithmetic, candidate bins and summation order as bp_tile_fan.  Buffers:
+// sinogram windows and rays 2 each (angle-major windows, angle stride PLANES * W),
+// window bounds 3 (a block's bounds are written two iterations before they are
+// overwritten, so no wave still applies that block).
+template <typename T, int BC, int NB, int NK, int AB, bool PAIRS>
+__device__ __forceinline__ void bp_tile_fan_async(const Geom &g, int tile, const ImageSet<T, BC> &imgs,
+                                                  const SinoInterleavedSource<T, BC, PAIRS> &src, int W,
+                                                  uint4 *lds) {
+    __shared__ int wlo_s[3][AB];
+    __shared__ int nb_s[3][AB];
+    // the blocks' cos/sin, read from LDS: after the asm-issued copies the compiler no
+    // longer reads uniform global tables with scalar loads
+    __shared__ double2 trig_s[3][AB];
+    constexpr int CH = PAIRS ? 4 : Chunk<T>::kImages;
+    constexpr int PLANES = BC / CH;
+    static_assert(BC % CH == 0, "BC must be a multiple of the images per chunk");
+    const int n = g.n, A = g.n_angles;
+    const int tiles_x = (n + kBpTile - 1) / kBpTile;
+    const int tx0 = (tile % tiles_x) * kBpTile, ty0 = (tile / tiles_x) * kBpTile;
+    const int c = tx0 + (threadIdx.x % kBpTile), r = ty0 + (threadIdx.x / kBpTile);
+    const float qx = (float)((double)c - g.cn), qy = (float)((double)r - g.cn);
+    const float lx = (float)(c - tx0), ly = (float)(r - ty0);
+    const float is2 = (float)(g.inv_step * g.inv_step);
+    const int pw = PLANES * W;                         // chunks per staged angle
+    // buffer k: sinogram windows at lds + k * AB * pw, rays after both windows
+    float4 *rays0 = reinterpret_cast<float4 *>(lds + 2 * AB * pw);
+
+    float acc[BC];
+#pragma unroll
+    for (int i = 0; i < BC; ++i) acc[i] = 0.0f;
+
+    const int nblk = (A + AB - 1) / AB;
+    if ((int)threadIdx.x < min(AB, A)) {
+        fan_tile_bounds<NB>(g, tx0, ty0, threadIdx.x, &wlo_s[0][threadIdx.x], &nb_s[0][threadIdx.x]);
+        trig_s[0][threadIdx.x] = g.trig[threadIdx.x];
+    }
+    __syncthreads();
+    src.issue(lds, 0, min(AB, A), W, wlo_s[0]);
+    for (int b = 0; b < nblk; ++b) {
+        const int a0 = b * AB, na = min(AB, A - a0), nn = min(AB, A - a0 - AB);
+        const int cur = b & 1, tb = b % 3, tn = (b + 1) % 3;
+        uint4 *sino_cur = lds + cur * AB * pw, *sino_next = lds + (cur ^ 1) * AB * pw;
+        float4 *rays_cur = rays0 + cur * AB * W;
+        if ((int)threadIdx.x < nn) {
+            fan_tile_bounds<NB>(g, tx0, ty0, a0 + AB + threadIdx.x, &wlo_s[tn][threadIdx.x], &nb_s[tn][threadIdx.x]);
+            trig_s[tn][threadIdx.x] = g.trig[a0 + AB + threadIdx.x];
+        }
+        fan_stage_rays(g, a0, na, W, wlo_s[tb], tx0, ty0, rays_cur);
+        __builtin_amdgcn_s_waitcnt(0);                 // this wave's copies of block b have landed
+        __syncthreads();                               // ... and everyone's; rays and bounds written
+        int nb_block = 0;
+        for (int al = 0; al < na; ++al) nb_block = max(nb_block, nb_s[tb][al]);
+        // the next block's copies run while this block is applied
+        if (nn > 0) src.issue(sino_next, a0 + AB, nn, W, wlo_s[tn]);
+
+        constexpr bool kTwoLevel = BC <= 32;
+        float part_buf[kTwoLevel ? BC : 1];
+        float *part = kTwoLevel ? part_buf : acc;
+        if (kTwoLevel) {
+#pragma unroll
+            for (int i = 0; i < BC; ++i) part[i] = 0.0f;
+        }
+        fan_angle_block<T, BC, 4, NK, PAIRS>(g, trig_s[tb], na, W, wlo_s[tb], rays_cur, sino_cur, W, pw, qx, qy, lx,
+                                             ly, is2, part);
+        if (NB > 4 && nb_block > 4)
+            fan_angle_block<T, BC, 2, NK, PAIRS>(g, trig_s[tb], na, W, wlo_s[tb], rays_cur, sino_cur, W, pw, qx, qy,
+                                                 lx, ly, is2, part, 4);
         if (kTwoLevel) {
 #pragma unroll
             for (int i = 0; i < BC; ++i) acc[i] += part[i];

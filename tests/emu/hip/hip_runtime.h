@@ -67,6 +67,11 @@ inline float emu_fractf(float x) { return x - std::floor(x); }
 #define __builtin_amdgcn_fractf(x) emu_fractf(x)
 #define __builtin_amdgcn_fmed3f(a, b, c) emu_med3(a, b, c)
 #define __builtin_amdgcn_readfirstlane(x) (x)
+// memory-counter waits: every emulated access has completed already
+#define __builtin_amdgcn_s_waitcnt(x) ((void)0)
+// v_rcp_f32 (1 ulp on the device; the correctly rounded quotient here)
+inline float emu_rcpf(float x) { return 1.0f / x; }
+#define __builtin_amdgcn_rcpf(x) emu_rcpf(x)
 // v_dot2c_f32_f16 / v_dot2c_f32_bf16: the two 16-bit products are exact, their sum with
 // the FP32 accumulator is rounded once
 template <class V> inline float emu_fdot2(V a, V b, float c) {

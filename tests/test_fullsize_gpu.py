@@ -130,10 +130,10 @@ class _forced_shape:
 
 
 def _pairs_case(tag, op, og, x, ys, y_ref, xb_ref, dt, shape):
-    """Both directions in tap-pair staging (16-bit weights, dot2), whatever the
-    autotuner picks: every image against the oracle on the FP32 inputs, and the
-    kernel arithmetic alone (the oracle on the 16-bit-rounded inputs) at every lane
-    and plane position."""
+    """Both directions in a forced shape (mostly tap-pair staging: 16-bit weights,
+    dot2), whatever the autotuner picks: every image against the oracle on the FP32
+    inputs, and the kernel arithmetic alone (the oracle on the 16-bit-rounded inputs)
+    at every lane and plane position."""
     with _forced_shape(shape):
         _announce(f"{tag} tap pairs {dt} shape {shape}")
         xd = torch.from_numpy(x).cuda().to(TDT[dt])
@@ -189,11 +189,19 @@ def test_fan_full(fan, dt):
     _compare(f"fan_bp_{dt}", xb_gpu, xb_ref, TOL[dt], shape=shapes["backprojection"])
 
 
-@pytest.mark.parametrize("shape", ["16,2,64,4,2", "8,2,32,4,2"])
+@pytest.mark.parametrize("shape", ["16,2,64,4,2", "8,2,32,4,2", "16,2,64,2,2"])
 @pytest.mark.parametrize("dt", ["bf16", "f16"])
 def test_fan_tap_pairs(fan, dt, shape):
     case, og, x, ys, y_ref, xb_ref = fan
     _pairs_case("fan", case.library(), og, x, ys, y_ref, xb_ref, dt, shape)
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16"])
+def test_fan_two_angle_blocks(fan, dt):
+    """Fan backprojection staging two angles per LDS block (interleaved 16-bit copy,
+    64 images per lane), every image against the oracle."""
+    case, og, x, ys, y_ref, xb_ref = fan
+    _pairs_case("fan_ab2", case.library(), og, x, ys, y_ref, xb_ref, dt, "16,1,64,2,1")
 
 
 # ------------------------------------------------------------------ 200 uneven jobs

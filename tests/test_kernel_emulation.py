@@ -34,6 +34,8 @@ def emu_bin(tmp_path_factory):
     src.mkdir()
     for name in os.listdir(CSRC):
         text = open(os.path.join(CSRC, name)).read()
+        if name == "radon_lds_dma.hpp":     # the asm-issued copy, emulated on the host
+            text = open(os.path.join(EMU, "radon_lds_dma.hpp")).read()
         text = text.replace('"../../include/radon.h"', '"radon.h"')
         # dynamic LDS becomes the emulated block's buffer
         text = re.sub(r"extern __shared__ (\w+) (\w+)\[\];", r"\1 *\2 = (\1 *)emu::dyn_lds();", text)
@@ -116,18 +118,20 @@ def test_emulated_kernels_match_oracle(emu_bin, tmp_path):
                                    "8,0,64,8,0", "8,1,4,8,1", "4,0,4,4,0", "8,2,16,4,2", "16,2,32,8,0",
                                    "8,1,64,8,2", "16,2,8,4,2", "8,1,32,4,1,1", "4,0,16,8,0,2",
                                    "16,2,64,4,2,3", "8,1,64,8,1,3", "16,1,32,4,1,2", "16,1,64,4,1,1",
-                                   "16,0,16,8,0,0"])
+                                   "16,0,16,8,0,0", "8,2,64,2,2", "16,1,32,2,1", "8,1,16,2,0"])
 def test_emulated_launch_shapes(emu_bin, tmp_path, shape):
     """Every forced launch shape (images per lane, staging -- 2: 16-bit tap pairs with
-    dot2, forward or backprojection --, angle block, forward tiling: slab rows and
-    angles per item) stays in bounds and at parity, with a ragged batch of 11 images."""
+    dot2, forward or backprojection --, angle block -- fan beam 4 or 2 --, forward
+    tiling: slab rows and angles per item) stays in bounds and at parity, with a ragged
+    batch of 11 images and an angle count that leaves a partial angle block."""
     U = inputs.uniform_angles
     lines = [_line("par", 40, U(24), 57, batch=11),
              _line("par", 40, U(24), 57, batch=11, dt=1),
              _line("fan", 40, U(24, 2 * math.pi), 66, 1.5, 250.0, 120.0, batch=11),
              _line("fan", 37, U(24, 2 * math.pi), 60, 1.5, 250.0, 120.0, batch=11, dt=2),
              # source close enough that some tiles need 5-6 candidate bins (second pass)
-             _line("fan", 40, U(16, 2 * math.pi), 80, 1.0, 130.0, 40.0, batch=11, dt=1)]
+             _line("fan", 40, U(16, 2 * math.pi), 80, 1.0, 130.0, 40.0, batch=11, dt=1),
+             _line("fan", 36, U(23, 2 * math.pi), 60, 1.5, 250.0, 120.0, batch=11, dt=2)]
     rows, _ = _run(emu_bin, tmp_path, lines, env={"RADON_FORCE_SHAPE": shape})
     _check_bars(rows, lines)
 
