@@ -121,9 +121,11 @@ struct InterleavedSource {
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         const int lane = threadIdx.x & 63;
         const uint4 *src0 = (axis ? tbase : base) + (oy0 + 2) * np + (ox0 + 2);
-        // per window row: the row's loads are issued before its LDS stores; the row and
-        // column-block tests are wave-uniform, the last partial block clamps its column
-        // (a valid address) and masks the store
+        // every window row of every plane goes straight from global memory into LDS
+        // (lds_copy16_async: a wave's 64 lanes fill 64 consecutive chunks of the row),
+        // all in flight together, then one wait: one global round trip per slab instead
+        // of one per row.  Row and column-block tests are wave-uniform; lanes past the
+        // window end are masked off.
 #pragma unroll
         for (int q = 0; q < PLANES; ++q) {
             const uint4 *src = src0 + q * plane_stride;
@@ -134,18 +136,13 @@ struct InterleavedSource {
                 if (row >= r_end) break;
                 const uint4 *srow = src + row * np;
                 uint4 *drow = dst + row * pitch;
-                const uint4 v0 = srow[min(lane, c_end - 1)];
-                if (c_end > 64) {
-                    const uint4 v1 = srow[min(lane + 64, c_end - 1)];
-                    if (c_end > 128) {
-                        const uint4 v2 = srow[min(lane + 128, c_end - 1)];
-                        if (lane + 128 < c_end) drow[lane + 128] = v2;
-                    }
-                    if (lane + 64 < c_end) drow[lane + 64] = v1;
-                }
-                if (lane < c_end) drow[lane] = v0;
+                if (lane < c_end) lds_copy16_async(srow + lane, drow);
+                if (c_end > 64 && lane + 64 < c_end) lds_copy16_async(srow + lane + 64, drow + 64);
+                if (c_end > 128 && lane + 128 < c_end) lds_copy16_async(srow + lane + 128, drow + 128);
             }
         }
+        __builtin_amdgcn_s_waitcnt(0);     // this wave's copies have landed (the caller's
+                                           // barrier publishes everyone's)
     }
 };
 
