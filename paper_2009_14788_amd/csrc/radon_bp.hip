@@ -238,10 +238,11 @@ static int par_async_angles(const LaunchShape &shape) { return shape.angles <= 2
 // fixed pitch.
 static size_t par_async_lds(int planes, int ab) { return 2 * (size_t)planes * ab * kBpWinPar * sizeof(uint4); }
 
-// LDS of the double-buffered fan kernels: two sinogram windows and two ray windows of
-// ab angles.
+// LDS of the double-buffered fan kernels: two sinogram windows and two FP32 ray windows
+// of ab angles, and one window of raw FP64 rays.
 static size_t fan_async_lds(int planes, int ab, int W) {
-    return 2 * ((size_t)planes * ab * W * sizeof(uint4) + (size_t)ab * W * sizeof(float4));
+    return 2 * ((size_t)planes * ab * W * sizeof(uint4) + (size_t)ab * W * sizeof(float4)) +
+           (size_t)ab * W * sizeof(double4);
 }
 
 template <typename T, int BC>

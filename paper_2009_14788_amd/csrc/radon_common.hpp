@@ -190,7 +190,9 @@ struct Geom {
 // Per-angle constants of the parallel-beam backprojection, formed on the host in FP64
 // once per geometry: the pixel at centred coordinates (qx, qy) has bin coordinate
 // u = qx*cu + qy*su + (D-1)/2 and step coordinate v = qy*cv - qx*sv.
-struct BpAngle {
+// 80 bytes (five 16-byte chunks), so the double-buffered kernels copy a block's
+// constants into LDS with 16-byte asynchronous copies.
+struct alignas(16) BpAngle {
     double cu, su;   // cos / spacing, sin / spacing
     double cv, sv;   // cos / step, sin / step
     double hu, hv;   // (|cos| + |sin|) / spacing, (|cos| + |sin|) / step
@@ -198,6 +200,7 @@ struct BpAngle {
     float ux, uy;    // one bin along the detector: spacing * (cos, sin)
     float vx, vy;    // one step along the ray: step * (-sin, cos)
 };
+static_assert(sizeof(BpAngle) == 80, "five 16-byte chunks per angle");
 
 // Ray parameters of (angle a, bin d), FP64: foot point in index coordinates and
 // step * unit direction.  Sample positions are formed in FP64 and only their

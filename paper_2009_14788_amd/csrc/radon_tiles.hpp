@@ -642,9 +642,11 @@ __device__ __forceinline__ void bp_tile_par(const Geom &g, int tile, const Image
 // Parallel beam from the interleaved copy, with the sinogram windows double-buffered
 // as in bp_tile_fan_async: the next block's copies (lds_copy16_async) run while this
 // block is applied.  Windows at a fixed plane pitch of kBpWinPar chunks, angle stride
-// PLANES * kBpWinPar (both immediates in the reads).  Same arithmetic and summation
-// order as bp_tile_par.  The blocks' angle constants are read from LDS: after the
-// asm-issued copies the compiler no longer reads uniform global tables with scalar loads.
+// PLANES * kBpWinPar (both immediates in the reads).  The blocks' angle constants are
+// copied into LDS the same way two blocks ahead (triple-buffered), so the steps before
+// each barrier touch no global memory: after the wait for this wave's copies, the first
+// AB threads form the next block's window bounds from LDS.  Same arithmetic and
+// summation order as bp_tile_par.
 template <typename T, int BC, int NB, int NK, int AB, bool PAIRS>
 __device__ __forceinline__ void bp_tile_par_async(const Geom &g, int tile, const ImageSet<T, BC> &imgs,
                                                   const SinoInterleavedSource<T, BC, PAIRS> &src, int W,
@@ -654,6 +656,7 @@ __device__ __forceinline__ void bp_tile_par_async(const Geom &g, int tile, const
     constexpr int CH = PAIRS ? 4 : Chunk<T>::kImages;
     constexpr int PLANES = BC / CH;
     static_assert(BC % CH == 0, "BC must be a multiple of the images per chunk");
+    static_assert(AB * sizeof(BpAngle) / 16 <= 64, "one wave copies a block's angle constants");
     constexpr int AS = PLANES * kBpWinPar;             // chunks per staged angle
     const int n = g.n, A = g.n_angles;
     const int tiles_x = (n + kBpTile - 1) / kBpTile;
@@ -662,12 +665,19 @@ __device__ __forceinline__ void bp_tile_par_async(const Geom &g, int tile, const
     const double qx = (double)c - g.cn, qy = (double)r - g.cn;
     const double tcx = tx0 + 0.5 * (kBpTile - 1) - g.cn, tcy = ty0 + 0.5 * (kBpTile - 1) - g.cn;
     const float dt = (float)g.step, sp = (float)g.spacing;
-    // angle a's constants and the first bin of the tile's window there, into slot t
-    auto bounds = [&](int a, int slot, int t) {
-        const BpAngle ba = g.bpa[a];
-        bpa_s[slot][t] = ba;
+    // copies of the constants of the angle block starting at a (na angles) into slot
+    // k, by the lanes of wave 0
+    auto copy_angles = [&](int a, int na, int k) {
+        constexpr int kChunks = sizeof(BpAngle) / 16;
+        if (threadIdx.x < 64 && (int)threadIdx.x < na * kChunks)
+            lds_copy16_async(reinterpret_cast<const uint4 *>(g.bpa + a) + threadIdx.x,
+                             reinterpret_cast<uint4 *>(&bpa_s[k][0]));
+    };
+    // first bin of the tile's window at angle al of slot k (thread al < AB)
+    auto bounds = [&](int k, int al) {
+        const BpAngle &ba = bpa_s[k][al];
         const double uc = fma(tcx, ba.cu, fma(tcy, ba.su, g.half_d));
-        wlo_s[slot][t] = (int)floor(uc - (0.5 * (kBpTile - 1) + 1.0) * ba.hu) - 1;
+        wlo_s[k][al] = (int)floor(uc - (0.5 * (kBpTile - 1) + 1.0) * ba.hu) - 1;
     };
 
     float acc[BC];
@@ -675,19 +685,25 @@ __device__ __forceinline__ void bp_tile_par_async(const Geom &g, int tile, const
     for (int i = 0; i < BC; ++i) acc[i] = 0.0f;
 
     const int nblk = (A + AB - 1) / AB;
-    if ((int)threadIdx.x < min(AB, A)) bounds(threadIdx.x, 0, threadIdx.x);
+    copy_angles(0, min(AB, A), 0);
+    if (A > AB) copy_angles(AB, min(AB, A - AB), 1);
+    __builtin_amdgcn_s_waitcnt(0);
+    if ((int)threadIdx.x < min(AB, A)) bounds(0, threadIdx.x);
     __syncthreads();
     src.template issue_pitched<kBpWinPar>(lds, 0, min(AB, A), W, wlo_s[0]);
     for (int b = 0; b < nblk; ++b) {
-        const int a0 = b * AB, na = min(AB, A - a0), nn = min(AB, A - a0 - AB);
+        const int a0 = b * AB, na = min(AB, A - a0), nn = min(AB, A - a0 - AB), n2 = min(AB, A - a0 - 2 * AB);
         const int cur = b & 1, tb = b % 3, tn = (b + 1) % 3;
         const uint4 *sino_cur = lds + cur * AB * AS;
         uint4 *sino_next = lds + (cur ^ 1) * AB * AS;
-        if ((int)threadIdx.x < nn) bounds(a0 + AB + threadIdx.x, tn, threadIdx.x);
-        __builtin_amdgcn_s_waitcnt(0);                 // this wave's copies of block b have landed
+        __builtin_amdgcn_s_waitcnt(0);                 // this wave's copies have landed: block
+                                                       // b's windows, block b + 1's constants
+        if ((int)threadIdx.x < nn) bounds(tn, threadIdx.x);
         __syncthreads();                               // ... and everyone's; next bounds written
-        // the next block's copies run while this block is applied
+        // the next block's windows and the constants two blocks ahead are copied while
+        // this block is applied
         if (nn > 0) src.template issue_pitched<kBpWinPar>(sino_next, a0 + AB, nn, W, wlo_s[tn]);
+        if (n2 > 0) copy_angles(a0 + 2 * AB, n2, (b + 2) % 3);
 
         constexpr bool kTwoLevel = BC <= 32;
         float part_buf[kTwoLevel ? BC : 1];
@@ -798,13 +814,12 @@ __device__ __forceinline__ void fan_angle_block(const Geom &g, const double2 *tr
     }
 }
 
-// Bin window start of a 16x16 tile at angle a (the projections of the corners of its
+// Bin window start of a 16x16 tile at an angle of cos/sin cs (the projections of the corners of its
 // footprint) and the candidate bins a footprint can need there:
 // |grad s| <= SE/(S+v) sqrt(1 + (u/(S+v))^2) with v the smallest and |u| the largest
 // over the corners (both linear).  FP64, one thread per angle.
 template <int NB>
-__device__ __forceinline__ void fan_tile_bounds(const Geom &g, int tx0, int ty0, int a, int *wlo, int *nb) {
-    const double2 cs = g.trig[a];
+__device__ __forceinline__ void fan_tile_bounds(const Geom &g, int tx0, int ty0, double2 cs, int *wlo, int *nb) {
     double lo = 1e30, vmin = 1e30, umax = 0.0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -826,20 +841,20 @@ __device__ __forceinline__ void fan_tile_bounds(const Geom &g, int tx0, int ty0,
 // are o + k s (index coordinates, FP64); staged is its lattice point nearest the tile
 // centre, relative to the tile origin, and its step, in FP32.  A bin outside the
 // detector gets a ray far from every pixel (weight 0).
+__device__ __forceinline__ float4 fan_tile_ray(const Geom &g, const double4 &rp, int tx0, int ty0) {
+    const double tcx = tx0 + 0.5 * (kBpTile - 1), tcy = ty0 + 0.5 * (kBpTile - 1);
+    const double k0 = rint(fma(tcx - rp.x, rp.z, (tcy - rp.y) * rp.w) * g.inv_step * g.inv_step);
+    return make_float4((float)(fma(k0, rp.z, rp.x) - tx0), (float)(fma(k0, rp.w, rp.y) - ty0), (float)rp.z,
+                       (float)rp.w);
+}
 __device__ __forceinline__ void fan_stage_rays(const Geom &g, int a0, int na, int W, const int *wlo_s,
                                                int tx0, int ty0, float4 *rays_s) {
     const int D = g.det_count;
-    const double tcx = tx0 + 0.5 * (kBpTile - 1), tcy = ty0 + 0.5 * (kBpTile - 1);
     for (int p = threadIdx.x; p < na * W; p += 256) {
         const int al = p / W, j = p - al * W;
         const int d = wlo_s[al] + j;
         float4 v = make_float4(-1e9f, -1e9f, 0.0f, 0.0f);
-        if ((unsigned)d < (unsigned)D) {
-            const double4 rp = g.rays[(size_t)(a0 + al) * D + d];
-            const double k0 = rint(fma(tcx - rp.x, rp.z, (tcy - rp.y) * rp.w) * g.inv_step * g.inv_step);
-            v = make_float4((float)(fma(k0, rp.z, rp.x) - tx0), (float)(fma(k0, rp.w, rp.y) - ty0),
-                            (float)rp.z, (float)rp.w);
-        }
+        if ((unsigned)d < (unsigned)D) v = fan_tile_ray(g, g.rays[(size_t)(a0 + al) * D + d], tx0, ty0);
         rays_s[al * W + j] = v;
     }
 }
@@ -882,7 +897,8 @@ __device__ __forceinline__ void bp_tile_fan(const Geom &g, int tile, const Image
     for (int a0 = 0; a0 < A; a0 += AB) {
         const int na = min(AB, A - a0);
         __syncthreads();
-        if (threadIdx.x < na) fan_tile_bounds<NB>(g, tx0, ty0, a0 + threadIdx.x, &wlo_s[threadIdx.x], &nb_s[threadIdx.x]);
+        if (threadIdx.x < na)
+            fan_tile_bounds<NB>(g, tx0, ty0, g.trig[a0 + threadIdx.x], &wlo_s[threadIdx.x], &nb_s[threadIdx.x]);
         __syncthreads();
         src.stage(lds, a0, na, W, wlo_s, per_plane);
         fan_stage_rays(g, a0, na, W, wlo_s, tx0, ty0, rays_s);
@@ -922,23 +938,27 @@ __device__ __forceinline__ void bp_tile_fan(const Geom &g, int tile, const Image
 // copy of the next block of AB angles goes straight from global memory into the other
 // LDS buffer (asynchronous, see SinoInterleavedSource::issue) while this block is
 // applied, so the block stalls on staging only when the copy outlasts the arithmetic.
-// Same arithmetic, candidate bins and summation order as bp_tile_fan.  Buffers:
-// sinogram windows and rays 2 each (angle-major windows, angle stride PLANES * W),
-// window bounds 3 (a block's bounds are written two iterations before they are
-// overwritten, so no wave still applies that block).
+// The block's cos/sin pairs are copied the same way two blocks ahead and its raw FP64
+// rays (32 bytes per bin) one block ahead, so the steps before each barrier touch no
+// global memory: after the wait for its own copies each wave turns the raw rays it
+// copied into tile-relative FP32 rays (a wave copies whole rays), and the first AB
+// threads bound the next block's windows from the cos/sin in LDS.  Same arithmetic,
+// candidate bins and summation order as bp_tile_fan.  Buffers: sinogram windows and
+// FP32 rays 2 each (angle-major windows, angle stride PLANES * W), raw rays 1 (consumed
+// before the barrier after which it is refilled), window bounds and cos/sin 3 (a
+// block's are overwritten two iterations after they are written, when no wave can
+// still apply that block).
 template <typename T, int BC, int NB, int NK, int AB, bool PAIRS>
 __device__ __forceinline__ void bp_tile_fan_async(const Geom &g, int tile, const ImageSet<T, BC> &imgs,
                                                   const SinoInterleavedSource<T, BC, PAIRS> &src, int W,
                                                   uint4 *lds) {
     __shared__ int wlo_s[3][AB];
     __shared__ int nb_s[3][AB];
-    // the blocks' cos/sin, read from LDS: after the asm-issued copies the compiler no
-    // longer reads uniform global tables with scalar loads
     __shared__ double2 trig_s[3][AB];
     constexpr int CH = PAIRS ? 4 : Chunk<T>::kImages;
     constexpr int PLANES = BC / CH;
     static_assert(BC % CH == 0, "BC must be a multiple of the images per chunk");
-    const int n = g.n, A = g.n_angles;
+    const int n = g.n, A = g.n_angles, D = g.det_count;
     const int tiles_x = (n + kBpTile - 1) / kBpTile;
     const int tx0 = (tile % tiles_x) * kBpTile, ty0 = (tile / tiles_x) * kBpTile;
     const int c = tx0 + (threadIdx.x % kBpTile), r = ty0 + (threadIdx.x / kBpTile);
@@ -946,36 +966,72 @@ __device__ __forceinline__ void bp_tile_fan_async(const Geom &g, int tile, const
     const float lx = (float)(c - tx0), ly = (float)(r - ty0);
     const float is2 = (float)(g.inv_step * g.inv_step);
     const int pw = PLANES * W;                         // chunks per staged angle
-    // buffer k: sinogram windows at lds + k * AB * pw, rays after both windows
+    // LDS: sinogram windows 2 x AB * pw chunks, FP32 rays 2 x AB * W, raw rays AB * W x 32 B
     float4 *rays0 = reinterpret_cast<float4 *>(lds + 2 * AB * pw);
+    uint4 *raw = lds + 2 * AB * pw + 2 * AB * W;
+    // cos/sin of the block starting at a (na angles) into slot k, by the lanes of wave 0
+    auto copy_trig = [&](int a, int na, int k) {
+        if ((int)threadIdx.x < na)
+            lds_copy16_async(reinterpret_cast<const uint4 *>(g.trig + a) + threadIdx.x,
+                             reinterpret_cast<uint4 *>(&trig_s[k][0]));
+    };
+    // raw rays of the block's windows: bin p = al * W + j is chunks 2p and 2p + 1 of
+    // `raw`; chunk e = threadIdx + 256 i is lane e mod 64 of a contiguous wave row, so
+    // each wave copies whole rays (bins outside the detector are not copied)
+    auto copy_rays = [&](int a, int na, const int *wlo) {
+        for (int e = threadIdx.x; e < 2 * na * W; e += 256) {
+            const int p = e >> 1, al = p / W, d = wlo[al] + (p - al * W);
+            if ((unsigned)d < (unsigned)D)
+                lds_copy16_async(reinterpret_cast<const uint4 *>(g.rays + (size_t)(a + al) * D + d) + (e & 1),
+                                 raw + (e - (threadIdx.x & 63)));
+        }
+    };
+    // the raw rays this thread's wave copied, as tile-relative FP32 rays
+    auto finish_rays = [&](int na, const int *wlo, float4 *rays_s) {
+        for (int e = threadIdx.x; e < 2 * na * W; e += 256) {
+            if (e & 1) continue;
+            const int p = e >> 1, al = p / W, d = wlo[al] + (p - al * W);
+            float4 v = make_float4(-1e9f, -1e9f, 0.0f, 0.0f);
+            if ((unsigned)d < (unsigned)D) v = fan_tile_ray(g, reinterpret_cast<const double4 *>(raw)[p], tx0, ty0);
+            rays_s[p] = v;
+        }
+    };
 
     float acc[BC];
 #pragma unroll
     for (int i = 0; i < BC; ++i) acc[i] = 0.0f;
 
     const int nblk = (A + AB - 1) / AB;
-    if ((int)threadIdx.x < min(AB, A)) {
-        fan_tile_bounds<NB>(g, tx0, ty0, threadIdx.x, &wlo_s[0][threadIdx.x], &nb_s[0][threadIdx.x]);
-        trig_s[0][threadIdx.x] = g.trig[threadIdx.x];
-    }
+    copy_trig(0, min(AB, A), 0);
+    if (A > AB) copy_trig(AB, min(AB, A - AB), 1);
+    __builtin_amdgcn_s_waitcnt(0);
+    if ((int)threadIdx.x < min(AB, A))
+        fan_tile_bounds<NB>(g, tx0, ty0, trig_s[0][threadIdx.x], &wlo_s[0][threadIdx.x], &nb_s[0][threadIdx.x]);
     __syncthreads();
     src.issue(lds, 0, min(AB, A), W, wlo_s[0]);
+    copy_rays(0, min(AB, A), wlo_s[0]);
     for (int b = 0; b < nblk; ++b) {
-        const int a0 = b * AB, na = min(AB, A - a0), nn = min(AB, A - a0 - AB);
+        const int a0 = b * AB, na = min(AB, A - a0), nn = min(AB, A - a0 - AB), n2 = min(AB, A - a0 - 2 * AB);
         const int cur = b & 1, tb = b % 3, tn = (b + 1) % 3;
-        uint4 *sino_cur = lds + cur * AB * pw, *sino_next = lds + (cur ^ 1) * AB * pw;
+        const uint4 *sino_cur = lds + cur * AB * pw;
+        uint4 *sino_next = lds + (cur ^ 1) * AB * pw;
         float4 *rays_cur = rays0 + cur * AB * W;
-        if ((int)threadIdx.x < nn) {
-            fan_tile_bounds<NB>(g, tx0, ty0, a0 + AB + threadIdx.x, &wlo_s[tn][threadIdx.x], &nb_s[tn][threadIdx.x]);
-            trig_s[tn][threadIdx.x] = g.trig[a0 + AB + threadIdx.x];
-        }
-        fan_stage_rays(g, a0, na, W, wlo_s[tb], tx0, ty0, rays_cur);
-        __builtin_amdgcn_s_waitcnt(0);                 // this wave's copies of block b have landed
+        __builtin_amdgcn_s_waitcnt(0);                 // this wave's copies have landed: block
+                                                       // b's windows and raw rays, b + 1's cos/sin
+        finish_rays(na, wlo_s[tb], rays_cur);
+        if ((int)threadIdx.x < nn)
+            fan_tile_bounds<NB>(g, tx0, ty0, trig_s[tn][threadIdx.x], &wlo_s[tn][threadIdx.x],
+                                &nb_s[tn][threadIdx.x]);
         __syncthreads();                               // ... and everyone's; rays and bounds written
         int nb_block = 0;
         for (int al = 0; al < na; ++al) nb_block = max(nb_block, nb_s[tb][al]);
-        // the next block's copies run while this block is applied
-        if (nn > 0) src.issue(sino_next, a0 + AB, nn, W, wlo_s[tn]);
+        // the next block's windows and raw rays, and the cos/sin two blocks ahead, are
+        // copied while this block is applied
+        if (nn > 0) {
+            src.issue(sino_next, a0 + AB, nn, W, wlo_s[tn]);
+            copy_rays(a0 + AB, nn, wlo_s[tn]);
+        }
+        if (n2 > 0) copy_trig(a0 + 2 * AB, n2, (b + 2) % 3);
 
         constexpr bool kTwoLevel = BC <= 32;
         float part_buf[kTwoLevel ? BC : 1];
@@ -984,11 +1040,11 @@ __device__ __forceinline__ void bp_tile_fan_async(const Geom &g, int tile, const
 #pragma unroll
             for (int i = 0; i < BC; ++i) part[i] = 0.0f;
         }
-        fan_angle_block<T, BC, 4, NK, PAIRS>(g, trig_s[tb], na, W, wlo_s[tb], rays_cur, sino_cur, W, pw, qx, qy, lx,
-                                             ly, is2, part);
+        fan_angle_block<T, BC, 4, NK, PAIRS>(g, trig_s[tb], na, W, wlo_s[tb], rays_cur, sino_cur, W, pw, qx, qy,
+                                             lx, ly, is2, part);
         if (NB > 4 && nb_block > 4)
-            fan_angle_block<T, BC, 2, NK, PAIRS>(g, trig_s[tb], na, W, wlo_s[tb], rays_cur, sino_cur, W, pw, qx, qy,
-                                                 lx, ly, is2, part, 4);
+            fan_angle_block<T, BC, 2, NK, PAIRS>(g, trig_s[tb], na, W, wlo_s[tb], rays_cur, sino_cur, W, pw, qx,
+                                                 qy, lx, ly, is2, part, 4);
         if (kTwoLevel) {
 #pragma unroll
             for (int i = 0; i < BC; ++i) acc[i] += part[i];

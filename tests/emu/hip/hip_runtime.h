@@ -67,8 +67,12 @@ inline float emu_fractf(float x) { return x - std::floor(x); }
 #define __builtin_amdgcn_fractf(x) emu_fractf(x)
 #define __builtin_amdgcn_fmed3f(a, b, c) emu_med3(a, b, c)
 #define __builtin_amdgcn_readfirstlane(x) (x)
-// memory-counter waits: every emulated access has completed already
-#define __builtin_amdgcn_s_waitcnt(x) ((void)0)
+// memory-counter waits: every emulated access has completed already, but after a wait
+// the lanes of a wave read what the other lanes of that wave copied asynchronously (the
+// device issues one copy instruction for all 64 lanes), so the wait synchronises the
+// lanes: here all the block's work-items, a stronger order than the device's (every use
+// is reached by the whole block)
+#define __builtin_amdgcn_s_waitcnt(x) __syncthreads()
 // v_rcp_f32 (1 ulp on the device; the correctly rounded quotient here)
 inline float emu_rcpf(float x) { return 1.0f / x; }
 #define __builtin_amdgcn_rcpf(x) emu_rcpf(x)
