@@ -9,7 +9,9 @@
 // angles per LDS block (with the interleaved copies, whose next block is copied
 // asynchronously into a second buffer, {4, 2}; from the caller's sinograms {8, 4}
 // parallel, 4 fan) x sinogram staging {interleaved copy, caller's sinograms, and for 16-bit storage
-// the tap-pair copy with dot2 arithmetic}, and the direct kernel.  The direct kernels win on tiny problems, where the
+// the tap-pair copy with dot2 arithmetic}, and the direct kernel.  Every candidate is
+// timed once (a warm-up launch, then three), the three fastest three more times
+// round-robin, and the fastest timing decides.  The direct kernels win on tiny problems, where the
 // tiled kernels' sequential slabs and angle blocks are latency-bound.  Results live in the plan
 // and, when RADON_TUNE_CACHE names a file, in that file (one line per entry:
 // "<key> <fwd variant> <fwd images> <fwd stage> <bp variant> <bp images> <bp angles>
@@ -17,6 +19,7 @@
 // so later processes skip the timing.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -93,6 +96,29 @@ static float time_launches(F launch, hipStream_t s, int reps = 3) {
     return ok ? ms / reps : -1.0f;
 }
 
+// The candidates within a few percent of each other after one timing each can swap
+// places between runs (launch-to-launch jitter, clocks), so the three fastest are timed
+// again, round-robin, three more times each, and the fastest of every candidate's
+// timings wins.  Returns the index of the winner in `ms` (or -1 if none ran).
+template <class F>
+static int pick_fastest(std::vector<float> &ms, F time_candidate) {
+    std::vector<int> order;
+    for (int i = 0; i < (int)ms.size(); ++i)
+        if (ms[i] > 0.0f) order.push_back(i);
+    if (order.empty()) return -1;
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return ms[a] < ms[b]; });
+    if (order.size() > 3) order.resize(3);
+    for (int round = 0; round < 3; ++round)
+        for (int i : order) {
+            const float t = time_candidate(i);
+            if (t > 0.0f && t < ms[i]) ms[i] = t;
+        }
+    int best = order[0];
+    for (int i : order)
+        if (ms[i] < ms[best]) best = i;
+    return best;
+}
+
 int autotune(Plan &p, int dtype, int batch, void *ws, size_t ws_bytes, TunedShapes &out) {
     const int bclass = batch_class(batch);
     const std::string key = tune_key(p, dtype, bclass);
@@ -126,12 +152,11 @@ int autotune(Plan &p, int dtype, int batch, void *ws, size_t ws_bytes, TunedShap
 
     if (p.fwd_shape.variant == VARIANT_TILED) {
         std::vector<int> imgs = dtype == F32 ? std::vector<int>{8, 4, 16} : std::vector<int>{8, 16};
-        float best = time_launches([&] {
-            LaunchShape sh = p.fwd_shape;
-            sh.variant = VARIANT_DIRECT;
-            return launch_forward(p.geom, p.fwd_work[0], dtype, sh, x, y, batch, 1.0f, ws, ws_bytes, s);
-        }, s);
-        out.fwd_variant = VARIANT_DIRECT;
+        // candidate 0: the direct kernel; then tilings x images x staging
+        std::vector<LaunchShape> cands;
+        LaunchShape direct = p.fwd_shape;
+        direct.variant = VARIANT_DIRECT;
+        cands.push_back(direct);
         const std::vector<int> stages = dtype == F32 ? std::vector<int>{1, 0} : std::vector<int>{2, 1, 0};
         for (int t = 0; t < kFwdTilings; ++t) {
             if (p.fwd_work[t].n_items == 0) continue;
@@ -142,27 +167,32 @@ int autotune(Plan &p, int dtype, int batch, void *ws, size_t ws_bytes, TunedShap
                     sh.images = im;
                     sh.stage = st;
                     sh.tiling = t;
-                    const float ms = time_launches([&] {
-                        return launch_forward(p.geom, p.fwd_work[t], dtype, sh, x, y, batch, 1.0f, ws,
-                                              ws_bytes, s);
-                    }, s);
-                    if (ms > 0.0f && (best < 0.0f || ms < best)) {
-                        best = ms;
-                        out.fwd_variant = VARIANT_TILED;
-                        out.fwd_images = im;
-                        out.fwd_stage = st;
-                        out.fwd_tiling = t;
-                    }
+                    cands.push_back(sh);
                 }
+        }
+        auto time_fwd = [&](int i) {
+            const LaunchShape &sh = cands[i];
+            const FwdWork &w = p.fwd_work[sh.variant == VARIANT_DIRECT ? 0 : sh.tiling];
+            return time_launches([&] {
+                return launch_forward(p.geom, w, dtype, sh, x, y, batch, 1.0f, ws, ws_bytes, s);
+            }, s);
+        };
+        std::vector<float> ms(cands.size());
+        for (int i = 0; i < (int)cands.size(); ++i) ms[i] = time_fwd(i);
+        const int b = pick_fastest(ms, time_fwd);
+        out.fwd_variant = VARIANT_DIRECT;
+        if (b > 0) {
+            out.fwd_variant = VARIANT_TILED;
+            out.fwd_images = cands[b].images;
+            out.fwd_stage = cands[b].stage;
+            out.fwd_tiling = cands[b].tiling;
         }
     }
     if (p.bp_shape.variant == VARIANT_TILED) {
-        float best = time_launches([&] {
-            LaunchShape sh = p.bp_shape;
-            sh.variant = VARIANT_DIRECT;
-            return launch_backproject(p.geom, p.bp_work, dtype, sh, y, x, batch, 1.0f, ws, ws_bytes, s);
-        }, s);
-        out.bp_variant = VARIANT_DIRECT;
+        std::vector<LaunchShape> cands;
+        LaunchShape direct = p.bp_shape;
+        direct.variant = VARIANT_DIRECT;
+        cands.push_back(direct);
         // angles per LDS block: the double-buffered kernels on the interleaved copies
         // (stages 1, 2) take {4, 2}, the caller's sinograms (stage 0) the parallel
         // beam's {8, 4} and the fan beam's 4
@@ -180,18 +210,23 @@ int autotune(Plan &p, int dtype, int batch, void *ws, size_t ws_bytes, TunedShap
                     sh.images = im;
                     sh.angles = ab;
                     sh.stage = st;
-                    const float ms = time_launches([&] {
-                        return launch_backproject(p.geom, p.bp_work, dtype, sh, y, x, batch, 1.0f, ws,
-                                                  ws_bytes, s);
-                    }, s);
-                    if (ms > 0.0f && (best < 0.0f || ms < best)) {
-                        best = ms;
-                        out.bp_variant = VARIANT_TILED;
-                        out.bp_images = im;
-                        out.bp_angles = ab;
-                        out.bp_stage = st;
-                    }
+                    cands.push_back(sh);
                 }
+        auto time_bp = [&](int i) {
+            return time_launches([&] {
+                return launch_backproject(p.geom, p.bp_work, dtype, cands[i], y, x, batch, 1.0f, ws, ws_bytes, s);
+            }, s);
+        };
+        std::vector<float> ms(cands.size());
+        for (int i = 0; i < (int)cands.size(); ++i) ms[i] = time_bp(i);
+        const int b = pick_fastest(ms, time_bp);
+        out.bp_variant = VARIANT_DIRECT;
+        if (b > 0) {
+            out.bp_variant = VARIANT_TILED;
+            out.bp_images = cands[b].images;
+            out.bp_angles = cands[b].angles;
+            out.bp_stage = cands[b].stage;
+        }
     }
     (void)hipDeviceSynchronize();
     (void)hipFree(x);
