@@ -116,8 +116,10 @@ RADON_FWD_TILING_DECL(3)
 #undef RADON_FWD_TILING_DECL
 // ------------------------------------------------------------------ tiled backprojection
 constexpr int kBpTile = 16;        // pixels per tile side (one lane per pixel)
-constexpr int kBpAngles = 8;       // angles per LDS block (parallel beam)
-constexpr int kBpAnglesFan = 4;    // angles per LDS block (fan beam; rays are staged too)
+// angles per LDS block: from the caller's sinograms (parallel 8 or 4, fan 4); the
+// double-buffered kernels on the interleaved copies take 4 or 2 (two windows in LDS)
+constexpr int kBpAngles = 8;       // parallel beam, caller's sinograms
+constexpr int kBpAnglesFan = 4;    // fan beam (rays are staged too)
 // Parallel beam: LDS pitch (in chunks) of one staged angle's bin window.  The planner's
 // window is 4 * ceil((floor(15 h / spacing) + 6) / 4) with h = |cos| + |sin| <= 1.5
 // spacing (3 candidate bins must cover a footprint), so it never exceeds 28; a fixed
