@@ -523,8 +523,8 @@ static int upload(V **dst, const std::vector<V> &src) {
 }
 
 // Images of all jobs that share a plan are pooled and cut into image groups, so
-// single-image jobs of one geometry share lanes: forward, one 16-byte chunk of images
-// per lane (4 FP32 / 8 16-bit);
+// single-image jobs of one geometry share lanes: forward, one 16-byte chunk of four
+// images per lane (FP32 values or 16-bit tap pairs);
 // backprojection, the narrowest of 8, 16 and 32 images that holds the images left (32
 // while more remain).  Units are sorted longest first.
 static int build_batch_table(const std::vector<Plan *> &plans, const radon_job_t *jobs, int n,
@@ -574,7 +574,7 @@ static int build_batch_table(const std::vector<Plan *> &plans, const radon_job_t
         bj.push_back(j);
         for (size_t k = 0; k < v.size();) {
             const size_t left = v.size() - k;
-            const int cap = direction == 0 ? ch
+            const int cap = direction == 0 ? 4
                                            : (left > (size_t)kBatchBpMid    ? kBatchBpWide
                                               : left > (size_t)kBatchBpNarrow ? kBatchBpMid
                                                                               : kBatchBpNarrow);

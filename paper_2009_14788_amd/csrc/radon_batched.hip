@@ -2,14 +2,17 @@
 // extended to jobs of different image sizes and angle sets).
 //
 // The host groups the images of all jobs that share a geometry into image groups
-// (for the forward one 16-byte chunk per lane, 4 FP32 or 8 16-bit images; 8, 16 or 32
-// for the backprojection, the narrowest that holds the images left)
+// (for the forward one 16-byte chunk per lane: 4 images, FP32 values or 16-bit tap
+// pairs; 8, 16 or 32 for the backprojection, the narrowest that holds the images left)
 // and flattens them into
 // work units -- forward: (geometry, plan item, image group); backprojection:
 // (geometry, pixel tile, image group) -- sorted longest first.
 // A grid sized to the resident capacity of the GPU pulls units from a device
 // counter (the only atomic) until the list is exhausted; each unit runs the same
-// per-item device function as the per-call kernels, so results are identical.
+// per-item device function as the per-call kernels, so results are identical to a
+// per-call run of the same arithmetic (bitwise, except that the 16-bit forward takes
+// tap pairs along the image's x here, while the per-call kernels take single taps or
+// pairs along the item's transverse axis).
 #include "radon_batched.hpp"
 #include "radon_tiles.hpp"
 
@@ -57,14 +60,19 @@ __global__ __launch_bounds__(kFwdThreads, 6) void fwd_batched(const BatchJob *__
         const WorkUnit u = work[w];
         const BatchJob &j = jobs[u.job];
         const FwdItem it = j.items[u.unit];
-        // one 16-byte chunk per lane (4 FP32 or 8 16-bit images): one LDS plane per
-        // slab keeps several blocks resident per CU even for the widest job's tile (two
-        // FP32 chunks per lane for geometries with more than four images measured 7%
-        // slower over the 200-job batch)
-        constexpr int BC = Chunk<T>::kImages;
+        // one 16-byte chunk per lane, four images (FP32 values, or 16-bit tap pairs): one
+        // LDS plane per slab keeps several blocks resident per CU even for the widest
+        // job's tile (two FP32 chunks per lane for geometries with more than four images
+        // measured 7% slower over the 200-job batch)
+        constexpr int BC = 4;
         const ImageSet<T, BC> imgs = group_images<T, BC>(groups[u.group]);
-        const PointerSource<T, BC> src{imgs.in, j.g.n};
-        fwd_item<T, BC>(j.g, it, j.ranges, imgs, src, j.tile_t, lds);
+        if constexpr (sizeof(T) == 2) {
+            const PairPointerSource<T> src{imgs.in, j.g.n};
+            fwd_item<T, BC>(j.g, it, j.ranges, imgs, src, j.tile_t, lds);
+        } else {
+            const PointerSource<T, BC> src{imgs.in, j.g.n};
+            fwd_item<T, BC>(j.g, it, j.ranges, imgs, src, j.tile_t, lds);
+        }
     }
 }
 

@@ -91,6 +91,47 @@ struct PointerSource {
     }
 };
 
+// From the callers' 16-bit images as tap pairs (Pair<T>, four images per chunk), in the
+// image frame: chunk (row, col) holds, in word e, pixels col and col + 1 of that row
+// of image e (the first in the low half), so that one 16-byte read per row serves a
+// sample's two horizontal taps of four images.  The walk is PointerSource's.
+template <typename T, class C = FwdCfg0>
+struct PairPointerSource {
+    using Cfg = C;
+    static constexpr bool kMarchFrame = false;
+    static constexpr bool kPairs = true;
+    const T *const *img;   // four image base pointers
+    int n;
+    __device__ __forceinline__ void stage(uint4 *lds, int /*plane_chunks*/, int pitch, int ox0, int oy0,
+                                          int rows, int cols, int /*axis*/) const {
+        const int total = rows * cols;
+        const int step_i = C::kThreads / cols, step_j = C::kThreads - step_i * cols;
+        int i = threadIdx.x / cols, jj = threadIdx.x - i * cols;
+        for (int idx = threadIdx.x; idx < total; idx += C::kThreads) {
+            const int gx = ox0 + jj, gy = oy0 + i;
+            const bool row_in = (unsigned)gy < (unsigned)n;
+            const bool in0 = row_in && (unsigned)gx < (unsigned)n;
+            const bool in1 = row_in && (unsigned)(gx + 1) < (unsigned)n;
+            const unsigned off0 = in0 ? (unsigned)(gy * n + gx) : 0u;
+            const unsigned off1 = in1 ? (unsigned)(gy * n + gx + 1) : 0u;
+            uint32_t w[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t lo = Pair<T>::bits(img[e][off0]);     // always valid addresses
+                const uint32_t hi = Pair<T>::bits(img[e][off1]);
+                w[e] = (in0 ? lo : 0u) | ((in1 ? hi : 0u) << 16);
+            }
+            lds[i * pitch + jj] = make_uint4(w[0], w[1], w[2], w[3]);
+            jj += step_j;
+            i += step_i;
+            if (jj >= cols) {
+                jj -= cols;
+                ++i;
+            }
+        }
+    }
+};
+
 // From the interleaved copies of the batch, in the march frame: chunk (group, y+2,
 // x+2) of the row-major copy [groups][N+4][N+4] holds pixel (x, y) of the group's
 // images, and chunk (group, x+2, y+2) of the transposed copy holds the same pixel,

@@ -40,6 +40,7 @@ struct Geo {
     size_t nx, ny;
     std::vector<unsigned char> x, y;           // inputs (storage type)
     void *fx = nullptr, *bx = nullptr;         // per-call outputs
+    std::vector<double> oracle_fx;             // FP64 oracle forward on the stored inputs
 };
 
 size_t esize(int dt) { return dt == RADON_F32 ? 4 : 2; }
@@ -433,6 +434,7 @@ int main(int argc, char **argv) {
         oracle_backproject(g.beam, g.n, g.A, g.angles.data(), g.D, g.sp, g.S, g.E, g.step,
                            yd.data(), g.batch, 1.0, ob.data());
         const double ef = rel_l2(g.fx, g.dt, of.data(), g.ny), eb = rel_l2(g.bx, g.dt, ob.data(), g.nx);
+        g.oracle_fx = of;
         const double df = rel_l2(fd, g.dt, of.data(), g.ny), db = rel_l2(bd, g.dt, ob.data(), g.nx);
         std::printf("geometry %zu fwd_variant %d bp_variant %d forward %.3e backprojection %.3e "
                     "direct_forward %.3e direct_backprojection %.3e\n",
@@ -469,11 +471,22 @@ int main(int argc, char **argv) {
         std::fprintf(stderr, "[emu] batched forward and backprojection of %zu jobs\n", geos.size());
         int rc = radon_forward_batched(jf.data(), (int)jf.size(), dt, nullptr);
         if (!rc) rc = radon_backproject_batched(jb.data(), (int)jb.size(), dt, nullptr);
+        // FP32: bitwise equal to the per-call results.  16-bit: the batched forward takes
+        // tap pairs along x (weights rounded to the storage type), so it is held to the
+        // 16-bit bar against the oracle instead; the backprojection is bitwise.
         int same = 0;
         for (size_t k = 0; !rc && k < geos.size(); ++k) {
-            const size_t es = esize(geos[k].dt);
-            same += std::memcmp(of[k], geos[k].fx, geos[k].ny * es) == 0 &&
-                    std::memcmp(ob[k], geos[k].bx, geos[k].nx * es) == 0;
+            const Geo &g = geos[k];
+            const size_t es = esize(g.dt);
+            bool fwd_ok;
+            if (g.dt == RADON_F32) {
+                fwd_ok = std::memcmp(of[k], g.fx, g.ny * es) == 0;
+            } else {
+                const double e = g.oracle_fx.size() == g.ny ? rel_l2(of[k], g.dt, g.oracle_fx.data(), g.ny) : 1.0;
+                std::printf("batched 16-bit forward %zu: rel L2 to the oracle %.3e\n", k, e);
+                fwd_ok = e <= 5e-3;
+            }
+            same += fwd_ok && std::memcmp(ob[k], g.bx, g.nx * es) == 0;
         }
         std::printf("batched status %d identical %d of %zu\n", rc, same, geos.size());
         if (rc || same != (int)geos.size()) ++fails;

@@ -1,5 +1,5 @@
-"""Uneven batches in one persistent launch: identical to per-job calls, matching the
-oracle, and replayable from a captured graph."""
+"""Uneven batches in one persistent launch: identical to per-job calls (the 16-bit forward
+within 1e-3 of them), matching the oracle, and replayable from a captured graph."""
 import math
 
 import numpy as np
@@ -35,7 +35,9 @@ def _images(jobs, dt="f32", batch=1):
 @pytest.mark.parametrize("dt", ["f32", "f16"])
 def test_batched_equals_per_job(dt):
     """24 jobs from the uneven distribution (N in {128..512}, 30..360 angles over pi or
-    2pi/3): the batched forward and backprojection equal the per-job calls bitwise."""
+    2pi/3): the batched forward and backprojection equal the per-job calls bitwise, except
+    the 16-bit forward, which takes tap pairs along x (its weights rounded to FP16) and is
+    held within 1e-3 of the per-job forward (both are within ~3e-4 of the oracle)."""
     from paper_2009_14788_amd.batched import BatchedRadon
     jobs = _jobs(24)
     ops = _ops(jobs)
@@ -51,7 +53,12 @@ def test_batched_equals_per_job(dt):
     bs_ref = [op.backprojection_raw(g) for op, g in zip(ops, gs)]
     torch.cuda.synchronize()
     for i in range(len(jobs)):
-        assert torch.equal(ys[i], ys_ref[i]), f"forward job {i}"
+        if dt == "f32":
+            assert torch.equal(ys[i], ys_ref[i]), f"forward job {i}"
+        else:
+            a, b = ys[i].double(), ys_ref[i].double()
+            d = float((a - b).norm() / b.norm())
+            assert d <= 1e-3, (i, d)
         assert torch.equal(bs[i], bs_ref[i]), f"backprojection job {i}"
 
 

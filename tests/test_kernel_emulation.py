@@ -163,6 +163,25 @@ def test_emulated_uneven_batch_groups(emu_bin, tmp_path):
     assert "identical 5 of 5" in out, out
 
 
+@pytest.mark.parametrize("dt", [1, 2])
+def test_emulated_uneven_batch_16bit(emu_bin, tmp_path, dt):
+    """16-bit uneven batch: the forward runs on tap pairs along x staged from the callers'
+    images (four images per lane, including a ragged group of one and a fan job), within
+    the 16-bit bar of the oracle; the backprojection is bitwise equal to per-call."""
+    # the emulator prints each 16-bit batched forward's error against the oracle and
+    # counts a job as matching only within 5e-3
+    U = inputs.uniform_angles
+    lines = [_line("par", 40, U(20), 57, batch=1, dt=dt),
+             _line("par", 24, U(30, 2 * math.pi / 3), 34, batch=2, dt=dt),
+             _line("par", 40, U(20), 57, batch=4, dt=dt),
+             _line("fan", 32, U(16, 2 * math.pi), 46, 1.5, 200.0, 100.0, batch=1, dt=dt),
+             _line("par", 37, U(9), 53, batch=3, dt=dt)]
+    rows, out = _run(emu_bin, tmp_path, lines, mode="batched")
+    print("\n".join(l for l in out.splitlines() if l.startswith("batched")))
+    _check_bars(rows, lines)
+    assert "identical 5 of 5" in out, out
+
+
 def test_emulated_filter_matches_oracle(emu_bin, tmp_path):
     """The FBP filter kernel (Stockham radix-8/radix-4 transforms in LDS, two rows per
     block) against the FP64 oracle filter for all five filters: odd row counts, padded
