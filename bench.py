@@ -8,7 +8,7 @@ projections/s (images x angles per second through forward+backprojection), rays/
 algorithmic HBM GB/s, the roofline of the dominant kernel (timed with HIP events on
 the stream the kernels run on), and the FP64 CPU oracle timed on a bounded sample.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick] [--no-solvers]
 """
 import argparse
 import json
@@ -205,6 +205,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quick", action="store_true",
                     help="only the headline workload (skip the other workloads and forms)")
+    ap.add_argument("--no-solvers", action="store_true",
+                    help="leave out the Landweber / CGNE workloads (2 x 500 iterations of "
+                         "several thousand dispatches, which dominate a counter-collection run)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the benchmark, run a plain elementwise copy of 1 GiB three times "
                          "(reference dispatch for scaling HBM traffic counters)")
@@ -351,7 +354,7 @@ def main():
     }
     if not args.quick:
         ref = {"sel": sel, "y": yr, "ys": ys_np, "xb": xr}
-        out["workloads"] = variants(op, x, x_np, B, A, D, ref)
+        out["workloads"] = variants(op, x, x_np, B, A, D, ref, solvers=not args.no_solvers)
     if args.copy_calibration:
         # a plain elementwise kernel that reads 1 GiB once and writes 1 GiB once
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
@@ -434,14 +437,15 @@ def _frac(samples, ms):
     return round(16.0 * samples / (ms * 1e-3) / (PEAK_FP32_TFLOPS * 1e12), 4)
 
 
-def variants(op, x, x_np, B, A, D, ref):
+def variants(op, x, x_np, B, A, D, ref, solvers=True):
     """The other workloads and forms, each timed on this GPU with its error stated:
     16-bit storage and the differentiable step on the headline batch; the single 64^2
     image (latency, eager and graph-replayed); the 16 x 256^2 batch; 200 uneven jobs
     in one persistent launch (eager, graph, and one call per job); the 64 x 512^2
     fan beam with 16-bit storage and a 10-step unrolled gradient descent
     differentiated end to end; the FBP filter on the headline sinograms, FBP in the
-    paper's 512^2 configuration, and Landweber and CGNE (500 iterations) there."""
+    paper's 512^2 configuration, and Landweber and CGNE (500 iterations) there (unless
+    solvers is False)."""
     import math
     import torch
     import oracle
@@ -531,8 +535,9 @@ def variants(op, x, x_np, B, A, D, ref):
     alpha = lw.estimate_alpha(512, "cuda") * 0.95
     zero = torch.zeros_like(xf)
     sol = {}
-    for name, run in (("landweber", lambda it: lw.run(zero, yf, alpha, iterations=it)),
-                      ("cgne", lambda it: cgne(opf, zero, yf, max_iter=it))):
+    runs = (("landweber", lambda it: lw.run(zero, yf, alpha, iterations=it)),
+            ("cgne", lambda it: cgne(opf, zero, yf, max_iter=it))) if solvers else ()
+    for name, run in runs:
         ms = _timed(lambda: run(500), reps=2)
         rec = run(500)[0].double().cpu().numpy()
         sol[name] = {"ms_per_iteration": round(ms / 500, 5), "ms_500_iterations": round(ms, 3),
@@ -540,10 +545,11 @@ def variants(op, x, x_np, B, A, D, ref):
                      "mse_vs_phantom_inside": float(np.mean((rec[inside] - xf_np[0][inside]) ** 2))}
         print(f"[bench] {name} 512^2 paper configuration: {ms / 500:.4f} ms/iteration",
               file=sys.stderr, flush=True)
-    res["solvers_paper_512"] = dict(sol, alpha=alpha, note=(
-        "500 iterations from zero on one 512^2 phantom (512 angles, 725 bins), each loop queued "
-        "natively with device-side FP64 scalars; random ellipses stand in for Shepp-Logan (the "
-        "paper's MSEs 1.39e-4 Landweber, 4.42e-5 CGNE are on that)"))
+    if solvers:
+        res["solvers_paper_512"] = dict(sol, alpha=alpha, note=(
+            "500 iterations from zero on one 512^2 phantom (512 angles, 725 bins), each loop "
+            "queued natively with device-side FP64 scalars; random ellipses stand in for "
+            "Shepp-Logan (the paper's MSEs 1.39e-4 Landweber, 4.42e-5 CGNE are on that)"))
 
     # -- single 64x64 image (latency)
     w0 = inputs.WORKLOADS["single64"]
