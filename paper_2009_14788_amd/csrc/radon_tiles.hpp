@@ -94,7 +94,12 @@ struct PointerSource {
 // From the callers' 16-bit images as tap pairs (Pair<T>, four images per chunk), in the
 // image frame: chunk (row, col) holds, in word e, pixels col and col + 1 of that row
 // of image e (the first in the low half), so that one 16-byte read per row serves a
-// sample's two horizontal taps of four images.  The walk is PointerSource's.
+// sample's two horizontal taps of four images.  The walk is PointerSource's.  For an
+// even image side and 4-byte aligned images (the usual case) a thread reads the 32-bit
+// words w(g) = pixels (2g, 2g + 1) and w(g + 1) of each image and forms the chunks at
+// columns 2g (w(g) itself) and 2g + 1 (high half of w(g), low half of w(g + 1)): one
+// 32-bit load per chunk and image instead of two 16-bit ones; a word is then either
+// wholly inside the row or wholly outside it.
 template <typename T, class C = FwdCfg0>
 struct PairPointerSource {
     using Cfg = C;
@@ -104,6 +109,55 @@ struct PairPointerSource {
     int n;
     __device__ __forceinline__ void stage(uint4 *lds, int /*plane_chunks*/, int pitch, int ox0, int oy0,
                                           int rows, int cols, int /*axis*/) const {
+        bool words = (n & 1) == 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) words = words && ((uintptr_t)img[e] & 3u) == 0;
+        if (words)
+            stage_words(lds, pitch, ox0, oy0, rows, cols);
+        else
+            stage_pixels(lds, pitch, ox0, oy0, rows, cols);
+    }
+
+    __device__ __forceinline__ void stage_words(uint4 *lds, int pitch, int ox0, int oy0, int rows,
+                                                int cols) const {
+        const int hn = n >> 1;                          // words per image row
+        const int g0 = ox0 >> 1;                        // floor: ox0 >= -2
+        const int wcols = ((ox0 + cols - 1) >> 1) - g0 + 1;
+        const int total = rows * wcols;
+        const int step_i = C::kThreads / wcols, step_j = C::kThreads - step_i * wcols;
+        int i = threadIdx.x / wcols, jj = threadIdx.x - i * wcols;
+        for (int idx = threadIdx.x; idx < total; idx += C::kThreads) {
+            const int g = g0 + jj, gy = oy0 + i;
+            const bool row_in = (unsigned)gy < (unsigned)n;
+            const bool in0 = row_in && (unsigned)g < (unsigned)hn;
+            const bool in1 = row_in && (unsigned)(g + 1) < (unsigned)hn;
+            const unsigned off0 = in0 ? (unsigned)(gy * hn + g) : 0u;
+            const unsigned off1 = in1 ? (unsigned)(gy * hn + g + 1) : 0u;
+            uint32_t a[4], b[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t *row = reinterpret_cast<const uint32_t *>(img[e]);
+                const uint32_t wa = row[off0], wb = row[off1];  // always valid addresses
+                a[e] = in0 ? wa : 0u;
+                b[e] = in1 ? wb : 0u;
+            }
+            const int c0 = 2 * g - ox0;                     // chunk columns c0 and c0 + 1
+            if (c0 >= 0 && c0 < cols) lds[i * pitch + c0] = make_uint4(a[0], a[1], a[2], a[3]);
+            if (c0 + 1 >= 0 && c0 + 1 < cols)
+                lds[i * pitch + c0 + 1] =
+                    make_uint4((a[0] >> 16) | (b[0] << 16), (a[1] >> 16) | (b[1] << 16),
+                               (a[2] >> 16) | (b[2] << 16), (a[3] >> 16) | (b[3] << 16));
+            jj += step_j;
+            i += step_i;
+            if (jj >= wcols) {
+                jj -= wcols;
+                ++i;
+            }
+        }
+    }
+
+    __device__ __forceinline__ void stage_pixels(uint4 *lds, int pitch, int ox0, int oy0, int rows,
+                                                 int cols) const {
         const int total = rows * cols;
         const int step_i = C::kThreads / cols, step_j = C::kThreads - step_i * cols;
         int i = threadIdx.x / cols, jj = threadIdx.x - i * cols;
