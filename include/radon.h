@@ -119,10 +119,13 @@ typedef struct radon_job {
 
 /* Uneven batch (Sec. 4.1 batch processing, for jobs of different image sizes and
  * angle sets): all jobs in ONE persistent kernel launch that pulls work items from a
- * device queue, longest first.  Same results as calling radon_forward /
- * radon_backproject per job.  The job table is built and uploaded on the first call
- * for a given job list (by content); later calls with the same list only launch, so
- * the call can be captured into a hipGraph once that first call has run. */
+ * device queue, longest first.  Results equal those of radon_forward /
+ * radon_backproject per job bitwise, except the 16-bit forward: it takes horizontal tap
+ * pairs with the bilinear weights rounded to the storage type (one dot2 per row and
+ * image), so it differs from the per-job forward by that rounding, within the 16-bit
+ * error of either against exact arithmetic.  The job table is built and uploaded on
+ * the first call for a given job list (by content); later calls with the same list only
+ * launch, so the call can be captured into a hipGraph once that first call has run. */
 int radon_forward_batched(const radon_job_t *jobs, int32_t n_jobs, int32_t dtype, void *stream);
 int radon_backproject_batched(const radon_job_t *jobs, int32_t n_jobs, int32_t dtype,
                               void *stream);
