@@ -89,6 +89,39 @@ def test_batched_matches_oracle():
     assert worst_f <= TOL_F32 and worst_b <= TOL_F32
 
 
+@pytest.mark.parametrize("dt", ["f16", "bf16"])
+def test_batched_16bit_odd_and_even_sides(dt):
+    """The 16-bit batched forward on tap pairs: odd image sides (pairs staged from 16-bit
+    loads) and even ones (pairs from 32-bit words), groups of 1 to 4 images per lane,
+    parallel and fan beam, every element against the FP64 oracle on the 16-bit-rounded
+    images; the backprojection of the same jobs within the same bar."""
+    from paper_2009_14788_amd.batched import BatchedRadon
+    U = inputs.uniform_angles
+    cases = [Case("parallel", 37, U(23), 53), Case("parallel", 64, U(40), 91),
+             Case("parallel", 37, U(23), 53),
+             Case("fanbeam", 46, U(30, 2 * math.pi), 70, 1.5, 200.0, 100.0)]
+    batches = (3, 5, 1, 2)
+    ops = [c.library() for c in cases]
+    xs = [torch.from_numpy(inputs.randn((b, c.n, c.n), 90 + k)).cuda().to(TDT[dt])
+          for k, (c, b) in enumerate(zip(cases, batches))]
+    gs = [torch.from_numpy(inputs.randn((b,) + op.sinogram_shape, 95 + k)).cuda().to(TDT[dt])
+          for k, (op, b) in enumerate(zip(ops, batches))]
+    print(f"[gpu-step] batched 16-bit forward and backprojection, odd and even sides, {dt}", flush=True)
+    br = BatchedRadon(ops)
+    ys = br.forward(xs)
+    bs = br.backprojection(gs)
+    torch.cuda.synchronize()
+    worst_f = worst_b = 0.0
+    for k, c in enumerate(cases):
+        og = c.oracle()
+        yr = oracle.forward(og, xs[k].double().cpu().numpy())
+        br_ = oracle.backproject(og, gs[k].double().cpu().numpy())
+        worst_f = max(worst_f, rel_l2(ys[k].double().cpu().numpy(), yr))
+        worst_b = max(worst_b, rel_l2(bs[k].double().cpu().numpy(), br_))
+    report(f"batched_16bit_sides_{dt}", fwd_worst_rel_l2=worst_f, bp_worst_rel_l2=worst_b)
+    assert worst_f <= TOL_16 and worst_b <= TOL_16, (worst_f, worst_b)
+
+
 def test_batched_mixed_beams_and_batches():
     """Parallel and fan jobs with several images each in one launch equal per-job calls."""
     from paper_2009_14788_amd.batched import BatchedRadon
